@@ -1,0 +1,364 @@
+/*
+ * mc3_oracle.c -- plain, slow FP64 CPU oracle for many-configuration Markov-chain
+ * Monte Carlo (MCMCMC) on the Sherrington-Kirkpatrick spin glass.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is checked
+ * against.  Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no code, header, table or constant generator with the HIP
+ * library; both were written separately from the same written definitions.
+ *
+ * What it follows (paper: "Many-Configuration Markov-Chain Monte Carlo"):
+ *  - SK energy, Sec. "The Sherrington-Kirkpatrick model": a pair sum over j<k of
+ *    couplings times spin products.  Convention used here (reading C1): the sign is
+ *    folded into the coupling, E(s) = -scale * sum_{i<j} J_ij s_i s_j.
+ *  - Markov chain of undirected graphs, App. "Markov chain of graphs of
+ *    configurations": the next graph is generated from one node of the current
+ *    graph, chosen with P_node(c|T) = P_eq(c) P_gen(T|c) / P_eq(T), normalised over
+ *    the nodes of T (Eq. eq_det_balance_graph_solution with the normalisation
+ *    Eq. eq_normalization_p_c_T).
+ *  - Graph generation, App. "General graph populating process": a tree shape is
+ *    fixed, the current state is placed at a root drawn uniformly, and every edge is
+ *    populated with a two-body generation probability.  With a uniform root and a
+ *    symmetric two-body law the tree is self-thermalising: P_gen(T|c_v) is the same
+ *    for every node, so P_node reduces to exp(-beta E_v) normalised over the nodes.
+ *    The tree used is a star: a hub (node 0) and M leaves (nodes 1..M), edge e
+ *    joining the hub and leaf e and carrying a flip set F_e.
+ *  - Standard MCMC with the Metropolis rate min(1, ratio), Sec. "Problem statement",
+ *    for the single-update baseline (rule METROPOLIS, M = 1).
+ *  - Observables as node-weighted averages over the graph, Eq. eq_monte_carlo_graph.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC'11), keyed by the seed; the counter names the
+ * purpose of the draw (tag), the chain, the step, the edge and the block index.
+ * Distinct k-subsets: R. W. Floyd's algorithm (Bentley & Floyd, CACM 30(9), 1987).
+ * exp: Cody-Waite argument reduction by ln 2 and a degree-13 Taylor polynomial.
+ *
+ * Compile with -O2 -ffp-contract=off (no fused multiply-add anywhere).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+/* ------------------------------------------------------------------ Philox4x32-10 */
+
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+/* One Philox4x32-10 block: 10 rounds of the S-box/permutation round of SC'11,
+ * with the Weyl key schedule bumped between rounds. */
+void mc3o_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Stream tags (counter word 3, top 4 bits). */
+enum { TAG_INIT = 1, TAG_ROOT = 2, TAG_EDGE = 3, TAG_SELECT = 4 };
+
+/* Word n of the stream (tag, chain, step, edge):
+ * counter = (n / 4, edge, step, tag << 28 | chain), key = (seed lo, seed hi),
+ * word = block[n % 4]. */
+uint32_t mc3o_word(uint64_t seed, uint32_t tag, uint32_t chain, uint32_t step,
+                   uint32_t edge, uint32_t n)
+{
+    uint32_t ctr[4] = { n / 4u, edge, step, (tag << 28) | (chain & 0x0FFFFFFFu) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t out[4];
+    mc3o_philox(ctr, key, out);
+    return out[n % 4u];
+}
+
+/* Integer in [0, n) from one 32-bit word: floor(w * n / 2^32). */
+uint32_t mc3o_randint(uint32_t w, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+/* 53-bit uniform integer from two words: top 27 bits of w0, top 26 bits of w1. */
+uint64_t mc3o_u53(uint32_t w0, uint32_t w1)
+{
+    return ((uint64_t)(w0 >> 5) << 26) | (uint64_t)(w1 >> 6);
+}
+
+/* --------------------------------------------------------------------------- exp */
+
+/* exp(x) for x <= 0.  x = k ln2 + r with |r| <= ln2/2 (Cody-Waite: ln 2 split into
+ * a 32-significant-bit head, so k * head is exact, and a tail); exp(r) by the
+ * Taylor series to degree 13 in Horner form; result scaled by 2^k.  Values below
+ * -708 return 0 (a weight below 2^-1021 cannot change any selection, see select). */
+double mc3o_exp(double x)
+{
+    const double LOG2E = 0x1.71547652b82fep+0;
+    const double LN2_HEAD = 0x1.62e42ff000000p-1;
+    const double LN2_TAIL = -0x1.718432a1b0e26p-35;
+    /* 1/n! rounded to nearest, n = 13 .. 2 */
+    const double C13 = 0x1.6124613a86d09p-33, C12 = 0x1.1eed8eff8d898p-29;
+    const double C11 = 0x1.ae64567f544e4p-26, C10 = 0x1.27e4fb7789f5cp-22;
+    const double C9 = 0x1.71de3a556c734p-19, C8 = 0x1.a01a01a01a01ap-16;
+    const double C7 = 0x1.a01a01a01a01ap-13, C6 = 0x1.6c16c16c16c17p-10;
+    const double C5 = 0x1.1111111111111p-7, C4 = 0x1.5555555555555p-5;
+    const double C3 = 0x1.5555555555555p-3, C2 = 0x1.0p-1;
+    if (x != x) return x;
+    if (x < -708.0) return 0.0;
+    if (x > 709.0) return INFINITY;
+    double kd = floor(x * LOG2E + 0.5);
+    int k = (int)kd;
+    double r = (x - kd * LN2_HEAD) - kd * LN2_TAIL;
+    double p = C13;
+    p = p * r + C12;
+    p = p * r + C11;
+    p = p * r + C10;
+    p = p * r + C9;
+    p = p * r + C8;
+    p = p * r + C7;
+    p = p * r + C6;
+    p = p * r + C5;
+    p = p * r + C4;
+    p = p * r + C3;
+    p = p * r + C2;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    uint64_t bits = (uint64_t)(k + 1023) << 52;   /* 2^k, a normal number here */
+    double two_k;
+    memcpy(&two_k, &bits, sizeof two_k);
+    return p * two_k;
+}
+
+/* ------------------------------------------------------------------------- Floyd */
+
+/* Floyd's k-of-N distinct-site draw, driven by the given words (k words):
+ * for j = N-k .. N-1: t = randint(word, j+1); insert t unless already present,
+ * else insert j.  member[0..N-1] receives 0/1. */
+void mc3o_floyd_words(int N, int k, const uint32_t* words, uint8_t* member)
+{
+    memset(member, 0, (size_t)N);
+    for (int idx = 0; idx < k; ++idx) {
+        int j = N - k + idx;
+        uint32_t t = mc3o_randint(words[idx], (uint32_t)(j + 1));
+        if (member[t]) member[j] = 1;
+        else member[t] = 1;
+    }
+}
+
+/* ------------------------------------------------------------------------ energy */
+
+/* E(s) = -scale * sum_{i<j} J_ij s_i s_j with J row-major N x N (only the strict
+ * upper triangle is read), plain i-major double loop. */
+double mc3o_energy(int N, const double* J, double scale, const int8_t* s)
+{
+    double sum = 0.0;
+    for (int i = 0; i < N; ++i) {
+        for (int j = i + 1; j < N; ++j) {
+            double term = J[(size_t)i * N + j];
+            if (s[i] != s[j]) term = -term;
+            sum += term;
+        }
+    }
+    return -(scale * sum);
+}
+
+/* Initial spins: bit i%32 of word i/32 of the INIT stream (step 0, edge 0);
+ * a set bit means spin -1. */
+void mc3o_init_spins(uint64_t seed, int N, uint32_t chain, int8_t* s)
+{
+    for (int i = 0; i < N; ++i) {
+        uint32_t w = mc3o_word(seed, TAG_INIT, chain, 0u, 0u, (uint32_t)(i / 32));
+        s[i] = ((w >> (i % 32)) & 1u) ? (int8_t)-1 : (int8_t)1;
+    }
+}
+
+/* ------------------------------------------------------------------------ propose */
+
+/* Flip set of edge e (1..M) of chain `chain` at `step`:
+ * k_e = kmin + randint(word 0, kmax-kmin+1), then Floyd on words 1..k_e. */
+int mc3o_edge_flips(uint64_t seed, uint32_t chain, uint32_t step, uint32_t edge,
+                    int N, int kmin, int kmax, uint8_t* member)
+{
+    uint32_t w0 = mc3o_word(seed, TAG_EDGE, chain, step, edge, 0u);
+    int k = kmin + (int)mc3o_randint(w0, (uint32_t)(kmax - kmin + 1));
+    uint32_t* words = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(k > 0 ? k : 1));
+    for (int idx = 0; idx < k; ++idx)
+        words[idx] = mc3o_word(seed, TAG_EDGE, chain, step, edge, (uint32_t)(1 + idx));
+    mc3o_floyd_words(N, k, words, member);
+    free(words);
+    return k;
+}
+
+/* Root position r in {0..M}: randint(ROOT word 0, M+1). */
+int mc3o_root(uint64_t seed, uint32_t chain, uint32_t step, int M)
+{
+    return (int)mc3o_randint(mc3o_word(seed, TAG_ROOT, chain, step, 0u, 0u), (uint32_t)(M + 1));
+}
+
+/* Node configurations of the star graph generated from the current state s.
+ * Root r = 0: hub = s, leaf e = s with F_e flipped.
+ * Root r >= 1: leaf r = s, hub = s with F_r flipped, leaf e != r = hub with F_e
+ * flipped.  nodes: [(M+1) x N] int8. */
+void mc3o_build_nodes(int N, int M, int r, const int8_t* s, const uint8_t* flips /*[M+1][N], row 0 unused*/,
+                      int8_t* nodes)
+{
+    for (int v = 0; v <= M; ++v) {
+        for (int i = 0; i < N; ++i) {
+            int flip;
+            if (r == 0) flip = (v == 0) ? 0 : flips[(size_t)v * N + i];
+            else if (v == r) flip = 0;
+            else if (v == 0) flip = flips[(size_t)r * N + i];
+            else flip = flips[(size_t)r * N + i] ^ flips[(size_t)v * N + i];
+            nodes[(size_t)v * N + i] = flip ? (int8_t)(-s[i]) : s[i];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ select */
+
+typedef struct {
+    int32_t r;          /* root position (position of the state the graph was generated from) */
+    int32_t vstar;      /* selected node */
+    double e_cur;       /* energy of the selected node (the new current state) */
+    double e_bar;       /* node-weighted energy sum_v P_node(v) E_v */
+    double margin;      /* distance of the draw to the selected interval's edges, in units of W */
+    uint64_t wsum;      /* W: sum of the fixed-point weights */
+} mc3o_rec;
+
+/* MCMCMC node rule for a self-thermalising graph:
+ * P_node(v) proportional to exp(-beta (E_v - Emin)).
+ * Weights w_v = exp(-(beta*(E_v - Emin))) in FP64, then q_v = floor(w_v * 2^52)
+ * (exact integers), Q_v = inclusive prefix sum, W = Q_M, threshold
+ * t = floor(u53 * W / 2^53), selected v* = min { v : Q_v > t }.
+ * log_prior (may be NULL) adds log g_v to the exponent for non-uniform P_gen. */
+int mc3o_select_mcmcmc(int nodes, const double* E, const double* log_prior, double beta,
+                       uint64_t u53, double* e_bar, double* margin, uint64_t* wsum)
+{
+    double emin = E[0];
+    for (int v = 1; v < nodes; ++v) if (E[v] < emin) emin = E[v];
+    double* w = (double*)malloc(sizeof(double) * (size_t)nodes);
+    double lmax = -INFINITY;
+    for (int v = 0; v < nodes; ++v) {
+        double l = -(beta * (E[v] - emin));
+        if (log_prior) l = l + log_prior[v];
+        w[v] = l;
+        if (l > lmax) lmax = l;
+    }
+    for (int v = 0; v < nodes; ++v) w[v] = mc3o_exp(w[v] - lmax);
+    uint64_t Wq = 0;
+    uint64_t* Q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nodes);
+    for (int v = 0; v < nodes; ++v) {
+        uint64_t q = (uint64_t)floor(w[v] * 0x1.0p52);
+        Wq += q;
+        Q[v] = Wq;
+    }
+    unsigned __int128 prod = (unsigned __int128)u53 * (unsigned __int128)Wq;
+    uint64_t t = (uint64_t)(prod >> 53);
+    int vs = 0;
+    while (Q[vs] <= t) ++vs;
+    uint64_t lo = vs ? Q[vs - 1] : 0u;
+    uint64_t d1 = t - lo, d2 = Q[vs] - t;
+    *margin = (double)(d1 < d2 ? d1 : d2) / (double)Wq;
+    double num = 0.0, den = 0.0;
+    for (int v = 0; v < nodes; ++v) { num += w[v] * E[v]; den += w[v]; }
+    *e_bar = num / den;
+    *wsum = Wq;
+    free(w);
+    free(Q);
+    return vs;
+}
+
+/* Metropolis rate min(1, exp(-beta dE)) for one proposal.  Accept iff dE <= 0 or
+ * u < exp(-(beta*dE)), u = u53 / 2^53. */
+int mc3o_accept_metropolis(double e_cur, double e_new, double beta, uint64_t u53, double* margin)
+{
+    double dE = e_new - e_cur;
+    if (dE <= 0.0) { *margin = INFINITY; return 1; }
+    double w = mc3o_exp(-(beta * dE));
+    double u = (double)u53 * 0x1.0p-53;
+    *margin = fabs(u - w);
+    return u < w;
+}
+
+/* ------------------------------------------------------------------------ run */
+
+typedef struct {
+    int32_t N, M, chains, kmin, kmax;
+    int32_t rule;          /* 0 = MCMCMC, 1 = METROPOLIS (M must be 1) */
+    uint32_t chain_base;   /* global index of chain 0 (RNG counter) */
+    uint32_t pad;
+    uint64_t seed;
+    double scale;          /* energy scale: E = -scale * sum_{i<j} J_ij s_i s_j */
+} mc3o_cfg;
+
+/* Run nsteps steps starting at global step step0 for every chain.
+ *   spins  [chains][N] in/out, e_cur [chains] in/out (energy of the current state).
+ *   beta   [nsteps] inverse temperature per step.
+ *   rec    [nsteps][chains] records (may be NULL).
+ *   node_e [nsteps][chains][M+1] energies of every node (may be NULL).
+ *   forced [nsteps][chains] node to take instead of the drawn one, -1 = none
+ *          (guided replay at steps where the compared path reported a near-tie;
+ *          may be NULL).
+ * Every node energy is recomputed from its configuration by the plain pair sum,
+ * including the current state's.  Returns 0, or -1 on a bad configuration. */
+int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
+             uint64_t step0, int64_t nsteps, const double* beta,
+             mc3o_rec* rec, double* node_e, const int32_t* forced)
+{
+    const int N = cfg->N, M = cfg->M;
+    if (N < 2 || M < 1 || cfg->chains < 1 || cfg->kmin < 1 || cfg->kmax < cfg->kmin || cfg->kmax > N) return -1;
+    if (cfg->rule == 1 && M != 1) return -1;
+    uint8_t* flips = (uint8_t*)malloc((size_t)(M + 1) * N);
+    int8_t* nodes = (int8_t*)malloc((size_t)(M + 1) * N);
+    double* E = (double*)malloc(sizeof(double) * (size_t)(M + 1));
+    for (int64_t ts = 0; ts < nsteps; ++ts) {
+        uint32_t step = (uint32_t)(step0 + (uint64_t)ts);
+        for (int c = 0; c < cfg->chains; ++c) {
+            uint32_t gc = cfg->chain_base + (uint32_t)c;
+            int8_t* s = spins + (size_t)c * N;
+            int r = (cfg->rule == 1) ? 0 : mc3o_root(cfg->seed, gc, step, M);
+            memset(flips, 0, (size_t)N);
+            for (int e = 1; e <= M; ++e)
+                mc3o_edge_flips(cfg->seed, gc, step, (uint32_t)e, N, cfg->kmin, cfg->kmax, flips + (size_t)e * N);
+            mc3o_build_nodes(N, M, r, s, flips, nodes);
+            for (int v = 0; v <= M; ++v) E[v] = mc3o_energy(N, J, cfg->scale, nodes + (size_t)v * N);
+            uint32_t w0 = mc3o_word(cfg->seed, TAG_SELECT, gc, step, 0u, 0u);
+            uint32_t w1 = mc3o_word(cfg->seed, TAG_SELECT, gc, step, 0u, 1u);
+            uint64_t u53 = mc3o_u53(w0, w1);
+            int vs;
+            double ebar, margin;
+            uint64_t wsum = 0;
+            if (cfg->rule == 1) {
+                int acc = mc3o_accept_metropolis(E[0], E[1], beta[ts], u53, &margin);
+                vs = acc ? 1 : 0;
+                ebar = E[vs];
+            } else {
+                vs = mc3o_select_mcmcmc(M + 1, E, NULL, beta[ts], u53, &ebar, &margin, &wsum);
+            }
+            if (forced && forced[(size_t)ts * cfg->chains + c] >= 0)
+                vs = forced[(size_t)ts * cfg->chains + c];
+            if (node_e) memcpy(node_e + ((size_t)ts * cfg->chains + c) * (M + 1), E, sizeof(double) * (size_t)(M + 1));
+            memcpy(s, nodes + (size_t)vs * N, (size_t)N);
+            e_cur[c] = E[vs];
+            if (rec) {
+                mc3o_rec* o = rec + (size_t)ts * cfg->chains + c;
+                o->r = r; o->vstar = vs; o->e_cur = E[vs]; o->e_bar = ebar;
+                o->margin = margin; o->wsum = wsum;
+            }
+        }
+    }
+    free(flips); free(nodes); free(E);
+    return 0;
+}

@@ -1,0 +1,151 @@
+"""Exact, brute-force checks of the MCMCMC method (numpy; shares no code with the
+oracle or the GPU library).
+
+Everything here enumerates: all 2^N spin states, every flip-set realisation of every
+edge, every root position.  These are the independent facts the oracle is pinned to.
+
+States are integers s in [0, 2^N); bit i set means spin i is -1.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+
+def spins_of(states: np.ndarray, N: int) -> np.ndarray:
+    """[len(states), N] array of +-1 spins."""
+    bits = (states[:, None] >> np.arange(N)[None, :]) & 1
+    return (1 - 2 * bits).astype(np.float64)
+
+
+def all_energies(J: np.ndarray, scale: float) -> np.ndarray:
+    """E(s) = -scale * sum_{i<j} J_ij s_i s_j for all 2^N states, via -scale/2 s^T J s
+    (J symmetric, zero diagonal)."""
+    N = J.shape[0]
+    S = spins_of(np.arange(2 ** N), N)
+    return -scale * 0.5 * np.einsum("si,ij,sj->s", S, J, S)
+
+
+def boltzmann(E: np.ndarray, beta: float) -> np.ndarray:
+    lw = -beta * (E - E.min())
+    w = np.exp(lw)
+    return w / w.sum()
+
+
+def flip_sets(N: int, kmin: int, kmax: int) -> Tuple[np.ndarray, np.ndarray]:
+    """All flip sets with kmin <= |F| <= kmax as bitmasks, and their probabilities
+    under k ~ U{kmin..kmax}, F uniform among k-subsets."""
+    masks, probs = [], []
+    nk = kmax - kmin + 1
+    for k in range(kmin, kmax + 1):
+        c = math.comb(N, k)
+        for sub in itertools.combinations(range(N), k):
+            masks.append(sum(1 << i for i in sub))
+            probs.append(1.0 / (nk * c))
+    return np.array(masks, dtype=np.int64), np.array(probs, dtype=np.float64)
+
+
+def star_kernel(E: np.ndarray, beta: float, N: int, M: int, kmin: int, kmax: int,
+                root_mode: str = "uniform", weights: str = "node") -> np.ndarray:
+    """Exact transition matrix of one MCMCMC step with the M-ary star, over all root
+    positions and all flip-set realisations.
+
+    root_mode "uniform": the current state sits at position r ~ U{0..M} (the
+    populating process with uniform root).  root_mode "hub": the current state is
+    always the hub (the invalid construction, kept as a negative control).
+    weights "node": P_node proportional to exp(-beta E_v) over all M+1 nodes.
+    """
+    S = 2 ** N
+    masks, probs = flip_sets(N, kmin, kmax)
+    nF = len(masks)
+    P = np.zeros((S, S))
+    combos = np.array(list(itertools.product(range(nF), repeat=M)), dtype=np.int64)  # [C, M]
+    cprob = np.prod(probs[combos], axis=1)                                          # [C]
+    fm = masks[combos]                                                              # [C, M]
+    roots = range(M + 1) if root_mode == "uniform" else [0]
+    for s in range(S):
+        for r in roots:
+            pr = 1.0 / len(roots)
+            nodes = np.zeros((len(combos), M + 1), dtype=np.int64)
+            if r == 0:
+                nodes[:, 0] = s
+                nodes[:, 1:] = s ^ fm
+            else:
+                hub = s ^ fm[:, r - 1]
+                nodes[:, 0] = hub
+                nodes[:, 1:] = hub[:, None] ^ fm
+                nodes[:, r] = s
+            En = E[nodes]
+            lw = -beta * (En - En.min(axis=1, keepdims=True))
+            w = np.exp(lw)
+            pn = w / w.sum(axis=1, keepdims=True)
+            np.add.at(P, (np.full(nodes.shape, s), nodes), pr * cprob[:, None] * pn)
+    return P
+
+
+def barker_kernel(E: np.ndarray, beta: float, N: int, kmin: int, kmax: int) -> np.ndarray:
+    """Single-proposal heat-bath (Barker) rate: w'/(w + w')."""
+    S = 2 ** N
+    masks, probs = flip_sets(N, kmin, kmax)
+    P = np.zeros((S, S))
+    for s in range(S):
+        for m, p in zip(masks, probs):
+            t = s ^ m
+            a = 1.0 / (1.0 + math.exp(beta * (E[t] - E[s])))
+            P[s, t] += p * a
+            P[s, s] += p * (1 - a)
+    return P
+
+
+def metropolis_kernel(E: np.ndarray, beta: float, N: int, kmin: int, kmax: int) -> np.ndarray:
+    """Single-proposal Metropolis rate min(1, exp(-beta dE))."""
+    S = 2 ** N
+    masks, probs = flip_sets(N, kmin, kmax)
+    P = np.zeros((S, S))
+    for s in range(S):
+        for m, p in zip(masks, probs):
+            t = s ^ m
+            a = min(1.0, math.exp(-beta * (E[t] - E[s])))
+            P[s, t] += p * a
+            P[s, s] += p * (1 - a)
+    return P
+
+
+# ---------------------------------------------------------------- worked examples
+
+def three_config_generation(Pprp: np.ndarray, p: float) -> Dict[Tuple[int, Tuple], float]:
+    """Enumerate the three-configuration generation process from every start x:
+    draw y1 ~ Pprp[x]; with probability p draw y2 ~ Pprp[x] (both attached to x),
+    otherwise y2 ~ Pprp[y1] (attached to y1).  Returns the probability of each
+    (start, undirected edge set) with three distinct configurations."""
+    n = Pprp.shape[0]
+    out: Dict[Tuple[int, Tuple], float] = {}
+    for x in range(n):
+        for y1 in range(n):
+            p1 = Pprp[x, y1]
+            for y2 in range(n):
+                if len({x, y1, y2}) < 3:
+                    continue
+                for branch, pb, src in (("star", p, x), ("line", 1 - p, y1)):
+                    pr = p1 * pb * Pprp[src, y2]
+                    if pr == 0:
+                        continue
+                    edges = tuple(sorted([tuple(sorted((x, y1))), tuple(sorted((src, y2)))]))
+                    key = (x, edges)
+                    out[key] = out.get(key, 0.0) + pr
+    return out
+
+
+def line_graph_generation(L: int) -> np.ndarray:
+    """Line-graph addition process with a symmetric two-body law, counting only the
+    combinatorial factor: starting from one node, add L-1 nodes, each at the left
+    or right end with probability 1/2.  Returns g[k] = probability that the starting
+    node ends at position k of the line (positions 0..L-1)."""
+    g = np.zeros(L)
+    for bits in itertools.product((0, 1), repeat=L - 1):
+        left = sum(1 for b in bits if b == 0)
+        g[left] += 0.5 ** (L - 1)
+    return g

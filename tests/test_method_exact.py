@@ -1,0 +1,172 @@
+"""Exact checks of the method itself (no oracle involved): the star graph with a
+uniform root leaves the Boltzmann distribution invariant, the hub-always-current
+reading does not, the paper's two- and three-configuration cases, and the reading of
+the line-graph prior."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from exact_tools import (all_energies, barker_kernel, boltzmann, line_graph_generation,
+                         metropolis_kernel, star_kernel, three_config_generation)
+from paper_2102_05613_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("N,M,kmin,kmax,beta", [(4, 2, 1, 1, 1.0), (5, 3, 1, 2, 0.3),
+                                                (5, 2, 1, 2, 3.0), (4, 3, 1, 2, 1.0)])
+def test_star_uniform_root_is_stationary_and_reversible(N, M, kmin, kmax, beta):
+    J, scale = inputs.couplings_gauss(N, 100 + N)
+    E = all_energies(J, scale)
+    pi = boltzmann(E, beta)
+    P = star_kernel(E, beta, N, M, kmin, kmax)
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-12)
+    assert np.max(np.abs(pi @ P - pi)) < 1e-12
+    F = pi[:, None] * P
+    assert np.max(np.abs(F - F.T)) < 1e-12
+
+
+def test_star_m1_is_heat_bath():
+    N, beta = 5, 0.8
+    J, scale = inputs.couplings_gauss(N, 5)
+    E = all_energies(J, scale)
+    assert np.allclose(star_kernel(E, beta, N, 1, 1, 2), barker_kernel(E, beta, N, 1, 2), atol=1e-13)
+
+
+def test_metropolis_kernel_is_stationary():
+    N, beta = 5, 1.7
+    J, scale = inputs.couplings_gauss(N, 6)
+    E = all_energies(J, scale)
+    pi = boltzmann(E, beta)
+    P = metropolis_kernel(E, beta, N, 1, 2)
+    assert np.max(np.abs(pi @ P - pi)) < 1e-12
+
+
+def test_negative_control_hub_always_current_is_biased():
+    """Keeping the current state at the hub and weighting nodes by exp(-beta E) is
+    not the node rule (P_gen(T|leaf) differs from P_gen(T|hub)): it breaks
+    stationarity for M >= 2."""
+    N, beta = 5, 2.0
+    J, scale = inputs.couplings_gauss(N, 7)
+    E = all_energies(J, scale)
+    pi = boltzmann(E, beta)
+    for M in (2, 3):
+        P = star_kernel(E, beta, N, M, 1, 2, root_mode="hub")
+        assert np.max(np.abs(pi @ P - pi) / pi) > 1e-2
+        # its own stationary law is measurably away from Boltzmann
+        w, v = np.linalg.eig(P.T)
+        st = np.real(v[:, np.argmin(np.abs(w - 1.0))])
+        st = st / st.sum()
+        assert 0.5 * np.abs(st - pi).sum() > 2e-3
+    # M = 1 is the exception: a two-node graph is symmetric under re-rooting
+    P1 = star_kernel(E, beta, N, 1, 1, 2, root_mode="hub")
+    assert np.max(np.abs(pi @ P1 - pi)) < 1e-13
+
+
+def _load_three():
+    with open(os.path.join(GOLDEN, "three_configuration.json")) as f:
+        return json.load(f)
+
+
+def _eval_factor(fac, Pprp, p, lab):
+    tot = 1.0
+    for x in fac:
+        if isinstance(x, (int, float)):
+            tot *= x
+        elif x == "p":
+            tot *= p
+        elif x == "q":
+            tot *= 1 - p
+        else:
+            _, a, b = x
+            tot *= Pprp[lab[b], lab[a]]
+    return tot
+
+
+@pytest.mark.parametrize("p", [0.2, 0.5, 0.8])
+def test_three_configuration_generation_probabilities(p):
+    """Brute-force enumeration of the three-configuration process reproduces the
+    printed P_gen(T|c) for every labelling of a line c0-c1-c2 (middle node c1),
+    including the factor 2 at the middle node, for an asymmetric proposal."""
+    gold = _load_three()["P_gen_T_given"]
+    n = 5
+    rng = np.random.Generator(np.random.PCG64(3))
+    Pprp = rng.random((n, n))
+    np.fill_diagonal(Pprp, 0.0)
+    Pprp /= Pprp.sum(axis=1, keepdims=True)
+    gen = three_config_generation(Pprp, p)
+    checked = 0
+    for c0 in range(n):
+        for c1 in range(n):
+            for c2 in range(n):
+                if len({c0, c1, c2}) < 3:
+                    continue
+                edges = tuple(sorted([tuple(sorted((c0, c1))), tuple(sorted((c1, c2)))]))
+                lab = {"c0": c0, "c1": c1, "c2": c2}
+                for node in ("c0", "c1", "c2"):
+                    want = _eval_factor(gold[node], Pprp, p, lab)
+                    got = gen.get((lab[node], edges), 0.0)
+                    assert got == pytest.approx(want, rel=1e-12, abs=1e-15)
+                    checked += 1
+    assert checked == 3 * n * (n - 1) * (n - 2)
+
+
+@pytest.mark.parametrize("p", [0.2, 0.5, 0.8])
+def test_three_configuration_node_rule_is_stationary(p):
+    """The graph chain with P_node proportional to P_eq(c) P_gen(T|c) leaves P_eq
+    invariant; dropping the printed factor 2 breaks it (unless p makes it vanish)."""
+    n = 5
+    rng = np.random.Generator(np.random.PCG64(4))
+    Pprp = rng.random((n, n))
+    np.fill_diagonal(Pprp, 0.0)
+    Pprp /= Pprp.sum(axis=1, keepdims=True)
+    w = rng.random(n) + 0.1
+    pi = w / w.sum()
+    gen = three_config_generation(Pprp, p)
+    graphs = {}
+    for (x, edges), pr in gen.items():
+        graphs.setdefault(edges, {})[x] = pr
+
+    def kernel(drop_two):
+        P = np.zeros((n, n))
+        for (x, edges), pr in gen.items():
+            g = dict(graphs[edges])
+            if drop_two:
+                # remove the factor 2 of the middle node of a line
+                deg = {}
+                for a, b in edges:
+                    deg[a] = deg.get(a, 0) + 1
+                    deg[b] = deg.get(b, 0) + 1
+                for node in g:
+                    if deg[node] == 2:
+                        g[node] = g[node] / 2.0
+            nodes = sorted({a for e in edges for a in e})
+            z = sum(pi[c] * g.get(c, 0.0) for c in nodes)
+            for c in nodes:
+                P[x, c] += pr * pi[c] * g.get(c, 0.0) / z
+        # generation paths that repeat a configuration are not enumerated above; the
+        # chain stays put on them (a self-loop cannot affect stationarity)
+        P[np.diag_indices(n)] += 1.0 - P.sum(axis=1)
+        return P
+
+    P = kernel(False)
+    assert np.allclose(P.sum(axis=1), 1.0)
+    assert np.max(np.abs(pi @ P - pi)) < 1e-13
+    P_bad = kernel(True)
+    assert np.max(np.abs(pi @ P_bad - pi)) > 1e-4
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 6, 8])
+def test_line_graph_prior_reading(L):
+    """Line-graph addition process (App. 'Line-graph addition process'): the start
+    node ends at position k with probability C(L-1, k) / 2^(L-1).  The printed
+    C(L, k) / 2^L does not even normalise over k = 0..L-1, so the reading taken is
+    C(L-1, k) / 2^(L-1)."""
+    g = line_graph_generation(L)
+    for k in range(L):
+        assert g[k] == pytest.approx(math.comb(L - 1, k) / 2 ** (L - 1), rel=1e-14)
+    printed = np.array([math.comb(L, k) / 2 ** L for k in range(L)])
+    assert abs(printed.sum() - 1.0) > 1e-3
