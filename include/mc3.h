@@ -1,0 +1,196 @@
+/*
+ * mc3.h -- C ABI of the MI355X many-configuration Markov-chain Monte Carlo (MCMCMC)
+ * hot path for the Sherrington-Kirkpatrick (SK) spin glass.
+ *
+ * Method (paper: "Many-Configuration Markov-Chain Monte Carlo"):
+ *   - Target: P_eq(s) proportional to exp(-beta E(s)) with the SK energy
+ *     E(s) = -scale * sum_{i<j} J_ij s_i s_j, s_i in {-1,+1}
+ *     (Sec. "The Sherrington-Kirkpatrick model"; the paper's +1/sqrt(L) sum J S S
+ *     with unit-variance J is the same law with J -> -J/sqrt(L)).
+ *   - Each step every chain generates a graph of configurations from its current
+ *     state and moves to one node of it, drawn with
+ *     P_node(c|T) = P_eq(c) P_gen(T|c) / sum_{c' in T} P_eq(c') P_gen(T|c')
+ *     (App. "Markov chain of graphs of configurations", Eq.
+ *     eq_det_balance_graph_solution with the normalisation of
+ *     Eq. eq_normalization_p_c_T).
+ *   - Graph: an M-ary star (hub = node 0, leaves 1..M) populated from a root drawn
+ *     uniformly among the M+1 positions (App. "General graph populating process");
+ *     each edge e carries a flip set F_e of k_e ~ U{kmin..kmax} distinct sites.
+ *     Flip sets do not depend on the state, so the two-body law is symmetric and
+ *     the tree is self-thermalising: P_node(v) = exp(-beta E_v) / sum_v' exp(-beta E_v').
+ *   - Rule METROPOLIS (M = 1): the single-update Metropolis rate min(1, e^{-beta dE})
+ *     of Sec. "Problem statement", the paper's baseline.
+ *
+ * Conventions
+ *   - Spin bitsets: bit i of word i/32 set <=> s_i = -1.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key (seed lo, seed hi)
+ *     and counter (block, edge, step, tag<<28 | global chain).  Tags: 1 init,
+ *     2 root, 3 edge, 4 select.  randint(w, n) = (w * n) >> 32.
+ *   - All calls are asynchronous on the stream given at create time unless stated.
+ *   - Results depend only on (config, couplings, seed, step numbers), never on the
+ *     launch geometry.
+ *
+ * Errors: every call returns an mc3_status; no C++ exception crosses the ABI.  A
+ * device error seen by a synchronising call (mc3_sync, mc3_measure, mc3_read_*)
+ * poisons the context: later calls return MC3_E_STATE.  mc3_last_error gives text.
+ */
+#ifndef MC3_H
+#define MC3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MC3_OK = 0,
+    MC3_E_ARG = -1,         /* invalid argument or configuration */
+    MC3_E_DEVICE = -3,      /* a HIP call or kernel failed */
+    MC3_E_STATE = -4,       /* call out of order, or context poisoned */
+    MC3_E_UNSUPPORTED = -5, /* valid request this build does not implement */
+    MC3_E_NUMERIC = -6,     /* non-finite or inconsistent couplings */
+    MC3_E_WORKSPACE = -7    /* workspace missing, too small or misaligned */
+} mc3_status;
+
+typedef enum {
+    MC3_FP64 = 0,        /* scoring in FP64 on the FP64 matrix cores */
+    MC3_SPLIT_BF16 = 1   /* J = hi + mid + lo (three BF16 terms), spins exact in BF16,
+                            FP32 accumulation on the BF16 matrix cores, FP64 epilogue */
+} mc3_precision;
+
+typedef enum {
+    MC3_RULE_MCMCMC = 0,     /* node rule over the (M+1)-node star */
+    MC3_RULE_METROPOLIS = 1  /* single proposal, Metropolis rate; requires M == 1 */
+} mc3_rule;
+
+/* One SK instance and its chains.  Constraints: 2 <= N <= 8192, 1 <= M <= 4096,
+ * 1 <= chains, 1 <= kmin <= kmax <= N, chains * M <= 2^24, rule METROPOLIS => M == 1. */
+typedef struct {
+    int32_t N;               /* spins */
+    int32_t M;               /* graph size minus one: leaves of the star = new configurations per chain-step */
+    int32_t chains;          /* independent chains */
+    int32_t kmin, kmax;      /* flip-set size range of every edge */
+    int32_t precision;       /* mc3_precision */
+    int32_t rule;            /* mc3_rule */
+    int32_t trace_steps;     /* capacity of the per-step record ring (>= 0) */
+    uint64_t seed;           /* Philox key */
+    uint32_t chain_base;     /* global index of chain 0 in the Philox counter */
+    uint32_t reserved;       /* must be 0 */
+    double near_tie_tol;     /* selection margin below which a step is flagged; < 0 => default */
+} mc3_config;
+
+/* Per-step, per-chain record (40 bytes). */
+typedef struct {
+    int32_t r;          /* position of the state the graph was generated from (root) */
+    int32_t vstar;      /* selected node; METROPOLIS: 1 = accepted, 0 = rejected */
+    double e_cur;       /* energy of the state after the step */
+    double e_bar;       /* node-weighted energy sum_v P_node(v) E_v (Eq. eq_monte_carlo_graph);
+                           METROPOLIS: e_cur */
+    double margin;      /* distance of the draw to the edges of the selected interval,
+                           as a fraction of the total weight (METROPOLIS: |u - rate|) */
+    uint32_t flags;     /* bit 0: near tie (margin < near_tie_tol); bit 1: moved */
+    uint32_t step;      /* global step number */
+} mc3_record;
+
+/* Aggregate counters since the last mc3_init_chains. */
+typedef struct {
+    int64_t steps_done;    /* chain-steps summed over chains / chains */
+    int64_t moves;         /* chain-steps that changed the state */
+    int64_t near_ties;     /* chain-steps flagged as near ties */
+    double min_margin;     /* smallest selection margin seen */
+    double max_drift;      /* largest |E_carried - E_recomputed| at mc3_recompute */
+} mc3_summary;
+
+typedef struct mc3_ctx mc3_ctx;
+
+/* Device workspace (bytes) the context needs for this configuration.  The caller
+ * allocates it (any device allocator; 256-byte aligned) and lends it to mc3_create. */
+mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes);
+
+/* Create a context on the current HIP device.  `workspace` is a device pointer of at
+ * least mc3_workspace_size bytes, borrowed for the lifetime of the context; `stream`
+ * is a hipStream_t (NULL = default stream), borrowed likewise.  Performs no device
+ * allocation.  Validates the configuration before any HIP call. */
+mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out);
+
+/* Release the host-side context (the workspace stays the caller's). */
+mc3_status mc3_destroy(mc3_ctx* ctx);
+
+/* Load couplings: J is a host array of N*N doubles, row-major with leading dimension
+ * ld >= N; only the strict upper triangle i<j is used (J is taken as symmetric with
+ * zero diagonal).  Energies are E = -scale * sum_{i<j} J_ij s_i s_j.  Values must
+ * be finite (MC3_E_NUMERIC otherwise).  The array is copied before return
+ * (synchronous on the stream); the device keeps J in FP64 and, for the split
+ * precision, as three BF16 terms hi = bf16(J), mid = bf16(J - hi),
+ * lo = bf16(J - hi - mid), each packed in matrix-core fragment order. */
+mc3_status mc3_init_couplings(mc3_ctx* ctx, const double* J, int64_t ld, double scale);
+
+/* Set the chains' states: spins is a host array [chains][N] of +-1 (int8), or NULL to
+ * draw them from the init stream (bit i%32 of word i/32 of stream (tag 1, chain,
+ * step 0, edge 0); set bit = spin -1).  Computes each chain's FP64 energy and clears
+ * the record ring and the summary.  Requires couplings. */
+mc3_status mc3_init_chains(mc3_ctx* ctx, const int8_t* spins);
+
+/* Draw the graph of every chain at global step `step` (App. "General graph
+ * populating process", uniform root): root r = randint(word 0 of (tag 2), M+1)
+ * (METROPOLIS: r = 0); for each edge e = 1..M of stream (tag 3, edge e):
+ * k_e = kmin + randint(word 0, kmax-kmin+1), then Floyd's k-of-N on words 1..k_e.
+ * Node configurations: r = 0: hub = s, leaf e = s^F_e; r >= 1: leaf r = s,
+ * hub = s^F_r, leaf e = s^F_r^F_e.  Materialises the M non-current nodes of each
+ * chain as candidate bitsets (column m of chain c is node m if m < r else m+1). */
+mc3_status mc3_propose(mc3_ctx* ctx, uint32_t step);
+
+/* Score the candidates of the last mc3_propose: E(c) = -scale sum_{i<j} J_ij c_i c_j
+ * for every candidate column, on the matrix cores (Sec. "The Sherrington-Kirkpatrick
+ * model").  If E_out is not NULL it receives the energies, a device array
+ * [chains][M] of doubles owned by the caller. */
+mc3_status mc3_score_candidates(mc3_ctx* ctx, double* E_out);
+
+/* Apply the node rule to the scored graphs at step `step` with inverse temperature
+ * beta and move every chain (App. "Markov chain of graphs of configurations"):
+ * Emin = min_v E_v (the current node's E is its carried energy);
+ * w_v = exp(-(beta (E_v - Emin))) in FP64; q_v = floor(w_v 2^52) (exact integers);
+ * Q_v their inclusive prefix sum in node order 0..M, W = Q_M;
+ * t = floor(u53 W / 2^53) with u53 from words 0,1 of (tag 4);
+ * v* = min{v : Q_v > t}.  METROPOLIS: accept iff dE <= 0 or u53/2^53 < exp(-(beta dE)).
+ * Writes one mc3_record per chain into the ring (slot step % trace_steps). */
+mc3_status mc3_select(mc3_ctx* ctx, uint32_t step, double beta);
+
+/* n steps starting at global step step0: propose, score, select each step, with
+ * beta_t = beta0 + (beta1 - beta0) * (t / (total - 1)) for t = step0 .. step0+n-1
+ * (beta0 if total <= 1). */
+mc3_status mc3_step_n(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
+
+/* Recompute every chain's energy from its spins in FP64 (plain pair sum on the
+ * device), record max |carried - recomputed| in the summary, and replace the
+ * carried energy by the recomputed one. */
+mc3_status mc3_recompute(mc3_ctx* ctx);
+
+/* Synchronise; copy the chains' energies (host [chains], may be NULL), spins (host
+ * bitsets [chains][ceil(N/32)] uint32, may be NULL) and the summary (may be NULL). */
+mc3_status mc3_measure(mc3_ctx* ctx, double* e_cur, uint32_t* spin_bits, mc3_summary* summary);
+
+/* Synchronise and copy `n` steps of records starting at global step `first`
+ * (they must still be in the ring) into host [n][chains]. */
+mc3_status mc3_read_records(mc3_ctx* ctx, uint32_t first, int32_t n, mc3_record* out);
+
+/* Synchronise and copy the candidate bitsets of the last mc3_propose into host
+ * [chains][M][ceil(N/32)] uint32, and the roots into host [chains] (either may be NULL). */
+mc3_status mc3_read_candidates(mc3_ctx* ctx, uint32_t* bits, int32_t* roots);
+
+/* Wait for the stream; report any device error. */
+mc3_status mc3_sync(mc3_ctx* ctx);
+
+/* Text of the last error on this context ("" if none); valid until the next call. */
+const char* mc3_last_error(const mc3_ctx* ctx);
+
+/* Library version string. */
+const char* mc3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC3_H */

@@ -1,0 +1,213 @@
+"""ctypes binding of libmc3.so with the same names as the C ABI (include/mc3.h).
+
+Marshalling only: the workspace is a torch uint8 CUDA tensor, the stream is torch's
+current HIP stream; every computation happens in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmc3.so")
+
+MC3_OK, MC3_E_ARG, MC3_E_DEVICE, MC3_E_STATE = 0, -1, -3, -4
+MC3_E_UNSUPPORTED, MC3_E_NUMERIC, MC3_E_WORKSPACE = -5, -6, -7
+MC3_FP64, MC3_SPLIT_BF16 = 0, 1
+MC3_RULE_MCMCMC, MC3_RULE_METROPOLIS = 0, 1
+
+PRECISIONS = {"fp64": MC3_FP64, "split_bf16": MC3_SPLIT_BF16}
+RULES = {"mcmcmc": MC3_RULE_MCMCMC, "metropolis": MC3_RULE_METROPOLIS}
+
+STATUS_NAMES = {0: "MC3_OK", -1: "MC3_E_ARG", -3: "MC3_E_DEVICE", -4: "MC3_E_STATE",
+                -5: "MC3_E_UNSUPPORTED", -6: "MC3_E_NUMERIC", -7: "MC3_E_WORKSPACE"}
+
+# every symbol include/mc3.h declares
+EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_couplings", "mc3_init_chains",
+           "mc3_propose", "mc3_score_candidates", "mc3_select", "mc3_step_n", "mc3_recompute", "mc3_measure",
+           "mc3_read_records", "mc3_read_candidates", "mc3_sync", "mc3_last_error", "mc3_version"]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("chains", ctypes.c_int32),
+                ("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("trace_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("chain_base", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("near_tie_tol", ctypes.c_double)]
+
+
+class Summary(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int64), ("moves", ctypes.c_int64), ("near_ties", ctypes.c_int64),
+                ("min_margin", ctypes.c_double), ("max_drift", ctypes.c_double)]
+
+
+RECORD_DTYPE = np.dtype([("r", np.int32), ("vstar", np.int32), ("e_cur", np.float64), ("e_bar", np.float64),
+                         ("margin", np.float64), ("flags", np.uint32), ("step", np.uint32)])
+assert RECORD_DTYPE.itemsize == 40
+
+
+class MC3Error(RuntimeError):
+    def __init__(self, status: int, what: str, msg: str = ""):
+        super().__init__(f"{what} -> {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmc3.so (built by paper_2102_05613_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2102_05613_amd.build.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    P, c = ctypes.POINTER, ctypes
+    vp = c.c_void_p
+    L.mc3_workspace_size.argtypes = [P(Config), P(c.c_size_t)]
+    L.mc3_create.argtypes = [P(Config), vp, c.c_size_t, vp, P(vp)]
+    L.mc3_destroy.argtypes = [vp]
+    L.mc3_init_couplings.argtypes = [vp, P(c.c_double), c.c_int64, c.c_double]
+    L.mc3_init_chains.argtypes = [vp, vp]
+    L.mc3_propose.argtypes = [vp, c.c_uint32]
+    L.mc3_score_candidates.argtypes = [vp, vp]
+    L.mc3_select.argtypes = [vp, c.c_uint32, c.c_double]
+    L.mc3_step_n.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
+    L.mc3_recompute.argtypes = [vp]
+    L.mc3_measure.argtypes = [vp, vp, vp, P(Summary)]
+    L.mc3_read_records.argtypes = [vp, c.c_uint32, c.c_int32, vp]
+    L.mc3_read_candidates.argtypes = [vp, vp, vp]
+    L.mc3_sync.argtypes = [vp]
+    L.mc3_last_error.argtypes = [vp]
+    L.mc3_last_error.restype = c.c_char_p
+    L.mc3_version.restype = c.c_char_p
+    for name in EXPORTS:
+        if name not in ("mc3_last_error", "mc3_version"):
+            getattr(L, name).restype = c.c_int
+    _lib = L
+    return L
+
+
+def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: str = "split_bf16",
+                rule: str = "mcmcmc", trace_steps: int = 0, seed: int = 0, chain_base: int = 0,
+                near_tie_tol: float = -1.0) -> Config:
+    return Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base, 0,
+                  near_tie_tol)
+
+
+def workspace_size(cfg: Config) -> int:
+    n = ctypes.c_size_t()
+    st = lib().mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n))
+    if st != MC3_OK:
+        raise MC3Error(st, "mc3_workspace_size")
+    return int(n.value)
+
+
+class Context:
+    """One SK instance with its chains on the current GPU."""
+
+    def __init__(self, cfg: Config, device=None):
+        import torch
+        self.cfg = cfg
+        self.N, self.M, self.chains = cfg.N, cfg.M, cfg.chains
+        self.words = (cfg.N + 31) // 32
+        nbytes = workspace_size(cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        h = ctypes.c_void_p()
+        st = lib().mc3_create(ctypes.byref(cfg), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != MC3_OK:
+            raise MC3Error(st, "mc3_create")
+        self.h = h
+
+    def _check(self, st: int, what: str):
+        if st != MC3_OK:
+            raise MC3Error(st, what, lib().mc3_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mc3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the ABI calls
+    def init_couplings(self, J: np.ndarray, scale: float):
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        assert J.shape == (self.N, self.N)
+        self._check(lib().mc3_init_couplings(self.h, J.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.N,
+                                             float(scale)), "mc3_init_couplings")
+
+    def init_chains(self, spins: Optional[np.ndarray] = None):
+        p = None
+        if spins is not None:
+            spins = np.ascontiguousarray(spins, dtype=np.int8)
+            assert spins.shape == (self.chains, self.N)
+            p = spins.ctypes.data
+        self._check(lib().mc3_init_chains(self.h, p), "mc3_init_chains")
+
+    def propose(self, step: int):
+        self._check(lib().mc3_propose(self.h, step), "mc3_propose")
+
+    def score_candidates(self, out=None):
+        """out: optional torch float64 CUDA tensor [chains*M] receiving the energies."""
+        p = None if out is None else ctypes.c_void_p(out.data_ptr())
+        self._check(lib().mc3_score_candidates(self.h, p), "mc3_score_candidates")
+
+    def select(self, step: int, beta: float):
+        self._check(lib().mc3_select(self.h, step, float(beta)), "mc3_select")
+
+    def step_n(self, step0: int, n: int, beta0: float, beta1: float, total: int):
+        self._check(lib().mc3_step_n(self.h, step0, n, float(beta0), float(beta1), total), "mc3_step_n")
+
+    def recompute(self):
+        self._check(lib().mc3_recompute(self.h), "mc3_recompute")
+
+    def measure(self):
+        e = np.zeros(self.chains, dtype=np.float64)
+        bits = np.zeros((self.chains, self.words), dtype=np.uint32)
+        s = Summary()
+        self._check(lib().mc3_measure(self.h, e.ctypes.data, bits.ctypes.data, ctypes.byref(s)), "mc3_measure")
+        summ = {k: getattr(s, k) for k, _ in Summary._fields_}
+        return e, bits, summ
+
+    def read_records(self, first: int, n: int) -> np.ndarray:
+        out = np.zeros((n, self.chains), dtype=RECORD_DTYPE)
+        self._check(lib().mc3_read_records(self.h, first, n, out.ctypes.data), "mc3_read_records")
+        return out
+
+    def read_candidates(self):
+        bits = np.zeros((self.chains, self.M, self.words), dtype=np.uint32)
+        roots = np.zeros(self.chains, dtype=np.int32)
+        self._check(lib().mc3_read_candidates(self.h, bits.ctypes.data, roots.ctypes.data), "mc3_read_candidates")
+        return bits, roots
+
+    def sync(self):
+        self._check(lib().mc3_sync(self.h), "mc3_sync")
+
+
+def bits_to_spins(bits: np.ndarray, N: int) -> np.ndarray:
+    """Bitsets [..., words] (set bit = -1) to int8 spins [..., N]."""
+    b = np.asarray(bits, dtype=np.uint32)
+    idx = np.arange(N)
+    v = (b[..., idx // 32] >> (idx % 32).astype(np.uint32)) & 1
+    return np.where(v == 1, -1, 1).astype(np.int8)
+
+
+def spins_to_bits(spins: np.ndarray) -> np.ndarray:
+    s = np.asarray(spins)
+    N = s.shape[-1]
+    words = (N + 31) // 32
+    out = np.zeros(s.shape[:-1] + (words,), dtype=np.uint32)
+    for i in range(N):
+        out[..., i // 32] |= ((s[..., i] < 0).astype(np.uint32) << np.uint32(i % 32))
+    return out

@@ -1,0 +1,105 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared symbol,
+its structs match the header, and configuration/workspace validation happens before
+any HIP call (so these run on a host without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2102_05613_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mc3.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2102_05613_amd import build
+        build.build()
+    return native.lib()
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mc3_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert names == sorted(native.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mc3_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header():
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "mc3.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mc3_config), offsetof(mc3_config, seed),
+         offsetof(mc3_config, near_tie_tol), sizeof(mc3_record), offsetof(mc3_record, margin), sizeof(mc3_summary));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = [int(x) for x in subprocess.check_output([exe]).split()]
+    assert vals == [ctypes.sizeof(native.Config), native.Config.seed.offset, native.Config.near_tie_tol.offset,
+                    native.RECORD_DTYPE.itemsize, native.RECORD_DTYPE.fields["margin"][1],
+                    ctypes.sizeof(native.Summary)]
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.mc3_version()
+
+
+@pytest.mark.parametrize("kw", [dict(N=1), dict(N=8193), dict(M=0), dict(chains=0), dict(kmin=0),
+                                dict(kmin=3, kmax=2), dict(kmax=65), dict(M=2, rule="metropolis"),
+                                dict(trace_steps=-1), dict(M=4097), dict(chains=70000, M=256)])
+def test_invalid_configs_rejected(lib, kw):
+    base = dict(N=64, M=4, chains=2, kmin=1, kmax=4)
+    rule = kw.pop("rule", "mcmcmc")
+    base.update(kw)
+    cfg = native.make_config(rule=rule, **base)
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == native.MC3_E_ARG
+    h = ctypes.c_void_p()
+    assert lib.mc3_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h)) == native.MC3_E_ARG
+
+
+def test_workspace_size_and_missing_workspace(lib):
+    cfg = native.make_config(1024, 128, 256, 1, 128, precision="split_bf16", trace_steps=10)
+    n = native.workspace_size(cfg)
+    # J64 (8 MiB) + split J (6 MiB) + candidates (4 MiB) + ...
+    assert 18 * 2 ** 20 < n < 40 * 2 ** 20
+    cfg2 = native.make_config(1024, 128, 512, 1, 128, precision="split_bf16", trace_steps=10)
+    assert native.workspace_size(cfg2) > n
+    h = ctypes.c_void_p()
+    assert lib.mc3_create(ctypes.byref(cfg), None, n, None, ctypes.byref(h)) == native.MC3_E_WORKSPACE
+    assert lib.mc3_create(ctypes.byref(cfg), ctypes.c_void_p(256), n - 1, None, ctypes.byref(h)) == native.MC3_E_WORKSPACE
+    assert lib.mc3_create(ctypes.byref(cfg), ctypes.c_void_p(4096 + 8), n, None, ctypes.byref(h)) == native.MC3_E_WORKSPACE
+
+
+def test_null_context_calls(lib):
+    assert lib.mc3_destroy(None) == native.MC3_E_ARG
+    assert lib.mc3_propose(None, 0) == native.MC3_E_ARG
+    assert lib.mc3_sync(None) == native.MC3_E_ARG
+    assert lib.mc3_last_error(None) == b"context is NULL"
+
+
+def test_bitset_helpers_roundtrip():
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(0))
+    s = np.where(rng.random((3, 77)) < 0.5, -1, 1).astype(np.int8)
+    assert np.array_equal(native.bits_to_spins(native.spins_to_bits(s), 77), s)

@@ -1,0 +1,215 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on seeded inputs.
+
+Bars: integer/bit work (spins, roots, candidate bitsets, selections of integer-energy
+instances) bit-exact; FP64-path energies within 1e-6 relative, split-BF16-path
+energies within 1e-4 relative; selections identical except at steps the GPU flags as
+near ties, where the oracle is guided onto the GPU's pick."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import announce, compare_trajectory, gpu_spins, make_ctx, oracle_candidates
+from paper_2102_05613_amd import inputs, native
+
+pytestmark = pytest.mark.gpu
+
+RTOL = {"fp64": 1e-6, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    native.lib()
+
+
+def _torch_f64(n):
+    import torch
+    return torch.zeros(n, dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("N,chains,prec", [(2, 3, "fp64"), (33, 5, "split_bf16"), (100, 7, "fp64"),
+                                           (1000, 4, "split_bf16"), (1024, 2, "fp64")])
+def test_init_spins_and_energies(N, chains, prec):
+    announce(f"init N={N} chains={chains} {prec}")
+    J, scale = inputs.couplings_gauss(N, 40 + N)
+    ctx = make_ctx(N, 2, chains, 1, 1, prec, J, scale, seed=123, chain_base=9)
+    e, bits, _ = ctx.measure()
+    s = native.bits_to_spins(bits, N)
+    for c in range(chains):
+        assert np.array_equal(s[c], oracle.init_spins(123, N, 9 + c))
+        assert e[c] == pytest.approx(oracle.energy(J, scale, s[c]), rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("N,M,chains,kmin,kmax,rule", [
+    (32, 4, 1, 1, 1, "mcmcmc"), (100, 9, 6, 1, 7, "mcmcmc"), (257, 16, 3, 2, 40, "mcmcmc"),
+    (1024, 128, 4, 1, 128, "mcmcmc"), (64, 1, 5, 1, 3, "metropolis"), (70, 3, 2, 70, 70, "mcmcmc"),
+    (2, 1, 2, 1, 2, "mcmcmc")])
+def test_propose_matches_oracle_bit_exact(N, M, chains, kmin, kmax, rule):
+    announce(f"propose N={N} M={M} chains={chains} k=[{kmin},{kmax}] {rule}")
+    J, scale = inputs.couplings_pm1(N, 3)
+    ctx = make_ctx(N, M, chains, kmin, kmax, "fp64", J, scale, rule=rule, seed=77)
+    s = gpu_spins(ctx)
+    for step in (0, 5, 2 ** 31 + 1):
+        ctx.propose(step)
+        bits, roots = ctx.read_candidates()
+        cand = native.bits_to_spins(bits, N)
+        for c in range(chains):
+            r, cols = oracle_candidates(77, c, step, N, M, kmin, kmax, s[c], rule=rule)
+            assert roots[c] == r
+            assert np.array_equal(cand[c], cols)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("N,M,chains,kmax", [(32, 4, 1, 1), (200, 5, 3, 20), (1000, 17, 9, 100),
+                                             (1024, 128, 8, 128)])
+def test_score_energies(prec, N, M, chains, kmax):
+    announce(f"score N={N} M={M} chains={chains} {prec}")
+    for kind in ("gauss", "pm1"):
+        J, scale = (inputs.couplings_gauss if kind == "gauss" else inputs.couplings_pm1)(N, 5 + N)
+        ctx = make_ctx(N, M, chains, 1, kmax, prec, J, scale, seed=3)
+        s = gpu_spins(ctx)
+        ctx.propose(11)
+        E = _torch_f64(chains * M)
+        ctx.score_candidates(E)
+        Eg = E.cpu().numpy().reshape(chains, M)
+        for c in range(chains):
+            _, cols = oracle_candidates(3, c, 11, N, M, 1, kmax, s[c])
+            Eo = np.array([oracle.energy(J, scale, x) for x in cols])
+            if kind == "pm1":
+                assert np.array_equal(Eg[c], Eo), (kind, c)
+            else:
+                np.testing.assert_allclose(Eg[c], Eo, rtol=RTOL[prec], atol=RTOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
+@pytest.mark.parametrize("M,rule", [(4, "mcmcmc"), (1, "mcmcmc"), (1, "metropolis")])
+def test_pm1_trajectory_bit_exact(prec, M, rule):
+    """N=32 +-1/sqrt(N) couplings, single flips, beta=1, 10^4 steps: every record of
+    the trajectory equals the oracle's (no guidance)."""
+    N, chains, steps = 32, 1, 10000
+    announce(f"pm1 trajectory M={M} {rule} {prec}")
+    J, scale = inputs.couplings_pm1(N, 0x5EED0001)
+    ctx = make_ctx(N, M, chains, 1, 1, prec, J, scale, rule=rule, trace_steps=steps, seed=0)
+    ctx.step_n(0, steps, 1.0, 1.0, 1)
+    rec = ctx.read_records(0, steps)
+    betas = np.ones(steps)
+    compare_trajectory(rec, J, scale, N, M, chains, 1, 1, 0, betas, rule, 0.0, exact=True)
+    e, bits, summ = ctx.measure()
+    assert summ["steps_done"] == steps
+
+
+def test_fp64_gauss_anneal_trajectory_guided():
+    """N=256, 16 chains, M=16, k in 1..4, beta 0.1 -> 3.0: records match the oracle
+    with guidance at flagged near ties only."""
+    N, M, chains, steps = 256, 16, 16, 300
+    announce("fp64 anneal trajectory")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0002)
+    ctx = make_ctx(N, M, chains, 1, 4, "fp64", J, scale, trace_steps=steps, seed=2)
+    ctx.step_n(0, steps, 0.1, 3.0, steps)
+    rec = ctx.read_records(0, steps)
+    betas = inputs.beta_schedule(0.1, 3.0, steps, 0, steps)
+    _, nforced = compare_trajectory(rec, J, scale, N, M, chains, 1, 4, 2, betas, "mcmcmc", RTOL["fp64"])
+    assert nforced <= 2
+
+
+def test_split_trajectory_guided():
+    N, M, chains, steps = 1024, 128, 4, 40
+    announce("split trajectory N=1024 M=128")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0003)
+    ctx = make_ctx(N, M, chains, 1, 128, "split_bf16", J, scale, trace_steps=steps, seed=3)
+    ctx.step_n(0, steps, 2.0, 2.0, 1)
+    rec = ctx.read_records(0, steps)
+    compare_trajectory(rec, J, scale, N, M, chains, 1, 128, 3, np.full(steps, 2.0), "mcmcmc", RTOL["split_bf16"])
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "fp64"])
+def test_headline_size_sampled_energies(prec):
+    """Full headline shape (N=1024, 256 chains x M=128, k in 1..128) in the launch
+    configuration the benchmark times: sampled chains' candidate energies against the
+    oracle, all 32768 energies finite, and a second identical run bitwise equal."""
+    N, M, chains = 1024, 128, 256
+    announce(f"headline sampled {prec}")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0003)
+    outs = []
+    for rep in range(2):
+        ctx = make_ctx(N, M, chains, 1, 128, prec, J, scale, seed=3)
+        ctx.step_n(0, 2, 2.0, 2.0, 1)
+        s = gpu_spins(ctx)
+        ctx.propose(2)
+        E = _torch_f64(chains * M)
+        ctx.score_candidates(E)
+        outs.append(E.cpu().numpy())
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+    Eg = outs[0].reshape(chains, M)
+    assert np.all(np.isfinite(Eg))
+    worst = 0.0
+    for c in (0, 97, 255):
+        _, cols = oracle_candidates(3, c, 2, N, M, 1, 128, s[c])
+        Eo = np.array([oracle.energy(J, scale, x) for x in cols])
+        np.testing.assert_allclose(Eg[c], Eo, rtol=RTOL[prec])
+        worst = max(worst, float(np.max(np.abs(Eg[c] - Eo) / np.abs(Eo))))
+    print(f"max rel energy error ({prec}): {worst:.3e}")
+
+
+def test_large_shape_sampled_energies():
+    """N=8192, 32 chains x M=1024, 256-spin flip sets, split path: sampled energies."""
+    N, M, chains = 8192, 1024, 32
+    announce("large N=8192 sampled")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0005)
+    ctx = make_ctx(N, M, chains, 256, 256, "split_bf16", J, scale, seed=5)
+    s = gpu_spins(ctx)
+    ctx.propose(0)
+    E = _torch_f64(chains * M)
+    ctx.score_candidates(E)
+    Eg = E.cpu().numpy().reshape(chains, M)
+    assert np.all(np.isfinite(Eg))
+    for c in (0, 31):
+        _, cols = oracle_candidates(5, c, 0, N, M, 256, 256, s[c])
+        for m in (0, 511, 1023):
+            Eo = oracle.energy(J, scale, cols[m])
+            assert Eg[c, m] == pytest.approx(Eo, rel=RTOL["split_bf16"])
+
+
+def test_errors_and_ordering():
+    N = 64
+    J, scale = inputs.couplings_gauss(N, 1)
+    ctx = make_ctx(N, 4, 2, 1, 2, "fp64", J, scale)
+    with pytest.raises(native.MC3Error) as ei:
+        ctx.select(0, 1.0)
+    assert ei.value.status == native.MC3_E_STATE
+    ctx.propose(0)
+    with pytest.raises(native.MC3Error):
+        ctx.select(0, 1.0)  # not scored yet
+    ctx.score_candidates()
+    with pytest.raises(native.MC3Error) as ei:
+        ctx.select(1, 1.0)  # step differs from the proposal's
+    assert ei.value.status == native.MC3_E_ARG
+    with pytest.raises(native.MC3Error) as ei:
+        ctx.select(0, float("nan"))
+    assert ei.value.status == native.MC3_E_ARG
+    ctx.select(0, 1.0)
+    ctx.step_n(1, 0, 1.0, 1.0, 1)  # zero steps is a no-op
+    Jbad = J.copy()
+    Jbad[3, 7] = np.inf
+    with pytest.raises(native.MC3Error) as ei:
+        ctx.init_couplings(Jbad, scale)
+    assert ei.value.status == native.MC3_E_NUMERIC
+
+
+def test_recompute_drift_is_small():
+    N, M, chains = 512, 32, 8
+    announce("recompute drift")
+    J, scale = inputs.couplings_gauss(N, 12)
+    for prec, bound in (("fp64", 1e-9), ("split_bf16", 1e-2)):
+        ctx = make_ctx(N, M, chains, 1, 8, prec, J, scale, seed=1)
+        ctx.step_n(0, 50, 0.5, 0.5, 1)
+        e_before, bits, _ = ctx.measure()
+        ctx.recompute()
+        e_after, _, summ = ctx.measure()
+        s = native.bits_to_spins(bits, N)
+        for c in range(chains):
+            assert e_after[c] == pytest.approx(oracle.energy(J, scale, s[c]), rel=1e-12)
+        assert summ["max_drift"] < bound
