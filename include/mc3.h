@@ -65,7 +65,7 @@ typedef enum {
     MC3_RULE_METROPOLIS = 1  /* single proposal, Metropolis rate; requires M == 1 */
 } mc3_rule;
 
-/* One SK instance and its chains.  Constraints: 2 <= N <= 8192, 1 <= M <= 4096,
+/* One SK instance and its chains.  Constraints: 2 <= N <= 8192, 1 <= M <= 4000,
  * 1 <= chains, 1 <= kmin <= kmax <= N, chains * M <= 2^24, rule METROPOLIS => M == 1. */
 typedef struct {
     int32_t N;               /* spins */
@@ -77,7 +77,7 @@ typedef struct {
     int32_t trace_steps;     /* capacity of the per-step record ring (>= 0) */
     uint64_t seed;           /* Philox key */
     uint32_t chain_base;     /* global index of chain 0 in the Philox counter */
-    uint32_t reserved;       /* must be 0 */
+    int32_t mean_steps;      /* capacity of the per-step chain-mean trace ring (>= 0) */
     double near_tie_tol;     /* selection margin below which a step is flagged; < 0 => default */
 } mc3_config;
 
@@ -112,7 +112,9 @@ mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes);
 /* Create a context on the current HIP device.  `workspace` is a device pointer of at
  * least mc3_workspace_size bytes, borrowed for the lifetime of the context; `stream`
  * is a hipStream_t (NULL = default stream), borrowed likewise.  Performs no device
- * allocation.  Validates the configuration before any HIP call. */
+ * memory allocation; creates one internal stream (default priority) and four events,
+ * used by mc3_step_n to overlap the next step's proposal with the current scoring;
+ * all work joins back into `stream`.  Validates the configuration before any HIP call. */
 mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out);
 
 /* Release the host-side context (the workspace stays the caller's). */
@@ -179,6 +181,20 @@ mc3_status mc3_read_records(mc3_ctx* ctx, uint32_t first, int32_t n, mc3_record*
 /* Synchronise and copy the candidate bitsets of the last mc3_propose into host
  * [chains][M][ceil(N/32)] uint32, and the roots into host [chains] (either may be NULL). */
 mc3_status mc3_read_candidates(mc3_ctx* ctx, uint32_t* bits, int32_t* roots);
+
+/* Synchronise and copy the chain means of steps first .. first+n-1 (still in the
+ * trace ring of capacity mean_steps) into host [n][2]: {mean over chains of the
+ * current energy after the step, mean of the node-weighted energy of the step's graph
+ * (Eq. eq_monte_carlo_graph)}.  Both means are fixed-order device reductions. */
+mc3_status mc3_read_means(mc3_ctx* ctx, uint32_t first, int32_t n, double* out);
+
+/* Measurement aid: while enabled, every scoring-kernel launch (mc3_score_candidates,
+ * mc3_step_n) is bracketed by HIP events recorded on the stream it runs on.
+ * Enabling resets the totals. */
+mc3_status mc3_timing_enable(mc3_ctx* ctx, int32_t on);
+
+/* Synchronise; total milliseconds of the timed scoring launches and their number. */
+mc3_status mc3_timing_read(mc3_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Wait for the stream; report any device error. */
 mc3_status mc3_sync(mc3_ctx* ctx);

@@ -47,72 +47,66 @@ __global__ void k_init_spins(uint32_t* __restrict__ spins, int chains, int N, in
 // ------------------------------------------------------------------- propose
 
 // One thread per (chain, edge): k_e and Floyd's k-of-N draw into the thread's own
-// LDS bitset, then a coalesced copy of the block's bitsets to `flips`.  Thread
-// (chain, edge 1) also draws the chain's root.  Dynamic LDS: blockDim.x * W words.
-__global__ void k_propose(uint32_t* __restrict__ flips, int32_t* __restrict__ roots, int chains,
-                          int M, int N, int W, int kmin, int kmax, int metropolis, Key key,
-                          uint32_t chain_base, uint32_t step) {
+// LDS bitset (row stride `stride` >= W words; W+1 where it fits, so the final copy
+// does not collide on banks), then every word written to the word-major flip array
+// flipsT[w][chain*M + e-1] (consecutive threads, consecutive addresses).  Thread
+// (chain, edge 1) also draws the chain's root.  Dynamic LDS: blockDim.x*stride words.
+__global__ void k_propose(uint32_t* __restrict__ flipsT, int32_t* __restrict__ roots, int chains, int M, int N,
+                          int W, int stride, int kmin, int kmax, int metropolis, Key key, uint32_t chain_base,
+                          uint32_t step) {
   extern __shared__ uint32_t lds_bits[];
   const int T = blockDim.x;
-  const long long g0 = (long long)blockIdx.x * T;
   const long long total = (long long)chains * M;
-  // clear this block's bitsets
-  for (int i = threadIdx.x; i < T * W; i += T) lds_bits[i] = 0u;
+  for (int i = threadIdx.x; i < T * stride; i += T) lds_bits[i] = 0u;
   __syncthreads();
-  const long long g = g0 + threadIdx.x;
-  if (g < total) {
-    const int c = (int)(g / M);
-    const uint32_t e = (uint32_t)(g % M) + 1u;
-    const uint32_t gc = chain_base + (uint32_t)c;
-    uint32_t* mine = lds_bits + (size_t)threadIdx.x * W;
-    uint4 blk = stream_block(key, kTagEdge, gc, step, e, 0u);
-    const int k = kmin + (int)randint(blk.x, (uint32_t)(kmax - kmin + 1));
-    for (int idx = 0; idx < k; ++idx) {
-      const uint32_t n = 1u + (uint32_t)idx;
-      if ((n & 3u) == 0u) blk = stream_block(key, kTagEdge, gc, step, e, n >> 2);
-      const uint32_t j = (uint32_t)(N - k + idx);
-      const uint32_t t = randint(pick(blk, n & 3u), j + 1u);
-      const uint32_t bt = mine[t >> 5] >> (t & 31u) & 1u;
-      const uint32_t pos = bt ? j : t;
-      mine[pos >> 5] |= 1u << (pos & 31u);
-    }
-    if (e == 1u) {
-      uint32_t r = 0u;
-      if (!metropolis) {
-        uint4 rb = stream_block(key, kTagRoot, gc, step, 0u, 0u);
-        r = randint(rb.x, (uint32_t)(M + 1));
-      }
-      roots[c] = (int32_t)r;
-    }
+  const long long g = (long long)blockIdx.x * T + threadIdx.x;
+  if (g >= total) return;
+  const int c = (int)(g / M);
+  const uint32_t e = (uint32_t)(g % M) + 1u;
+  const uint32_t gc = chain_base + (uint32_t)c;
+  uint32_t* mine = lds_bits + (size_t)threadIdx.x * stride;
+  uint4 blk = stream_block(key, kTagEdge, gc, step, e, 0u);
+  const int k = kmin + (int)randint(blk.x, (uint32_t)(kmax - kmin + 1));
+  for (int idx = 0; idx < k; ++idx) {
+    const uint32_t n = 1u + (uint32_t)idx;
+    if ((n & 3u) == 0u) blk = stream_block(key, kTagEdge, gc, step, e, n >> 2);
+    const uint32_t j = (uint32_t)(N - k + idx);
+    const uint32_t t = randint(pick(blk, n & 3u), j + 1u);
+    const uint32_t bt = mine[t >> 5] >> (t & 31u) & 1u;
+    const uint32_t pos = bt ? j : t;
+    mine[pos >> 5] |= 1u << (pos & 31u);
   }
-  __syncthreads();
-  const long long nthreads = (total - g0) < T ? (total - g0) : T;
-  const long long words = nthreads * W;
-  uint32_t* dst = flips + g0 * W;
-  for (long long i = threadIdx.x; i < words; i += T) dst[i] = lds_bits[i];
+  if (e == 1u) {
+    uint32_t r = 0u;
+    if (!metropolis) {
+      uint4 rb = stream_block(key, kTagRoot, gc, step, 0u, 0u);
+      r = randint(rb.x, (uint32_t)(M + 1));
+    }
+    roots[c] = (int32_t)r;
+  }
+  for (int w = 0; w < W; ++w) flipsT[(size_t)w * total + g] = mine[w];
 }
 
 // Candidate column m of chain c is node v = m (m < r) or m + 1 (m >= r).  Its bitset
 // is s ^ D_v with D_v = F_v (r = 0), F_r (v = 0, r >= 1) or F_r ^ F_v (r >= 1).
-// Grid: x over columns (coalesced stores), y over words.
+// Grid: x over columns (coalesced loads of flipsT and stores of candT), y over words.
 __global__ void k_build_candidates(uint32_t* __restrict__ candT, const uint32_t* __restrict__ spins,
-                                   const uint32_t* __restrict__ flips, const int32_t* __restrict__ roots,
+                                   const uint32_t* __restrict__ flipsT, const int32_t* __restrict__ roots,
                                    int chains, int M, int W, int Bp) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y;
   if (col >= Bp || w >= W) return;
   uint32_t out = 0u;
-  if (col < chains * M) {
+  const int B = chains * M;
+  if (col < B) {
     const int c = col / M, m = col % M;
     const int r = roots[c];
     const int v = m < r ? m : m + 1;
-    const uint32_t s = spins[(size_t)c * W + w];
-    const uint32_t* fc = flips + (size_t)c * M * W;
-    uint32_t d;
-    if (r == 0) d = fc[(size_t)(v - 1) * W + w];
-    else if (v == 0) d = fc[(size_t)(r - 1) * W + w];
-    else d = fc[(size_t)(r - 1) * W + w] ^ fc[(size_t)(v - 1) * W + w];
-    out = s ^ d;
+    const uint32_t* fw = flipsT + (size_t)w * B + (size_t)c * M;
+    uint32_t d = 0u;
+    if (r != 0) d = fw[r - 1];
+    if (v != 0) d ^= fw[v - 1];
+    out = spins[(size_t)c * W + w] ^ d;
   }
   candT[(size_t)w * Bp + col] = out;
 }
@@ -173,15 +167,76 @@ __global__ void k_pack_split(uint4* __restrict__ Apack, const double* __restrict
 
 // ------------------------------------------------------------------- split scoring
 
-// Expand 8 spin bits (set = -1) into 8 bfloat16 values +-1 (0x3F80 | bit << 15).
+// Expand 8 spin bits (set = -1) into 8 bfloat16 values +-1 (0x3F80 | bit << 15):
+// register p holds elements 2p (low half) and 2p+1 (high half).
 __device__ __forceinline__ bf16x8 spins_to_bf16(uint32_t byte) {
   union { uint32_t u[4]; bf16x8 v; } r;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const uint32_t x = (byte >> (2 * p)) & 3u;
-    r.u[p] = ((x * 0x40008000u) & 0x80008000u) | 0x3F803F80u;
-  }
+  for (int p = 0; p < 4; ++p)
+    r.u[p] = ((byte << (30 - 2 * p)) & 0x80000000u) | ((byte << (15 - 2 * p)) & 0x00008000u) | 0x3F803F80u;
   return r.v;
+}
+
+// Asynchronous copy of 16 bytes per lane from global memory straight into LDS:
+// lane l's bytes land at lds_base + 16 l (lds_base must be wave-uniform).
+__device__ __forceinline__ void lds_dma16(const uint4* gsrc, uint4* lds_base) {
+  __builtin_amdgcn_global_load_lds((const void*)gsrc,
+                                   (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+}
+
+// Asynchronous copy of 4 bytes per lane from global memory straight into LDS:
+// lane l's word lands at lds_base + 4 l.
+__device__ __forceinline__ void lds_dma4(const uint32_t* gsrc, uint32_t* lds_base) {
+  __builtin_amdgcn_global_load_lds((const void*)gsrc,
+                                   (__attribute__((address_space(3))) void*)lds_base, 4, 0, 0);
+}
+
+// LDS stage of the split scoring loop: six A fragments per wave (its row fragment)
+// and one spin-bit word per column of the tile.
+template <int CF>
+struct SplitStage {
+  uint4 a[4][6][64];
+  uint32_t bits[4 * 32 * CF];
+};
+
+// One 32-k chunk of the split scoring loop: DMA of the next chunk (A fragments and
+// spin-bit words) into `nxt`, then 2 k-steps x 12 A fragments x CF columns of MFMAs
+// from `cur`.  Two distinct LDS stages alternate, so the compiler can see that
+// reading one never waits for the copy into the other; nothing loaded from global
+// memory is carried in registers across chunks.
+template <int CF>
+__device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitStage<CF>& cur, SplitStage<CF>& nxt,
+                                            const uint4* next_a, const uint32_t* next_bits, int lane, int wave) {
+#pragma unroll
+  for (int f = 0; f < 6; ++f) lds_dma16(next_a + f * 64, &nxt.a[wave][f][0]);
+#pragma unroll
+  for (int q = 0; q < CF / 2; ++q) lds_dma4(next_bits + 64 * q, &nxt.bits[wave * 32 * CF + 64 * q]);
+  __builtin_amdgcn_sched_barrier(0);
+  uint32_t w[CF];
+#pragma unroll
+  for (int cf = 0; cf < CF; ++cf) w[cf] = cur.bits[wave * 32 * CF + cf * 32 + (lane & 31)];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    bf16x8 b[CF];
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf) b[cf] = spins_to_bf16((w[cf] >> (16 * s + 8 * (lane >> 5))) & 0xFFu);
+    bf16x8 a[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      union { uint4 q; bf16x8 v; } x;
+      x.q = cur.a[i % 4][s * 3 + i / 4][lane];
+      a[i] = x.v;
+    }
+    // consecutive instructions update different accumulators
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+#pragma unroll
+      for (int cf = 0; cf < CF; ++cf)
+        acc[i % 4][cf] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[cf], acc[i % 4][cf], 0, 0, 0);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 }
 
 // Energies of candidate columns on the BF16 matrix cores.
@@ -189,25 +244,29 @@ __device__ __forceinline__ bf16x8 spins_to_bf16(uint32_t byte) {
 // E(c) = -scale * sum_i c_i h_i with h_i = sum_{j>i} J_ij c_j (strict upper triangle),
 // J = hi + mid + lo.  A work unit is (row-block pair p, column tile): row blocks p and
 // NB-1-p (128 rows each; their K ranges start at the block's first row, so the pair
-// costs NB+1 blocks of K whatever p is).  Four waves share the A tiles through LDS
-// (double-buffered, 32 k per stage); each wave owns 32*CF columns whose spins are
-// expanded from bitsets in registers.  The epilogue multiplies h by the column's
-// spins and sums over rows in FP64; the unit writes one FP64 value per column.
-// Units are laid out XCD-major so the blocks of one XCD share few row pairs of J.
+// costs NB+1 blocks of K whatever p is).  Four waves share the A tiles through LDS,
+// filled by direct global->LDS copies one 32-k chunk ahead (double-buffered); each
+// wave owns 32*CF columns whose spin-bit words come through LDS the same way and are
+// expanded to +-1 in registers.  The epilogue multiplies h by the column's spins and
+// sums over rows in FP64; the unit writes one FP64 value per column.  Units are laid
+// out XCD-major so the blocks of one XCD share few row pairs of J.
 template <int CF>
-__global__ __launch_bounds__(256, 1) void k_score_split(const uint4* __restrict__ Apack,
+__global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(const uint4* __restrict__ Apack,
                                                         const uint32_t* __restrict__ candT,
                                                         double* __restrict__ partial, int Np, int Bp,
                                                         int NB, int P, int CT) {
+  static_assert(CF % 2 == 0, "CF must be even (64-column spin-bit copies)");
   constexpr int TN = 4 * 32 * CF;
-  __shared__ uint4 lds[2][4][6][64];
+  __shared__ SplitStage<CF> st0;
+  __shared__ SplitStage<CF> st1;
   const int U = P * CT;
   const int per = (U + 7) / 8;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int u = xcd * per + slot;
   if (slot >= per || u >= U) return;
   const int p = u / CT, ct = u % CT;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col_w = ct * TN + wave * 32 * CF;   // first column of this wave
   const int KS = Np / 16;
 
@@ -219,7 +278,7 @@ __global__ __launch_bounds__(256, 1) void k_score_split(const uint4* __restrict_
   for (int bi = 0; bi < nblk; ++bi) {
     const int I = bi == 0 ? p : NB - 1 - p;
     const int k0 = I * kRowBlock;
-    const int nchunk = (Np - k0) / 32;
+    const int nchunk = (Np - k0) / 32;   // a multiple of 4
     f32x16 acc[4][CF];
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf)
@@ -228,48 +287,23 @@ __global__ __launch_bounds__(256, 1) void k_score_split(const uint4* __restrict_
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[rf][cf][e] = 0.0f;
 
-    // this thread stages fragment row R = 4I + wave, lane `lane`, six fragments per chunk
+    // this wave copies fragment row R = 4I + wave (six fragments per chunk) and the
+    // spin-bit words of its own columns
     const uint4* src = Apack + (((size_t)(4 * I + wave) * KS + (k0 / 16)) * 3) * 64 + lane;
-    uint4 stage[6];
+    const uint32_t* bsrc = candT + (size_t)(k0 >> 5) * Bp + col_w + lane;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) stage[f] = src[f * 64];
+    for (int f = 0; f < 6; ++f) lds_dma16(src + f * 64, &st0.a[wave][f][0]);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) lds[0][wave][f][lane] = stage[f];
+    for (int q = 0; q < CF / 2; ++q) lds_dma4(bsrc + 64 * q, &st0.bits[wave * 32 * CF + 64 * q]);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    for (int c = 0; c < nchunk; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < nchunk) {
-        const uint4* s2 = src + (size_t)(c + 1) * 6 * 64;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) stage[f] = s2[f * 64];
-      }
-      const int kw = (k0 >> 5) + c;
-      uint32_t bits[CF];
-#pragma unroll
-      for (int cf = 0; cf < CF; ++cf) bits[cf] = candT[(size_t)kw * Bp + col_w + cf * 32 + (lane & 31)];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        bf16x8 b[CF];
-#pragma unroll
-        for (int cf = 0; cf < CF; ++cf) b[cf] = spins_to_bf16((bits[cf] >> (16 * s + 8 * (lane >> 5))) & 0xFFu);
-#pragma unroll
-        for (int rf = 0; rf < 4; ++rf) {
-#pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            union { uint4 q; bf16x8 v; } a;
-            a.q = lds[buf][rf][s * 3 + t][lane];
-#pragma unroll
-            for (int cf = 0; cf < CF; ++cf)
-              acc[rf][cf] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b[cf], acc[rf][cf], 0, 0, 0);
-          }
-        }
-      }
-      if (c + 1 < nchunk) {
-#pragma unroll
-        for (int f = 0; f < 6; ++f) lds[buf ^ 1][wave][f][lane] = stage[f];
-      }
-      __syncthreads();
+    for (int c = 0; c < nchunk; c += 2) {
+      split_chunk<CF>(acc, st0, st1, src + (size_t)(c + 1) * 6 * 64, bsrc + (size_t)(c + 1) * Bp, lane, wave);
+      // past the end the copy re-reads the last chunk (in bounds; st0 is not read again
+      // before the next row block refills it after a barrier)
+      const int cn = (c + 2 < nchunk) ? c + 2 : nchunk - 1;
+      split_chunk<CF>(acc, st1, st0, src + (size_t)cn * 6 * 64, bsrc + (size_t)cn * Bp, lane, wave);
     }
     // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf + lane%32
 #pragma unroll
@@ -291,7 +325,7 @@ __global__ __launch_bounds__(256, 1) void k_score_split(const uint4* __restrict_
 #pragma unroll
   for (int cf = 0; cf < CF; ++cf) {
     const double other = __shfl_xor(part[cf], 32);
-    const double tot = (lane < 32) ? part[cf] + other : other + part[cf];
+    const double tot = part[cf] + other;
     if (lane < 32) partial[(size_t)p * Bp + col_w + cf * 32 + lane] = tot;
   }
 }
@@ -489,143 +523,200 @@ __global__ void k_column_energies(double* __restrict__ Ecol, const double* __res
 }
 
 // One wave per chain: node rule (MCMCMC) or Metropolis rate, move, record.
-// Column energies are reduced from the scoring partials here (fixed order over p) and
-// kept in Ecol for the later passes of the same lane.
+// One block of 256 threads per chain: node rule (MCMCMC) or Metropolis rate, move,
+// record, and (build_next) the next step's candidate columns.
+//   1. all threads: column energies -(scale * sum_p partial[p][col]) (fixed order over
+//      p) into the node-energy array En (LDS), the root's entry = carried energy;
+//   2. wave 0: minimum, fixed-point weights Qn (LDS), totals, threshold, prefix scan,
+//      pick, margin, weighted energy;
+//   3. all threads: the new state's bitset (the picked column of candT, or unchanged);
+//   4. build_next: candT columns of step t+1 from the new state and that step's flip
+//      sets and root (same arithmetic as k_build_candidates).  Each block touches only
+//      its own chain's columns, and reads its old columns before overwriting them.
+// Without a log-prior the largest exponent is -0, so exp(l - lmax) = exp(l) bit for
+// bit and that shift is not formed.  Dynamic LDS: 16 (M+1) + 4 W bytes.
 __global__ __launch_bounds__(256) void k_select(
-    uint32_t* __restrict__ spins, double* __restrict__ e_cur, const uint32_t* __restrict__ candT,
-    const double* __restrict__ partial, int P, double scale, double* __restrict__ Ecol,
-    const int32_t* __restrict__ roots, Record* __restrict__ ring,
-    unsigned long long* __restrict__ moves, unsigned long long* __restrict__ near_ties,
-    double* __restrict__ min_margin, int chains, int M, int W, int Bp, int metropolis, double beta,
-    double tol, Key key, uint32_t chain_base, uint32_t step, int trace_steps) {
-  const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    uint32_t* __restrict__ spins, double* __restrict__ e_cur, uint32_t* __restrict__ candT,
+    const double* __restrict__ partial, int P, double scale, const int32_t* __restrict__ roots,
+    Record* __restrict__ ring, unsigned long long* __restrict__ moves, unsigned long long* __restrict__ near_ties,
+    double* __restrict__ min_margin, double* __restrict__ e_bar_out, int chains, int M, int W, int Bp,
+    int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, int trace_steps,
+    int build_next, const uint32_t* __restrict__ flipsT_next, const int32_t* __restrict__ roots_next) {
+  extern __shared__ double sel_lds[];
+  __shared__ int sh_vstar;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = blockIdx.x;
   if (c >= chains) return;
-  const uint32_t gc = chain_base + (uint32_t)c;
-  const int r = roots[c];
+  const int nodes = M + 1;
+  double* En = sel_lds;                                                              // [nodes]
+  unsigned long long* Qn = reinterpret_cast<unsigned long long*>(sel_lds + nodes);   // [nodes]
+  uint32_t* snew = reinterpret_cast<uint32_t*>(sel_lds + 2 * (size_t)nodes);        // [W]
+  const int r = metropolis ? 0 : roots[c];
   const double ecur = e_cur[c];
-  double* Ec = Ecol + (size_t)c * M;
-  for (int m = lane; m < M; m += 64) {
+  const int B = chains * M;
+
+  // 1. node energies
+  for (int m = tid; m < M; m += 256) {
     const size_t col = (size_t)c * M + m;
     double acc = 0.0;
     for (int q = 0; q < P; ++q) acc += partial[(size_t)q * Bp + col];
-    Ec[m] = -(scale * acc);
+    En[m < r ? m : m + 1] = -(scale * acc);
   }
-  uint4 ub = stream_block(key, kTagSelect, gc, step, 0u, 0u);
-  const uint64_t u53 = u53_of(ub.x, ub.y);
+  if (tid == 0) En[r] = ecur;
+  __syncthreads();
 
-  int vstar;
-  double e_new, ebar, margin;
-  if (metropolis) {
-    const double e1 = Ec[0];
-    const double dE = e1 - ecur;
-    bool acc;
-    if (dE <= 0.0) {
-      acc = true;
-      margin = __longlong_as_double(0x7FF0000000000000ll);
-    } else {
-      const double w = exp_weight(-(beta * dE));
-      const double u = (double)u53 * 0x1.0p-53;
-      acc = u < w;
-      margin = fabs(u - w);
-    }
-    vstar = acc ? 1 : 0;
-    e_new = acc ? e1 : ecur;
-    ebar = e_new;
-  } else {
-    const int nodes = M + 1;
-    // pass 1: minimum energy over the nodes
-    double emin = __longlong_as_double(0x7FF0000000000000ll);
-    for (int v = lane; v < nodes; v += 64) {
-      const double E = (v == r) ? ecur : Ec[v < r ? v : v - 1];
-      emin = E < emin ? E : emin;
-    }
-    emin = wave_min(emin);
-    // pass 2: log-weight maximum (a no-op shift without a log-prior, kept so the
-    // exponent is formed exactly as the rule states it)
-    double lmax = -__longlong_as_double(0x7FF0000000000000ll);
-    for (int v = lane; v < nodes; v += 64) {
-      const double E = (v == r) ? ecur : Ec[v < r ? v : v - 1];
-      const double l = -(beta * (E - emin));
-      lmax = l > lmax ? l : lmax;
-    }
-    lmax = wave_max(lmax);
-    // pass 3: fixed-point weights, their total, and the weighted energy
-    unsigned long long wq = 0ull;
-    double num = 0.0, den = 0.0;
-    for (int v = lane; v < nodes; v += 64) {
-      const double E = (v == r) ? ecur : Ec[v < r ? v : v - 1];
-      const double w = exp_weight(-(beta * (E - emin)) - lmax);
-      wq += (unsigned long long)(w * 0x1.0p52);
-      num += w * E;
-      den += w;
-    }
-    const unsigned long long Wq = wave_sum_u64(wq);
-    num = wave_sum(num);
-    den = wave_sum(den);
-    ebar = num / den;
-    // threshold t = floor(u53 * W / 2^53)
-    const unsigned long long lo = (unsigned long long)u53 * Wq;
-    const unsigned long long hi = __umul64hi((unsigned long long)u53, Wq);
-    const unsigned long long t = (hi << 11) | (lo >> 53);
-    // pass 4: inclusive prefix sums in node order; first node with Q_v > t
-    unsigned long long carry = 0ull;
-    vstar = -1;
-    unsigned long long qv = 0ull, Qv = 0ull;
-    for (int base = 0; base < nodes; base += 64) {
-      const int v = base + lane;
-      unsigned long long q = 0ull;
-      if (v < nodes) {
-        const double E = (v == r) ? ecur : Ec[v < r ? v : v - 1];
-        const double w = exp_weight(-(beta * (E - emin)) - lmax);
-        q = (unsigned long long)(w * 0x1.0p52);
+  // 2. the rule (wave 0)
+  if (wave == 0) {
+    const uint32_t gc = chain_base + (uint32_t)c;
+    uint4 ub = stream_block(key, kTagSelect, gc, step, 0u, 0u);
+    const uint64_t u53 = u53_of(ub.x, ub.y);
+    int vstar;
+    double e_new, ebar, margin;
+    if (metropolis) {
+      const double e1 = En[1];
+      const double dE = e1 - ecur;
+      bool acc;
+      if (dE <= 0.0) {
+        acc = true;
+        margin = __longlong_as_double(0x7FF0000000000000ll);
+      } else {
+        const double w = exp_weight(-(beta * dE));
+        const double u = (double)u53 * 0x1.0p-53;
+        acc = u < w;
+        margin = fabs(u - w);
       }
-      const unsigned long long Q = carry + wave_scan_u64(q, lane);
-      const unsigned long long hit = __ballot(v < nodes && Q > t);
-      if (hit) {
-        const int first = __ffsll((long long)hit) - 1;
-        vstar = base + first;
-        qv = __shfl(q, first);
-        Qv = __shfl(Q, first);
-        break;
-      }
-      carry = __shfl(Q, 63);
-    }
-    if (vstar < 0) {
-      // unreachable for finite energies (the minimum-energy node has q = 2^52 > 0);
-      // stay put and report a zero margin rather than index outside the graph
-      vstar = r;
-      margin = 0.0;
+      vstar = acc ? 1 : 0;
+      e_new = acc ? e1 : ecur;
+      ebar = e_new;
     } else {
-      const unsigned long long d1 = t - (Qv - qv), d2 = Qv - t;
-      margin = (double)(d1 < d2 ? d1 : d2) / (double)Wq;
+      double emin = __longlong_as_double(0x7FF0000000000000ll);
+      for (int v = lane; v < nodes; v += 64) emin = En[v] < emin ? En[v] : emin;
+      emin = wave_min(emin);
+      // fixed-point weights, their total, and the weighted energy
+      unsigned long long wq = 0ull;
+      double num = 0.0, den = 0.0;
+      for (int v = lane; v < nodes; v += 64) {
+        const double E = En[v];
+        const double w = exp_weight(-(beta * (E - emin)));
+        const unsigned long long q = (unsigned long long)(w * 0x1.0p52);
+        Qn[v] = q;
+        wq += q;
+        num += w * E;
+        den += w;
+      }
+      const unsigned long long Wq = wave_sum_u64(wq);
+      num = wave_sum(num);
+      den = wave_sum(den);
+      ebar = num / den;
+      // threshold t = floor(u53 * W / 2^53)
+      const unsigned long long lo = (unsigned long long)u53 * Wq;
+      const unsigned long long hi = __umul64hi((unsigned long long)u53, Wq);
+      const unsigned long long t = (hi << 11) | (lo >> 53);
+      // inclusive prefix sums in node order; first node with Q_v > t
+      unsigned long long carry = 0ull;
+      vstar = -1;
+      unsigned long long qv = 0ull, Qv = 0ull;
+      for (int base = 0; base < nodes; base += 64) {
+        const int v = base + lane;
+        const unsigned long long q = (v < nodes) ? Qn[v] : 0ull;
+        const unsigned long long Q = carry + wave_scan_u64(q, lane);
+        const unsigned long long hit = __ballot(v < nodes && Q > t);
+        if (hit) {
+          const int first = __ffsll((long long)hit) - 1;
+          vstar = base + first;
+          qv = __shfl(q, first);
+          Qv = __shfl(Q, first);
+          break;
+        }
+        carry = __shfl(Q, 63);
+      }
+      if (vstar < 0) {
+        // unreachable for finite energies (the minimum-energy node has q = 2^52 > 0);
+        // stay put and report a zero margin rather than index outside the graph
+        vstar = r;
+        margin = 0.0;
+      } else {
+        const unsigned long long d1 = t - (Qv - qv), d2 = Qv - t;
+        margin = (double)(d1 < d2 ? d1 : d2) / (double)Wq;
+      }
+      e_new = En[vstar];
     }
-    e_new = (vstar == r) ? ecur : Ec[vstar < r ? vstar : vstar - 1];
-  }
-  const int cur_node = metropolis ? 0 : r;
-  const bool moved = vstar != cur_node;
-  if (moved) {
-    const int m = metropolis ? 0 : (vstar < r ? vstar : vstar - 1);
-    const int col = c * M + m;
-    for (int w = lane; w < W; w += 64) spins[(size_t)c * W + w] = candT[(size_t)w * Bp + col];
-  }
-  if (lane == 0) {
-    const bool near = margin < tol;
-    e_cur[c] = e_new;
-    moves[c] += moved ? 1ull : 0ull;
-    near_ties[c] += near ? 1ull : 0ull;
-    min_margin[c] = margin < min_margin[c] ? margin : min_margin[c];
-    if (trace_steps > 0) {
-      Record rec;
-      rec.r = metropolis ? 0 : r;
-      rec.vstar = vstar;
-      rec.e_cur = e_new;
-      rec.e_bar = ebar;
-      rec.margin = margin;
-      rec.flags = (near ? 1u : 0u) | (moved ? 2u : 0u);
-      rec.step = step;
-      ring[(size_t)(step % (uint32_t)trace_steps) * chains + c] = rec;
+    if (lane == 0) {
+      const bool moved = vstar != r;
+      const bool near = margin < tol;
+      sh_vstar = vstar;
+      e_cur[c] = e_new;
+      e_bar_out[c] = ebar;
+      moves[c] += moved ? 1ull : 0ull;
+      near_ties[c] += near ? 1ull : 0ull;
+      min_margin[c] = margin < min_margin[c] ? margin : min_margin[c];
+      if (trace_steps > 0) {
+        Record rec;
+        rec.r = r;
+        rec.vstar = vstar;
+        rec.e_cur = e_new;
+        rec.e_bar = ebar;
+        rec.margin = margin;
+        rec.flags = (near ? 1u : 0u) | (moved ? 2u : 0u);
+        rec.step = step;
+        ring[(size_t)(step % (uint32_t)trace_steps) * chains + c] = rec;
+      }
     }
+  }
+  __syncthreads();
+
+  // 3. the new state
+  const int vstar = sh_vstar;
+  const bool moved = vstar != r;
+  const int mcol = c * M + (vstar < r ? vstar : vstar - 1);
+  for (int w = tid; w < W; w += 256) {
+    const uint32_t x = moved ? candT[(size_t)w * Bp + mcol] : spins[(size_t)c * W + w];
+    snew[w] = x;
+    if (moved) spins[(size_t)c * W + w] = x;
+  }
+  if (!build_next) return;
+  __syncthreads();
+
+  // 4. candidate columns of the next step
+  const int r1 = roots_next[c];
+  for (int idx = tid; idx < M * W; idx += 256) {
+    const int w = idx / M, m = idx - (idx / M) * M;
+    const int v = m < r1 ? m : m + 1;
+    const uint32_t* fw = flipsT_next + (size_t)w * B + (size_t)c * M;
+    uint32_t d = 0u;
+    if (r1 != 0) d = fw[r1 - 1];
+    if (v != 0) d ^= fw[v - 1];
+    candT[(size_t)w * Bp + (size_t)c * M + m] = snew[w] ^ d;
+  }
+}
+
+// ------------------------------------------------------------------- means trace
+
+// Chain means of the current and node-weighted energies of this step, one block of
+// 256 threads, fixed-order tree: trace[slot] = {step, mean e_cur, mean e_bar}.
+__global__ __launch_bounds__(256) void k_chain_means(double* __restrict__ trace, const double* __restrict__ e_cur,
+                                                     const double* __restrict__ e_bar, int chains, uint32_t slot,
+                                                     uint32_t step) {
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int c = threadIdx.x; c < chains; c += 256) {
+    a += e_cur[c];
+    b += e_bar[c];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = red[0][threadIdx.x] + red[0][threadIdx.x + o];
+      red[1][threadIdx.x] = red[1][threadIdx.x] + red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    trace[3 * (size_t)slot] = (double)step;
+    trace[3 * (size_t)slot + 1] = red[0][0] / (double)chains;
+    trace[3 * (size_t)slot + 2] = red[1][0] / (double)chains;
   }
 }
 

@@ -41,8 +41,8 @@ Dims dims_of(const mc3_config& c) {
 }
 
 struct Layout {
-  size_t J64, Jpack, spins, e_cur, flips, roots, candT, partial, Ecol, ring, moves, near, minm, drift, erecomp,
-      total;
+  size_t J64, Jpack, spins, e_cur, e_bar, flips, roots, candT, partial, Ecol, ring, means, moves, near, minm, drift,
+      erecomp, total;
 };
 
 Layout layout_of(const mc3_config& c) {
@@ -61,12 +61,14 @@ Layout layout_of(const mc3_config& c) {
     L.Jpack = take((size_t)d.Np * d.Np * sizeof(double));
   L.spins = take((size_t)d.chains * d.W * 4);
   L.e_cur = take((size_t)d.chains * 8);
-  L.flips = take((size_t)d.chains * d.M * d.W * 4);
-  L.roots = take((size_t)d.chains * 4);
+  L.e_bar = take((size_t)d.chains * 8);
+  L.flips = take((size_t)2 * d.chains * d.M * d.W * 4);   // two steps (by parity)
+  L.roots = take((size_t)2 * d.chains * 4);
   L.candT = take((size_t)d.W * d.Bp * 4);
   L.partial = take((size_t)d.P * d.Bp * 8);
   L.Ecol = take((size_t)d.Bp * 8);
   L.ring = take((size_t)(c.trace_steps > 0 ? c.trace_steps : 0) * d.chains * sizeof(mc3::Record));
+  L.means = take((size_t)(c.mean_steps > 0 ? c.mean_steps : 0) * 3 * sizeof(double));
   L.moves = take((size_t)d.chains * 8);
   L.near = take((size_t)d.chains * 8);
   L.minm = take((size_t)d.chains * 8);
@@ -79,7 +81,7 @@ Layout layout_of(const mc3_config& c) {
 const char* validate(const mc3_config* c) {
   if (!c) return "config is NULL";
   if (c->N < 2 || c->N > 8192) return "N must be in [2, 8192]";
-  if (c->M < 1 || c->M > 4096) return "M must be in [1, 4096]";
+  if (c->M < 1 || c->M > 4000) return "M must be in [1, 4000]";
   if (c->chains < 1) return "chains must be >= 1";
   if ((long long)c->chains * c->M > (1ll << 24)) return "chains * M must be <= 2^24";
   if ((long long)c->chains + c->chain_base > (1ll << 28)) return "chain_base + chains must be <= 2^28";
@@ -88,7 +90,7 @@ const char* validate(const mc3_config* c) {
   if (c->rule != MC3_RULE_MCMCMC && c->rule != MC3_RULE_METROPOLIS) return "unknown rule";
   if (c->rule == MC3_RULE_METROPOLIS && c->M != 1) return "rule METROPOLIS requires M == 1";
   if (c->trace_steps < 0) return "trace_steps must be >= 0";
-  if (c->reserved != 0) return "reserved must be 0";
+  if (c->mean_steps < 0) return "mean_steps must be >= 0";
   if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
   return nullptr;
 }
@@ -101,6 +103,8 @@ struct mc3_ctx {
   Layout L;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;          // proposals of the next step run here, overlapping scoring
+  hipEvent_t ev_prop[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};
   int device = 0;
   bool have_J = false, have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
   uint32_t proposal_step = 0;
@@ -108,10 +112,19 @@ struct mc3_ctx {
   double tol = 0.0;
   int64_t steps_done = 0;
   int split_cf = 2;  // split scoring tile: 32*split_cf columns per wave (2 or 4)
+  // optional HIP-event timing of the scoring launches
+  bool timing = false;
+  std::vector<hipEvent_t> t_start, t_stop;
+  std::vector<char> t_pending;
+  size_t t_next = 0;
+  double t_total_ms = 0.0;
+  int64_t t_count = 0;
   std::string err;
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  uint32_t* flips(uint32_t step) const { return at<uint32_t>(L.flips) + (size_t)(step & 1u) * d.chains * d.M * d.W; }
+  int32_t* roots(uint32_t step) const { return at<int32_t>(L.roots) + (size_t)(step & 1u) * d.chains; }
   mc3::Key key() const { return mc3::Key{(uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32)}; }
 };
 
@@ -160,31 +173,80 @@ mc3_status launch_energy(mc3_ctx* c, double* out) {
   return check_launch(c, "energy kernel");
 }
 
-mc3_status do_propose(mc3_ctx* c, uint32_t step) {
+mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st) {
   const Dims& d = c->d;
-  const size_t wbytes = (size_t)d.W * 4;
-  int T = (int)(65536 / wbytes);
+  int stride = d.W + 1;
+  int T = (int)(65536 / ((size_t)stride * 4));
+  if (T < 64) {
+    stride = d.W;
+    T = (int)(65536 / ((size_t)stride * 4));
+  }
   if (T > 256) T = 256;
   T = (T / 64) * 64;
-  if (T < 64) T = 64;
-  const size_t lds = (size_t)T * wbytes;
+  const size_t lds = (size_t)T * stride * 4;
   const long long total = (long long)d.chains * d.M;
   const int blocks = (int)((total + T - 1) / T);
-  hipLaunchKernelGGL(mc3::k_propose, dim3(blocks), dim3(T), lds, c->stream, c->at<uint32_t>(c->L.flips),
-                     c->at<int32_t>(c->L.roots), d.chains, d.M, d.N, d.W, c->cfg.kmin, c->cfg.kmax,
-                     c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, c->key(), c->cfg.chain_base, step);
-  MC3_TRY(check_launch(c, "propose kernel"));
+  hipLaunchKernelGGL(mc3::k_propose, dim3(blocks), dim3(T), lds, st, c->flips(step), c->roots(step), d.chains, d.M,
+                     d.N, d.W, stride, c->cfg.kmin, c->cfg.kmax, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, c->key(),
+                     c->cfg.chain_base, step);
+  return check_launch(c, "propose kernel");
+}
+
+mc3_status launch_build(mc3_ctx* c, uint32_t step) {
+  const Dims& d = c->d;
   hipLaunchKernelGGL(mc3::k_build_candidates, dim3(d.Bp / 256, d.W), dim3(256), 0, c->stream,
-                     c->at<uint32_t>(c->L.candT), c->at<uint32_t>(c->L.spins), c->at<uint32_t>(c->L.flips),
-                     c->at<int32_t>(c->L.roots), d.chains, d.M, d.W, d.Bp);
-  MC3_TRY(check_launch(c, "candidate kernel"));
+                     c->at<uint32_t>(c->L.candT), c->at<uint32_t>(c->L.spins), c->flips(step), c->roots(step),
+                     d.chains, d.M, d.W, d.Bp);
+  return check_launch(c, "candidate kernel");
+}
+
+mc3_status do_propose(mc3_ctx* c, uint32_t step) {
+  MC3_TRY(launch_propose(c, step, c->stream));
+  MC3_TRY(launch_build(c, step));
   c->have_proposal = true;
   c->have_scores = false;
   c->proposal_step = step;
   return MC3_OK;
 }
 
+mc3_status timing_collect(mc3_ctx* c, size_t i) {
+  if (!c->t_pending[i]) return MC3_OK;
+  MC3_TRY(hip_ok(c, hipEventSynchronize(c->t_stop[i]), "timing sync"));
+  float ms = 0.0f;
+  MC3_TRY(hip_ok(c, hipEventElapsedTime(&ms, c->t_start[i], c->t_stop[i]), "timing read"));
+  c->t_total_ms += ms;
+  c->t_count += 1;
+  c->t_pending[i] = 0;
+  return MC3_OK;
+}
+
+mc3_status launch_score_kernel(mc3_ctx* c);
+
 mc3_status do_score(mc3_ctx* c, double* E_out) {
+  const Dims& d = c->d;
+  if (c->timing) {
+    const size_t i = c->t_next;
+    c->t_next = (c->t_next + 1) % c->t_start.size();
+    MC3_TRY(timing_collect(c, i));
+    MC3_TRY(hip_ok(c, hipEventRecord(c->t_start[i], c->stream), "timing event"));
+    MC3_TRY(launch_score_kernel(c));
+    MC3_TRY(hip_ok(c, hipEventRecord(c->t_stop[i], c->stream), "timing event"));
+    c->t_pending[i] = 1;
+  } else {
+    MC3_TRY(launch_score_kernel(c));
+  }
+  if (E_out) {
+    hipLaunchKernelGGL(mc3::k_column_energies, dim3((d.B + 255) / 256), dim3(256), 0, c->stream,
+                       c->at<double>(c->L.Ecol), c->at<const double>(c->L.partial), d.P, d.Bp, d.B, c->scale);
+    MC3_TRY(check_launch(c, "column energy kernel"));
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(E_out, c->at<double>(c->L.Ecol), (size_t)d.B * 8, hipMemcpyDeviceToDevice,
+                                     c->stream), "copy energies"));
+  }
+  c->have_scores = true;
+  return MC3_OK;
+}
+
+mc3_status launch_score_kernel(mc3_ctx* c) {
   const Dims& d = c->d;
   if (c->cfg.precision == MC3_SPLIT_BF16) {
     const int TN = 128 * c->split_cf;
@@ -206,31 +268,71 @@ mc3_status do_score(mc3_ctx* c, double* E_out) {
     hipLaunchKernelGGL(mc3::k_score_f64, dim3(grid), dim3(256), 0, c->stream, c->at<const double>(c->L.Jpack),
                        c->at<const uint32_t>(c->L.candT), c->at<double>(c->L.partial), d.Np, d.Bp, d.NB, d.P, CT);
   }
-  MC3_TRY(check_launch(c, "score kernel"));
-  if (E_out) {
-    hipLaunchKernelGGL(mc3::k_column_energies, dim3((d.B + 255) / 256), dim3(256), 0, c->stream,
-                       c->at<double>(c->L.Ecol), c->at<const double>(c->L.partial), d.P, d.Bp, d.B, c->scale);
-    MC3_TRY(check_launch(c, "column energy kernel"));
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(E_out, c->at<double>(c->L.Ecol), (size_t)d.B * 8, hipMemcpyDeviceToDevice,
-                                     c->stream), "copy energies"));
+  return check_launch(c, "score kernel");
+}
+
+// Selection of step `step`; with build_next, also the candidates of step+1 (whose
+// flip sets and roots must already be proposed).
+mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool build_next = false) {
+  const Dims& d = c->d;
+  const size_t lds = (size_t)(d.M + 1) * 16 + (size_t)d.W * 4;
+  hipLaunchKernelGGL(mc3::k_select, dim3(d.chains), dim3(256), lds, c->stream, c->at<uint32_t>(c->L.spins),
+                     c->at<double>(c->L.e_cur), c->at<uint32_t>(c->L.candT), c->at<const double>(c->L.partial), d.P,
+                     c->scale, c->roots(step), c->at<mc3::Record>(c->L.ring), c->at<unsigned long long>(c->L.moves),
+                     c->at<unsigned long long>(c->L.near), c->at<double>(c->L.minm), c->at<double>(c->L.e_bar),
+                     d.chains, d.M, d.W, d.Bp, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, beta, c->tol, c->key(),
+                     c->cfg.chain_base, step, c->cfg.trace_steps, build_next ? 1 : 0, c->flips(step + 1u),
+                     c->roots(step + 1u));
+  MC3_TRY(check_launch(c, "select kernel"));
+  if (c->cfg.mean_steps > 0) {
+    hipLaunchKernelGGL(mc3::k_chain_means, dim3(1), dim3(256), 0, c->stream, c->at<double>(c->L.means),
+                       c->at<const double>(c->L.e_cur), c->at<const double>(c->L.e_bar), d.chains,
+                       step % (uint32_t)c->cfg.mean_steps, step);
+    MC3_TRY(check_launch(c, "means kernel"));
   }
-  c->have_scores = true;
+  c->have_proposal = build_next;
+  c->have_scores = false;
+  if (build_next) c->proposal_step = step + 1u;
+  c->steps_done += 1;
   return MC3_OK;
 }
 
-mc3_status do_select(mc3_ctx* c, uint32_t step, double beta) {
-  const Dims& d = c->d;
-  hipLaunchKernelGGL(mc3::k_select, dim3((d.chains + 3) / 4), dim3(256), 0, c->stream, c->at<uint32_t>(c->L.spins),
-                     c->at<double>(c->L.e_cur), c->at<const uint32_t>(c->L.candT),
-                     c->at<const double>(c->L.partial), d.P, c->scale, c->at<double>(c->L.Ecol),
-                     c->at<const int32_t>(c->L.roots), c->at<mc3::Record>(c->L.ring),
-                     c->at<unsigned long long>(c->L.moves), c->at<unsigned long long>(c->L.near),
-                     c->at<double>(c->L.minm), d.chains, d.M, d.W, d.Bp, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0,
-                     beta, c->tol, c->key(), c->cfg.chain_base, step, c->cfg.trace_steps);
-  MC3_TRY(check_launch(c, "select kernel"));
+double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
+  if (total <= 1) return beta0;
+  return beta0 + (beta1 - beta0) * ((double)t / (double)(total - 1));
+}
+
+// n steps with the proposal of step t+1 on the auxiliary stream, overlapping the
+// scoring of step t; the selection of step t also builds the candidates of step t+1.
+// Flip sets and roots are double-buffered by step parity: propose(t+1) waits for
+// select(t-1) (the last reader of its buffers); select(t) waits for propose(t+1).
+// Everything joins back into the caller's stream.
+mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
+  if (n <= 0) return MC3_OK;
+  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[0], c->stream), "event"));
+  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[1], c->stream), "event"));
+  MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[step0 & 1u], 0), "wait"));
+  MC3_TRY(launch_propose(c, step0, c->aux));
+  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[step0 & 1u], c->aux), "event"));
+  MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_prop[step0 & 1u], 0), "wait"));
+  MC3_TRY(launch_build(c, step0));
+  c->have_proposal = true;
+  c->proposal_step = step0;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint32_t t = step0 + (uint32_t)i;
+    const bool last = i + 1 == n;
+    if (!last) {
+      const uint32_t t1 = t + 1u;
+      MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[t1 & 1u], 0), "wait"));
+      MC3_TRY(launch_propose(c, t1, c->aux));
+      MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[t1 & 1u], c->aux), "event"));
+    }
+    MC3_TRY(do_score(c, nullptr));
+    if (!last) MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_prop[(t + 1u) & 1u], 0), "wait"));
+    MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last));
+    MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[t & 1u], c->stream), "event"));
+  }
   c->have_proposal = false;
-  c->have_scores = false;
-  c->steps_done += 1;
   return MC3_OK;
 }
 
@@ -267,6 +369,15 @@ mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void
   c->ws = (char*)workspace;
   c->stream = (hipStream_t)stream;
   c->device = dev;
+  bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < 2 && ok; ++i) {
+    ok = hipEventCreateWithFlags(&c->ev_prop[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->ev_sel[i], hipEventDisableTiming) == hipSuccess;
+  }
+  if (!ok) {
+    mc3_destroy(c);
+    return MC3_E_DEVICE;
+  }
   if (const char* e = std::getenv("MC3_SPLIT_CF")) {
     if (std::strcmp(e, "4") == 0) c->split_cf = 4;
   }
@@ -280,6 +391,16 @@ mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void
 
 mc3_status mc3_destroy(mc3_ctx* ctx) {
   if (!ctx) return MC3_E_ARG;
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->ev_prop[i]) (void)hipEventDestroy(ctx->ev_prop[i]);
+    if (ctx->ev_sel[i]) (void)hipEventDestroy(ctx->ev_sel[i]);
+  }
+  for (hipEvent_t e : ctx->t_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
   delete ctx;
   return MC3_OK;
 }
@@ -354,6 +475,12 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
                                      hipMemcpyHostToDevice, c->stream), "clear ring"));
     MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
   }
+  if (c->cfg.mean_steps > 0) {
+    std::vector<double> tr((size_t)c->cfg.mean_steps * 3, -1.0);
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(c->L.means), tr.data(), tr.size() * 8, hipMemcpyHostToDevice,
+                                     c->stream), "clear means"));
+    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
+  }
   c->have_chains = true;
   c->have_proposal = c->have_scores = false;
   c->steps_done = 0;
@@ -387,15 +514,7 @@ mc3_status mc3_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, doubl
   if (n < 0 || (uint64_t)step0 + (uint64_t)n > 0x100000000ull) return fail(c, MC3_E_ARG, "bad step range");
   if (!std::isfinite(beta0) || !std::isfinite(beta1) || beta0 < 0.0 || beta1 < 0.0)
     return fail(c, MC3_E_ARG, "beta must be finite and >= 0");
-  for (int64_t i = 0; i < n; ++i) {
-    const uint32_t t = step0 + (uint32_t)i;
-    double beta = beta0;
-    if (total > 1) beta = beta0 + (beta1 - beta0) * ((double)t / (double)(total - 1));
-    MC3_TRY(do_propose(c, t));
-    MC3_TRY(do_score(c, nullptr));
-    MC3_TRY(do_select(c, t, beta));
-  }
-  return MC3_OK;
+  return do_step_n(c, step0, n, beta0, beta1, total);
 }
 
 mc3_status mc3_recompute(mc3_ctx* c) {
@@ -490,8 +609,56 @@ mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
       for (int w = 0; w < d.Wn; ++w) bits[(size_t)col * d.Wn + w] = t[(size_t)w * d.Bp + col];
   }
   if (roots)
-    MC3_TRY(hip_ok(c, hipMemcpy(roots, c->at<int32_t>(c->L.roots), (size_t)d.chains * 4, hipMemcpyDeviceToHost),
+    MC3_TRY(hip_ok(c, hipMemcpy(roots, c->roots(c->proposal_step), (size_t)d.chains * 4, hipMemcpyDeviceToHost),
                    "read roots"));
+  return MC3_OK;
+}
+
+mc3_status mc3_timing_enable(mc3_ctx* c, int32_t on) {
+  MC3_TRY(usable(c));
+  if (on && c->t_start.empty()) {
+    const size_t n = 256;
+    c->t_start.assign(n, nullptr);
+    c->t_stop.assign(n, nullptr);
+    c->t_pending.assign(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+      MC3_TRY(hip_ok(c, hipEventCreate(&c->t_start[i]), "timing events"));
+      MC3_TRY(hip_ok(c, hipEventCreate(&c->t_stop[i]), "timing events"));
+    }
+  }
+  if (on) {
+    for (size_t i = 0; i < c->t_pending.size(); ++i) c->t_pending[i] = 0;
+    c->t_total_ms = 0.0;
+    c->t_count = 0;
+  }
+  c->timing = on != 0;
+  return MC3_OK;
+}
+
+mc3_status mc3_timing_read(mc3_ctx* c, double* total_ms, int64_t* launches) {
+  MC3_TRY(usable(c));
+  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "timing sync"));
+  for (size_t i = 0; i < c->t_pending.size(); ++i) MC3_TRY(timing_collect(c, i));
+  if (total_ms) *total_ms = c->t_total_ms;
+  if (launches) *launches = c->t_count;
+  return MC3_OK;
+}
+
+mc3_status mc3_read_means(mc3_ctx* c, uint32_t first, int32_t n, double* out) {
+  MC3_TRY(usable(c));
+  if (n < 0 || !out) return fail(c, MC3_E_ARG, "bad arguments");
+  if (n > c->cfg.mean_steps) return fail(c, MC3_E_ARG, "more steps than the trace holds");
+  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_means sync"));
+  std::vector<double> buf((size_t)c->cfg.mean_steps * 3);
+  MC3_TRY(hip_ok(c, hipMemcpy(buf.data(), c->at<double>(c->L.means), buf.size() * 8, hipMemcpyDeviceToHost),
+                 "read means"));
+  for (int32_t i = 0; i < n; ++i) {
+    const uint32_t st = first + (uint32_t)i;
+    const size_t slot = st % (uint32_t)c->cfg.mean_steps;
+    if (buf[3 * slot] != (double)st) return fail(c, MC3_E_ARG, "step %u is not in the trace", st);
+    out[2 * (size_t)i] = buf[3 * slot + 1];
+    out[2 * (size_t)i + 1] = buf[3 * slot + 2];
+  }
   return MC3_OK;
 }
 

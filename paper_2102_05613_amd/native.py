@@ -28,14 +28,15 @@ STATUS_NAMES = {0: "MC3_OK", -1: "MC3_E_ARG", -3: "MC3_E_DEVICE", -4: "MC3_E_STA
 # every symbol include/mc3.h declares
 EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_couplings", "mc3_init_chains",
            "mc3_propose", "mc3_score_candidates", "mc3_select", "mc3_step_n", "mc3_recompute", "mc3_measure",
-           "mc3_read_records", "mc3_read_candidates", "mc3_sync", "mc3_last_error", "mc3_version"]
+           "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
+           "mc3_sync", "mc3_last_error", "mc3_version"]
 
 
 class Config(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("chains", ctypes.c_int32),
                 ("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("trace_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("chain_base", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("chain_base", ctypes.c_uint32), ("mean_steps", ctypes.c_int32),
                 ("near_tie_tol", ctypes.c_double)]
 
 
@@ -81,6 +82,9 @@ def lib() -> ctypes.CDLL:
     L.mc3_measure.argtypes = [vp, vp, vp, P(Summary)]
     L.mc3_read_records.argtypes = [vp, c.c_uint32, c.c_int32, vp]
     L.mc3_read_candidates.argtypes = [vp, vp, vp]
+    L.mc3_read_means.argtypes = [vp, c.c_uint32, c.c_int32, vp]
+    L.mc3_timing_enable.argtypes = [vp, c.c_int32]
+    L.mc3_timing_read.argtypes = [vp, P(c.c_double), P(c.c_int64)]
     L.mc3_sync.argtypes = [vp]
     L.mc3_last_error.argtypes = [vp]
     L.mc3_last_error.restype = c.c_char_p
@@ -94,9 +98,9 @@ def lib() -> ctypes.CDLL:
 
 def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: str = "split_bf16",
                 rule: str = "mcmcmc", trace_steps: int = 0, seed: int = 0, chain_base: int = 0,
-                near_tie_tol: float = -1.0) -> Config:
-    return Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base, 0,
-                  near_tie_tol)
+                near_tie_tol: float = -1.0, mean_steps: int = 0) -> Config:
+    return Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base,
+                  mean_steps, near_tie_tol)
 
 
 def workspace_size(cfg: Config) -> int:
@@ -190,6 +194,19 @@ class Context:
         roots = np.zeros(self.chains, dtype=np.int32)
         self._check(lib().mc3_read_candidates(self.h, bits.ctypes.data, roots.ctypes.data), "mc3_read_candidates")
         return bits, roots
+
+    def read_means(self, first: int, n: int) -> np.ndarray:
+        out = np.zeros((n, 2), dtype=np.float64)
+        self._check(lib().mc3_read_means(self.h, first, n, out.ctypes.data), "mc3_read_means")
+        return out
+
+    def timing_enable(self, on: bool = True):
+        self._check(lib().mc3_timing_enable(self.h, 1 if on else 0), "mc3_timing_enable")
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().mc3_timing_read(self.h, ctypes.byref(ms), ctypes.byref(n)), "mc3_timing_read")
+        return ms.value, n.value
 
     def sync(self):
         self._check(lib().mc3_sync(self.h), "mc3_sync")

@@ -66,7 +66,7 @@ def test_version(lib):
 
 @pytest.mark.parametrize("kw", [dict(N=1), dict(N=8193), dict(M=0), dict(chains=0), dict(kmin=0),
                                 dict(kmin=3, kmax=2), dict(kmax=65), dict(M=2, rule="metropolis"),
-                                dict(trace_steps=-1), dict(M=4097), dict(chains=70000, M=256)])
+                                dict(trace_steps=-1), dict(mean_steps=-1), dict(M=4001), dict(chains=70000, M=256)])
 def test_invalid_configs_rejected(lib, kw):
     base = dict(N=64, M=4, chains=2, kmin=1, kmax=4)
     rule = kw.pop("rule", "mcmcmc")

@@ -106,12 +106,22 @@ def test_fp64_gauss_anneal_trajectory_guided():
     N, M, chains, steps = 256, 16, 16, 300
     announce("fp64 anneal trajectory")
     J, scale = inputs.couplings_gauss(N, 0x5EED0002)
-    ctx = make_ctx(N, M, chains, 1, 4, "fp64", J, scale, trace_steps=steps, seed=2)
+    cfg = native.make_config(N, M, chains, 1, 4, precision="fp64", trace_steps=steps, seed=2, mean_steps=steps)
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    ctx.timing_enable(True)
     ctx.step_n(0, steps, 0.1, 3.0, steps)
+    ms, launches = ctx.timing_read()
+    assert launches == steps and ms > 0
     rec = ctx.read_records(0, steps)
     betas = inputs.beta_schedule(0.1, 3.0, steps, 0, steps)
-    _, nforced = compare_trajectory(rec, J, scale, N, M, chains, 1, 4, 2, betas, "mcmcmc", RTOL["fp64"])
+    ro, nforced = compare_trajectory(rec, J, scale, N, M, chains, 1, 4, 2, betas, "mcmcmc", RTOL["fp64"])
     assert nforced <= 2
+    # chain-mean trace against the oracle's per-chain records
+    means = ctx.read_means(0, steps)
+    np.testing.assert_allclose(means[:, 0], ro["rec"]["e_cur"].mean(axis=1), rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(means[:, 1], ro["rec"]["e_bar"].mean(axis=1), rtol=1e-10, atol=1e-10)
 
 
 def test_split_trajectory_guided():
