@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--thermalize-steps", type=int, default=20000)
     ap.add_argument("--cpu-chains", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-collection run: one plain 512 MiB device copy (calibrates FETCH_SIZE/WRITE_SIZE), "
+                         "then --steps split steps; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -164,6 +167,17 @@ def main():
         sys.exit(1)
     w = inputs.workload(args.workload)
     J, scale = w.couplings_matrix()
+    if args.profile:
+        src = torch.ones(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ctx = _context(w, "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax, J, scale)
+        ctx.step_n(0, args.steps, w.beta0, w.beta0, 1)
+        ctx.sync()
+        ctx.close()
+        print(json.dumps({"profile_run": True, "copy_bytes": 512 * 2 ** 20, "steps": args.steps}))
+        return
     split = _time_path(w, "split_bf16", args.steps, args.warmup, J, scale)
     fp64 = _time_path(w, "fp64", args.fp64_steps, min(args.warmup, 2), J, scale)
 

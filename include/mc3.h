@@ -140,8 +140,10 @@ mc3_status mc3_init_chains(mc3_ctx* ctx, const int8_t* spins);
  * (METROPOLIS: r = 0); for each edge e = 1..M of stream (tag 3, edge e):
  * k_e = kmin + randint(word 0, kmax-kmin+1), then Floyd's k-of-N on words 1..k_e.
  * Node configurations: r = 0: hub = s, leaf e = s^F_e; r >= 1: leaf r = s,
- * hub = s^F_r, leaf e = s^F_r^F_e.  Materialises the M non-current nodes of each
- * chain as candidate bitsets (column m of chain c is node m if m < r else m+1). */
+ * hub = s^F_r, leaf e = s^F_r^F_e.  The M non-current nodes of chain c are its
+ * candidate columns c*M + m, m = 0..M-1: column m is leaf m+1, except that for a
+ * root r >= 1 column r-1 is the hub.  Stores the flip sets, the roots and, per chain,
+ * base = s^F_r; candidates are formed from these inside the scoring kernels. */
 mc3_status mc3_propose(mc3_ctx* ctx, uint32_t step);
 
 /* Score the candidates of the last mc3_propose: E(c) = -scale sum_{i<j} J_ij c_i c_j

@@ -19,10 +19,10 @@ struct Key { uint32_t lo, hi; };
 __device__ __forceinline__ uint4 philox10(uint4 c, Key k) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint32_t a = 0xD2511F53u, b = 0xCD9E8D57u;
-    uint32_t hi0 = __umulhi(a, c.x), lo0 = a * c.x;
-    uint32_t hi1 = __umulhi(b, c.z), lo1 = b * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k.lo, lo1, hi0 ^ c.w ^ k.hi, lo0);
+    // one 32x32 -> 64-bit product per multiplier (high and low halves together)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.lo, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.hi, (uint32_t)p0);
     k.lo += 0x9E3779B9u;
     k.hi += 0xBB67AE85u;
   }

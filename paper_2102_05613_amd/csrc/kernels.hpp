@@ -1,17 +1,26 @@
 // kernels.hpp -- device kernels of the SK MCMCMC hot path (gfx950).
 //
 // Data layout in HBM (all sizes padded: Np = N rounded up to 128, W = Np/32 words
-// per spin bitset, Bp = candidate columns rounded up to the scoring tile):
+// per spin bitset, B = chains*M candidate columns, Bp = B rounded up to 512):
 //   J64     [Np][Np] double, row-major, zero outside the N x N block.
 //   Jsplit  bf16 hi/mid/lo of the strict upper triangle of J, in matrix-core
 //           fragment order: fragment (R, S, t) = rows 32R..32R+31, k = 16S..16S+15,
 //           term t, stored as 64 lanes x 8 bf16 (lane l holds row 32R + l%32,
 //           k = 16S + 8(l/32) + e for e = 0..7); 1 KiB per fragment.
 //   spins   [chains][W] uint32 bitsets (set bit = spin -1).
-//   flips   [chains][M][W] uint32 flip sets of edges 1..M.
-//   candT   [W][Bp] uint32: word w of every candidate column, columns contiguous so
-//           a matrix-core B fragment's 32 columns are one 128-byte line.
+//   flipsT  [W][Bp] uint32: word w of the flip set F_{m+1} of edge m+1 of chain c at
+//           column c*M + m (columns contiguous, so a matrix-core B fragment's 32
+//           columns are one 128-byte line); padding columns stay zero.
+//   base    [chains+1][W] uint32: s ^ F_r (s if r = 0) per chain; row `chains` is
+//           zero (used by padding columns).
 //   partial [P][Bp] double: energy contributions of row-block pair p.
+//
+// Candidate columns are never materialised on the hot path.  Column m of chain c is
+// node m+1 of the star, except that when the root r >= 1 column r-1 holds the hub
+// (node 0) instead of leaf r (the current state).  Its bitset is therefore
+// base_c ^ F_{m+1}, or base_c alone for column r-1:
+//   r = 0:  base = s, column m = s ^ F_{m+1} = leaf m+1;
+//   r >= 1: base = s ^ F_r = hub, column m = hub ^ F_{m+1} = leaf m+1, column r-1 = hub.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,13 +55,23 @@ __global__ void k_init_spins(uint32_t* __restrict__ spins, int chains, int N, in
 
 // ------------------------------------------------------------------- propose
 
+// Root position r of chain gc at `step`: randint(ROOT word 0, M+1), 0 for Metropolis.
+__device__ __forceinline__ int root_of(Key key, uint32_t gc, uint32_t step, int M, int metropolis) {
+  if (metropolis) return 0;
+  uint4 rb = stream_block(key, kTagRoot, gc, step, 0u, 0u);
+  return (int)randint(rb.x, (uint32_t)(M + 1));
+}
+
 // One thread per (chain, edge): k_e and Floyd's k-of-N draw into the thread's own
 // LDS bitset (row stride `stride` >= W words; W+1 where it fits, so the final copy
-// does not collide on banks), then every word written to the word-major flip array
-// flipsT[w][chain*M + e-1] (consecutive threads, consecutive addresses).  Thread
-// (chain, edge 1) also draws the chain's root.  Dynamic LDS: blockDim.x*stride words.
-__global__ void k_propose(uint32_t* __restrict__ flipsT, int32_t* __restrict__ roots, int chains, int M, int N,
-                          int W, int stride, int kmin, int kmax, int metropolis, Key key, uint32_t chain_base,
+// does not collide on banks), then every word written to flipsT[w][chain*M + e-1]
+// (consecutive threads, consecutive addresses).  Thread (chain, edge 1) stores the
+// chain's root.  With write_base, the thread of edge r (edge 1 if r = 0) also
+// writes base = s ^ F_r from the chain's current spins.  Dynamic LDS:
+// blockDim.x * stride words.
+__global__ void k_propose(uint32_t* __restrict__ flipsT, int32_t* __restrict__ roots, uint32_t* __restrict__ base,
+                          const uint32_t* __restrict__ spins, int write_base, int chains, int M, int N, int W, int Bp,
+                          int stride, int kmin, int kmax, int metropolis, Key key, uint32_t chain_base,
                           uint32_t step) {
   extern __shared__ uint32_t lds_bits[];
   const int T = blockDim.x;
@@ -76,39 +95,34 @@ __global__ void k_propose(uint32_t* __restrict__ flipsT, int32_t* __restrict__ r
     const uint32_t pos = bt ? j : t;
     mine[pos >> 5] |= 1u << (pos & 31u);
   }
-  if (e == 1u) {
-    uint32_t r = 0u;
-    if (!metropolis) {
-      uint4 rb = stream_block(key, kTagRoot, gc, step, 0u, 0u);
-      r = randint(rb.x, (uint32_t)(M + 1));
-    }
-    roots[c] = (int32_t)r;
+  const int r = root_of(key, gc, step, M, metropolis);
+  if (e == 1u) roots[c] = (int32_t)r;
+  for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = mine[w];
+  if (write_base && (int)e == (r == 0 ? 1 : r)) {
+    for (int w = 0; w < W; ++w) base[(size_t)c * W + w] = spins[(size_t)c * W + w] ^ (r ? mine[w] : 0u);
   }
-  for (int w = 0; w < W; ++w) flipsT[(size_t)w * total + g] = mine[w];
 }
 
-// Candidate column m of chain c is node v = m (m < r) or m + 1 (m >= r).  Its bitset
-// is s ^ D_v with D_v = F_v (r = 0), F_r (v = 0, r >= 1) or F_r ^ F_v (r >= 1).
-// Grid: x over columns (coalesced loads of flipsT and stores of candT), y over words.
-__global__ void k_build_candidates(uint32_t* __restrict__ candT, const uint32_t* __restrict__ spins,
-                                   const uint32_t* __restrict__ flipsT, const int32_t* __restrict__ roots,
-                                   int chains, int M, int W, int Bp) {
+// Bit word w of candidate column `col` (see the layout note at the top).
+__device__ __forceinline__ uint32_t column_word(const uint32_t* __restrict__ flipsT, const uint32_t* __restrict__ base,
+                                                const int32_t* __restrict__ roots, int M, int W, int Bp, int B,
+                                                int col, int w) {
+  if (col >= B) return 0u;
+  const int c = col / M, m = col - c * M;
+  const int r = roots[c];
+  const uint32_t b = base[(size_t)c * W + w];
+  return (r >= 1 && m == r - 1) ? b : (b ^ flipsT[(size_t)w * Bp + col]);
+}
+
+// Materialise the candidate bitsets candT[w][col] (inspection only; the hot path
+// scores straight from flipsT and base).  Grid: x over columns, y over words.
+__global__ void k_build_candidates(uint32_t* __restrict__ candT, const uint32_t* __restrict__ flipsT,
+                                   const uint32_t* __restrict__ base, const int32_t* __restrict__ roots, int chains,
+                                   int M, int W, int Bp) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y;
   if (col >= Bp || w >= W) return;
-  uint32_t out = 0u;
-  const int B = chains * M;
-  if (col < B) {
-    const int c = col / M, m = col % M;
-    const int r = roots[c];
-    const int v = m < r ? m : m + 1;
-    const uint32_t* fw = flipsT + (size_t)w * B + (size_t)c * M;
-    uint32_t d = 0u;
-    if (r != 0) d = fw[r - 1];
-    if (v != 0) d ^= fw[v - 1];
-    out = spins[(size_t)c * W + w] ^ d;
-  }
-  candT[(size_t)w * Bp + col] = out;
+  candT[(size_t)w * Bp + col] = column_word(flipsT, base, roots, M, W, Bp, chains * M, col, w);
 }
 
 // ------------------------------------------------------------------- split J
@@ -192,29 +206,41 @@ __device__ __forceinline__ void lds_dma4(const uint32_t* gsrc, uint32_t* lds_bas
 }
 
 // LDS stage of the split scoring loop: six A fragments per wave (its row fragment)
-// and one spin-bit word per column of the tile.
+// and, per column of the tile, the flip-set word and the chain's base word.
 template <int CF>
 struct SplitStage {
   uint4 a[4][6][64];
-  uint32_t bits[4 * 32 * CF];
+  uint32_t flip[4 * 32 * CF];
+  uint32_t base[4 * 32 * CF];
 };
 
-// One 32-k chunk of the split scoring loop: DMA of the next chunk (A fragments and
-// spin-bit words) into `nxt`, then 2 k-steps x 12 A fragments x CF columns of MFMAs
-// from `cur`.  Two distinct LDS stages alternate, so the compiler can see that
+// One 32-k chunk of the split scoring loop: DMA of the next chunk (A fragments, flip
+// words, base words) into `nxt`, then 2 k-steps x 12 A fragments x CF columns of
+// MFMAs from `cur`.  Two distinct LDS stages alternate, so the compiler can see that
 // reading one never waits for the copy into the other; nothing loaded from global
-// memory is carried in registers across chunks.
-template <int CF>
+// memory is carried in registers across chunks.  RF_LAST: row fragments rf > RF_LAST
+// of this chunk lie entirely below the diagonal (every k <= i), so their fragments
+// are zero and are neither read nor multiplied.  rootmask bit cf: this lane's column
+// of fragment cf is its chain's root column (bits = base only).
+template <int CF, int RF_LAST = 3>
 __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitStage<CF>& cur, SplitStage<CF>& nxt,
-                                            const uint4* next_a, const uint32_t* next_bits, int lane, int wave) {
+                                            const uint4* next_a, const uint32_t* next_flip,
+                                            const uint32_t* const (&next_base)[CF / 2], uint32_t rootmask, int lane,
+                                            int wave) {
 #pragma unroll
   for (int f = 0; f < 6; ++f) lds_dma16(next_a + f * 64, &nxt.a[wave][f][0]);
 #pragma unroll
-  for (int q = 0; q < CF / 2; ++q) lds_dma4(next_bits + 64 * q, &nxt.bits[wave * 32 * CF + 64 * q]);
+  for (int q = 0; q < CF / 2; ++q) {
+    lds_dma4(next_flip + 64 * q, &nxt.flip[wave * 32 * CF + 64 * q]);
+    lds_dma4(next_base[q], &nxt.base[wave * 32 * CF + 64 * q]);
+  }
   __builtin_amdgcn_sched_barrier(0);
   uint32_t w[CF];
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) w[cf] = cur.bits[wave * 32 * CF + cf * 32 + (lane & 31)];
+  for (int cf = 0; cf < CF; ++cf) {
+    const int j = wave * 32 * CF + cf * 32 + (lane & 31);
+    w[cf] = cur.base[j] ^ (((rootmask >> cf) & 1u) ? 0u : cur.flip[j]);
+  }
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     bf16x8 b[CF];
@@ -223,6 +249,7 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
     bf16x8 a[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
+      if (i % 4 > RF_LAST) continue;
       union { uint4 q; bf16x8 v; } x;
       x.q = cur.a[i % 4][s * 3 + i / 4][lane];
       a[i] = x.v;
@@ -230,6 +257,7 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
     // consecutive instructions update different accumulators
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
+      if (i % 4 > RF_LAST) continue;
 #pragma unroll
       for (int cf = 0; cf < CF; ++cf)
         acc[i % 4][cf] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[cf], acc[i % 4][cf], 0, 0, 0);
@@ -246,16 +274,17 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
 // NB-1-p (128 rows each; their K ranges start at the block's first row, so the pair
 // costs NB+1 blocks of K whatever p is).  Four waves share the A tiles through LDS,
 // filled by direct global->LDS copies one 32-k chunk ahead (double-buffered); each
-// wave owns 32*CF columns whose spin-bit words come through LDS the same way and are
-// expanded to +-1 in registers.  The epilogue multiplies h by the column's spins and
-// sums over rows in FP64; the unit writes one FP64 value per column.  Units are laid
-// out XCD-major so the blocks of one XCD share few row pairs of J.
+// wave owns 32*CF columns whose flip-set and base words come through LDS the same way
+// and are combined and expanded to +-1 in registers.  The epilogue multiplies h by
+// the column's spins and sums over rows in FP64; the unit writes one FP64 value per
+// column.  Units are laid out XCD-major so the blocks of one XCD share few row pairs
+// of J.
 template <int CF>
-__global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(const uint4* __restrict__ Apack,
-                                                        const uint32_t* __restrict__ candT,
-                                                        double* __restrict__ partial, int Np, int Bp,
-                                                        int NB, int P, int CT) {
-  static_assert(CF % 2 == 0, "CF must be even (64-column spin-bit copies)");
+__global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
+    const uint4* __restrict__ Apack, const uint32_t* __restrict__ flipsT, const uint32_t* __restrict__ base,
+    const int32_t* __restrict__ roots, double* __restrict__ partial, int chains, int M, int Np, int Bp, int NB, int P,
+    int CT) {
+  static_assert(CF % 2 == 0, "CF must be even (64-column copies)");
   constexpr int TN = 4 * 32 * CF;
   __shared__ SplitStage<CF> st0;
   __shared__ SplitStage<CF> st1;
@@ -269,6 +298,25 @@ __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(const ui
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col_w = ct * TN + wave * 32 * CF;   // first column of this wave
   const int KS = Np / 16;
+  const int W = Np / 32;
+  const int B = chains * M;
+
+  // per-lane column data: base rows of the copied columns, root-column mask
+  const uint32_t* brow[CF / 2];
+#pragma unroll
+  for (int q = 0; q < CF / 2; ++q) {
+    const int col = col_w + 64 * q + lane;
+    brow[q] = base + (size_t)(col < B ? col / M : chains) * W;
+  }
+  uint32_t rootmask = 0u;
+#pragma unroll
+  for (int cf = 0; cf < CF; ++cf) {
+    const int col = col_w + cf * 32 + (lane & 31);
+    if (col < B) {
+      const int c = col / M, r = roots[c];
+      if (r >= 1 && col - c * M == r - 1) rootmask |= 1u << cf;
+    }
+  }
 
   double part[CF];
 #pragma unroll
@@ -278,6 +326,7 @@ __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(const ui
   for (int bi = 0; bi < nblk; ++bi) {
     const int I = bi == 0 ? p : NB - 1 - p;
     const int k0 = I * kRowBlock;
+    const int kw0 = k0 >> 5;
     const int nchunk = (Np - k0) / 32;   // a multiple of 4
     f32x16 acc[4][CF];
 #pragma unroll
@@ -288,29 +337,61 @@ __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(const ui
         for (int e = 0; e < 16; ++e) acc[rf][cf][e] = 0.0f;
 
     // this wave copies fragment row R = 4I + wave (six fragments per chunk) and the
-    // spin-bit words of its own columns
+    // flip/base words of its own columns
     const uint4* src = Apack + (((size_t)(4 * I + wave) * KS + (k0 / 16)) * 3) * 64 + lane;
-    const uint32_t* bsrc = candT + (size_t)(k0 >> 5) * Bp + col_w + lane;
+    const uint32_t* fsrc = flipsT + (size_t)kw0 * Bp + col_w + lane;
+    const uint32_t* bsrc[CF / 2];
+#pragma unroll
+    for (int q = 0; q < CF / 2; ++q) bsrc[q] = brow[q] + kw0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) lds_dma16(src + f * 64, &st0.a[wave][f][0]);
 #pragma unroll
-    for (int q = 0; q < CF / 2; ++q) lds_dma4(bsrc + 64 * q, &st0.bits[wave * 32 * CF + 64 * q]);
+    for (int q = 0; q < CF / 2; ++q) {
+      lds_dma4(fsrc + 64 * q, &st0.flip[wave * 32 * CF + 64 * q]);
+      lds_dma4(bsrc[q], &st0.base[wave * 32 * CF + 64 * q]);
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    for (int c = 0; c < nchunk; c += 2) {
-      split_chunk<CF>(acc, st0, st1, src + (size_t)(c + 1) * 6 * 64, bsrc + (size_t)(c + 1) * Bp, lane, wave);
-      // past the end the copy re-reads the last chunk (in bounds; st0 is not read again
-      // before the next row block refills it after a barrier)
-      const int cn = (c + 2 < nchunk) ? c + 2 : nchunk - 1;
-      split_chunk<CF>(acc, st1, st0, src + (size_t)cn * 6 * 64, bsrc + (size_t)cn * Bp, lane, wave);
+    // chunk c of this row block: A at src + 6*64 c, flip words at fsrc + Bp c, base
+    // words at bsrc + c.  The first four chunks cover the diagonal block: chunk c needs
+    // row fragments 0..c (nchunk is a multiple of 4; past the end a copy re-reads the
+    // last chunk, which is in bounds and not read again before the next row block
+    // refills the stage after a barrier).
+#define MC3_NEXT(cn)                                                                 \
+  const uint32_t* nb##cn[CF / 2];                                                    \
+  _Pragma("unroll") for (int q = 0; q < CF / 2; ++q) nb##cn[q] = bsrc[q] + (cn);
+    {
+      const int c1 = 1, c2 = 2;
+      const int c3 = 3 < nchunk - 1 ? 3 : nchunk - 1;
+      const int c4 = 4 < nchunk - 1 ? 4 : nchunk - 1;
+      MC3_NEXT(c1)
+      split_chunk<CF, 0>(acc, st0, st1, src + (size_t)c1 * 6 * 64, fsrc + (size_t)c1 * Bp, nbc1, rootmask, lane, wave);
+      MC3_NEXT(c2)
+      split_chunk<CF, 1>(acc, st1, st0, src + (size_t)c2 * 6 * 64, fsrc + (size_t)c2 * Bp, nbc2, rootmask, lane, wave);
+      MC3_NEXT(c3)
+      split_chunk<CF, 2>(acc, st0, st1, src + (size_t)c3 * 6 * 64, fsrc + (size_t)c3 * Bp, nbc3, rootmask, lane, wave);
+      MC3_NEXT(c4)
+      split_chunk<CF, 3>(acc, st1, st0, src + (size_t)c4 * 6 * 64, fsrc + (size_t)c4 * Bp, nbc4, rootmask, lane, wave);
     }
+    for (int c = 4; c < nchunk; c += 2) {
+      const int ca = c + 1;
+      const int cb = (c + 2 < nchunk) ? c + 2 : nchunk - 1;
+      MC3_NEXT(ca)
+      split_chunk<CF>(acc, st0, st1, src + (size_t)ca * 6 * 64, fsrc + (size_t)ca * Bp, nbca, rootmask, lane, wave);
+      MC3_NEXT(cb)
+      split_chunk<CF>(acc, st1, st0, src + (size_t)cb * 6 * 64, fsrc + (size_t)cb * Bp, nbcb, rootmask, lane, wave);
+    }
+#undef MC3_NEXT
     // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf + lane%32
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf) {
 #pragma unroll
       for (int cf = 0; cf < CF; ++cf) {
-        const uint32_t rb = candT[(size_t)(4 * I + rf) * Bp + col_w + cf * 32 + (lane & 31)];
+        const int col = col_w + cf * 32 + (lane & 31);
+        const int rw = 4 * I + rf;
+        const uint32_t bw = col < B ? base[(size_t)(col / M) * W + rw] : 0u;
+        const uint32_t rb = ((rootmask >> cf) & 1u) ? bw : (bw ^ flipsT[(size_t)rw * Bp + col]);
         double sum = 0.0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -357,9 +438,11 @@ __global__ void k_pack_f64(double* __restrict__ Apack, const double* __restrict_
 // Output layout of the 16x16x4 f64 instruction: C[i][j] is element i/4 of lane
 // j + 16 (i % 4).
 __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__ Apack,
-                                                      const uint32_t* __restrict__ candT,
-                                                      double* __restrict__ partial, int Np, int Bp,
-                                                      int NB, int P, int CT) {
+                                                      const uint32_t* __restrict__ flipsT,
+                                                      const uint32_t* __restrict__ base,
+                                                      const int32_t* __restrict__ roots,
+                                                      double* __restrict__ partial, int chains, int M, int Np,
+                                                      int Bp, int NB, int P, int CT) {
   constexpr int TN = 128;
   __shared__ double lds[2][8][4][64];
   const int U = P * CT;
@@ -372,7 +455,22 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__
   const int wr = wave >> 1, wc = wave & 1;
   const int col_w = ct * TN + wc * 64;
   const int KS = Np / 4;
+  const int W = Np / 32;
+  const int B = chains * M;
   const double one = 1.0;
+  // per-lane column data: base row and root-column flag of the 4 columns of this lane
+  const uint32_t* brow[4];
+  bool isroot[4];
+#pragma unroll
+  for (int cf = 0; cf < 4; ++cf) {
+    const int col = col_w + cf * 16 + (lane & 15);
+    brow[cf] = base + (size_t)(col < B ? col / M : chains) * W;
+    isroot[cf] = false;
+    if (col < B) {
+      const int c = col / M, r = roots[c];
+      isroot[cf] = r >= 1 && col - c * M == r - 1;
+    }
+  }
 
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int nblk = (p == NB - 1 - p) ? 1 : 2;
@@ -407,7 +505,11 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__
       const int kbase = k0 + 16 * c;
       uint32_t bw[4];
 #pragma unroll
-      for (int cf = 0; cf < 4; ++cf) bw[cf] = candT[(size_t)(kbase >> 5) * Bp + col_w + cf * 16 + (lane & 15)];
+      for (int cf = 0; cf < 4; ++cf) {
+        const int kw = kbase >> 5;
+        const uint32_t b0 = brow[cf][kw];
+        bw[cf] = isroot[cf] ? b0 : (b0 ^ flipsT[(size_t)kw * Bp + col_w + cf * 16 + (lane & 15)]);
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         double b[4];
@@ -437,7 +539,9 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__
       const int row0 = k0 + wr * 64 + rf * 16;
 #pragma unroll
       for (int cf = 0; cf < 4; ++cf) {
-        const uint32_t rb = candT[(size_t)(row0 >> 5) * Bp + col_w + cf * 16 + (lane & 15)];
+        const int rw = row0 >> 5;
+        const uint32_t b0 = brow[cf][rw];
+        const uint32_t rb = isroot[cf] ? b0 : (b0 ^ flipsT[(size_t)rw * Bp + col_w + cf * 16 + (lane & 15)]);
         double sum = 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -524,24 +628,26 @@ __global__ void k_column_energies(double* __restrict__ Ecol, const double* __res
 
 // One wave per chain: node rule (MCMCMC) or Metropolis rate, move, record.
 // One block of 256 threads per chain: node rule (MCMCMC) or Metropolis rate, move,
-// record, and (build_next) the next step's candidate columns.
+// record, and (next_base) the base words of step t+1.
 //   1. all threads: column energies -(scale * sum_p partial[p][col]) (fixed order over
-//      p) into the node-energy array En (LDS), the root's entry = carried energy;
+//      p) into the node-energy array En (LDS) at their node (column m is node m+1,
+//      or the hub for column r-1), the root's entry = carried energy;
 //   2. wave 0: minimum, fixed-point weights Qn (LDS), totals, threshold, prefix scan,
 //      pick, margin, weighted energy;
-//   3. all threads: the new state's bitset (the picked column of candT, or unchanged);
-//   4. build_next: candT columns of step t+1 from the new state and that step's flip
-//      sets and root (same arithmetic as k_build_candidates).  Each block touches only
-//      its own chain's columns, and reads its old columns before overwriting them.
+//   3. all threads: the new state's bitset, base ^ F_{v*} (base alone for the hub),
+//      or unchanged;
+//   4. next_base: base of step t+1 = new state ^ F_{r'} of that step's root r'.
 // Without a log-prior the largest exponent is -0, so exp(l - lmax) = exp(l) bit for
 // bit and that shift is not formed.  Dynamic LDS: 16 (M+1) + 4 W bytes.
 __global__ __launch_bounds__(256) void k_select(
-    uint32_t* __restrict__ spins, double* __restrict__ e_cur, uint32_t* __restrict__ candT,
-    const double* __restrict__ partial, int P, double scale, const int32_t* __restrict__ roots,
+    uint32_t* __restrict__ spins, double* __restrict__ e_cur, const uint32_t* __restrict__ flipsT,
+    const uint32_t* __restrict__ base, const double* __restrict__ partial, int P, double scale,
+    const int32_t* __restrict__ roots,
     Record* __restrict__ ring, unsigned long long* __restrict__ moves, unsigned long long* __restrict__ near_ties,
     double* __restrict__ min_margin, double* __restrict__ e_bar_out, int chains, int M, int W, int Bp,
     int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, int trace_steps,
-    int build_next, const uint32_t* __restrict__ flipsT_next, const int32_t* __restrict__ roots_next) {
+    int next_base, const uint32_t* __restrict__ flipsT_next, const int32_t* __restrict__ roots_next,
+    uint32_t* __restrict__ base_next) {
   extern __shared__ double sel_lds[];
   __shared__ int sh_vstar;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -553,14 +659,13 @@ __global__ __launch_bounds__(256) void k_select(
   uint32_t* snew = reinterpret_cast<uint32_t*>(sel_lds + 2 * (size_t)nodes);        // [W]
   const int r = metropolis ? 0 : roots[c];
   const double ecur = e_cur[c];
-  const int B = chains * M;
 
   // 1. node energies
   for (int m = tid; m < M; m += 256) {
     const size_t col = (size_t)c * M + m;
     double acc = 0.0;
     for (int q = 0; q < P; ++q) acc += partial[(size_t)q * Bp + col];
-    En[m < r ? m : m + 1] = -(scale * acc);
+    En[(r >= 1 && m == r - 1) ? 0 : m + 1] = -(scale * acc);
   }
   if (tid == 0) En[r] = ecur;
   __syncthreads();
@@ -668,25 +773,26 @@ __global__ __launch_bounds__(256) void k_select(
   // 3. the new state
   const int vstar = sh_vstar;
   const bool moved = vstar != r;
-  const int mcol = c * M + (vstar < r ? vstar : vstar - 1);
   for (int w = tid; w < W; w += 256) {
-    const uint32_t x = moved ? candT[(size_t)w * Bp + mcol] : spins[(size_t)c * W + w];
+    uint32_t x;
+    if (moved) {
+      x = base[(size_t)c * W + w];
+      if (vstar >= 1) x ^= flipsT[(size_t)w * Bp + (size_t)c * M + (vstar - 1)];
+      spins[(size_t)c * W + w] = x;
+    } else {
+      x = spins[(size_t)c * W + w];
+    }
     snew[w] = x;
-    if (moved) spins[(size_t)c * W + w] = x;
   }
-  if (!build_next) return;
+  if (!next_base) return;
   __syncthreads();
 
-  // 4. candidate columns of the next step
+  // 4. base of the next step
   const int r1 = roots_next[c];
-  for (int idx = tid; idx < M * W; idx += 256) {
-    const int w = idx / M, m = idx - (idx / M) * M;
-    const int v = m < r1 ? m : m + 1;
-    const uint32_t* fw = flipsT_next + (size_t)w * B + (size_t)c * M;
-    uint32_t d = 0u;
-    if (r1 != 0) d = fw[r1 - 1];
-    if (v != 0) d ^= fw[v - 1];
-    candT[(size_t)w * Bp + (size_t)c * M + m] = snew[w] ^ d;
+  for (int w = tid; w < W; w += 256) {
+    uint32_t x = snew[w];
+    if (r1 >= 1) x ^= flipsT_next[(size_t)w * Bp + (size_t)c * M + (r1 - 1)];
+    base_next[(size_t)c * W + w] = x;
   }
 }
 

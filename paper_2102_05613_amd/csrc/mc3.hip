@@ -41,8 +41,8 @@ Dims dims_of(const mc3_config& c) {
 }
 
 struct Layout {
-  size_t J64, Jpack, spins, e_cur, e_bar, flips, roots, candT, partial, Ecol, ring, means, moves, near, minm, drift,
-      erecomp, total;
+  size_t J64, Jpack, spins, e_cur, e_bar, flips, roots, base, candT, partial, Ecol, ring, means, moves, near, minm,
+      drift, erecomp, total;
 };
 
 Layout layout_of(const mc3_config& c) {
@@ -62,8 +62,9 @@ Layout layout_of(const mc3_config& c) {
   L.spins = take((size_t)d.chains * d.W * 4);
   L.e_cur = take((size_t)d.chains * 8);
   L.e_bar = take((size_t)d.chains * 8);
-  L.flips = take((size_t)2 * d.chains * d.M * d.W * 4);   // two steps (by parity)
+  L.flips = take((size_t)2 * d.W * d.Bp * 4);           // two steps (by parity)
   L.roots = take((size_t)2 * d.chains * 4);
+  L.base = take((size_t)2 * (d.chains + 1) * d.W * 4);
   L.candT = take((size_t)d.W * d.Bp * 4);
   L.partial = take((size_t)d.P * d.Bp * 8);
   L.Ecol = take((size_t)d.Bp * 8);
@@ -123,8 +124,9 @@ struct mc3_ctx {
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  uint32_t* flips(uint32_t step) const { return at<uint32_t>(L.flips) + (size_t)(step & 1u) * d.chains * d.M * d.W; }
+  uint32_t* flips(uint32_t step) const { return at<uint32_t>(L.flips) + (size_t)(step & 1u) * d.W * d.Bp; }
   int32_t* roots(uint32_t step) const { return at<int32_t>(L.roots) + (size_t)(step & 1u) * d.chains; }
+  uint32_t* base(uint32_t step) const { return at<uint32_t>(L.base) + (size_t)(step & 1u) * (d.chains + 1) * d.W; }
   mc3::Key key() const { return mc3::Key{(uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32)}; }
 };
 
@@ -173,7 +175,7 @@ mc3_status launch_energy(mc3_ctx* c, double* out) {
   return check_launch(c, "energy kernel");
 }
 
-mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st) {
+mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st, bool write_base) {
   const Dims& d = c->d;
   int stride = d.W + 1;
   int T = (int)(65536 / ((size_t)stride * 4));
@@ -186,23 +188,15 @@ mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st) {
   const size_t lds = (size_t)T * stride * 4;
   const long long total = (long long)d.chains * d.M;
   const int blocks = (int)((total + T - 1) / T);
-  hipLaunchKernelGGL(mc3::k_propose, dim3(blocks), dim3(T), lds, st, c->flips(step), c->roots(step), d.chains, d.M,
-                     d.N, d.W, stride, c->cfg.kmin, c->cfg.kmax, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, c->key(),
+  hipLaunchKernelGGL(mc3::k_propose, dim3(blocks), dim3(T), lds, st, c->flips(step), c->roots(step), c->base(step),
+                     c->at<const uint32_t>(c->L.spins), write_base ? 1 : 0, d.chains, d.M, d.N, d.W, d.Bp, stride,
+                     c->cfg.kmin, c->cfg.kmax, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, c->key(),
                      c->cfg.chain_base, step);
   return check_launch(c, "propose kernel");
 }
 
-mc3_status launch_build(mc3_ctx* c, uint32_t step) {
-  const Dims& d = c->d;
-  hipLaunchKernelGGL(mc3::k_build_candidates, dim3(d.Bp / 256, d.W), dim3(256), 0, c->stream,
-                     c->at<uint32_t>(c->L.candT), c->at<uint32_t>(c->L.spins), c->flips(step), c->roots(step),
-                     d.chains, d.M, d.W, d.Bp);
-  return check_launch(c, "candidate kernel");
-}
-
 mc3_status do_propose(mc3_ctx* c, uint32_t step) {
-  MC3_TRY(launch_propose(c, step, c->stream));
-  MC3_TRY(launch_build(c, step));
+  MC3_TRY(launch_propose(c, step, c->stream, true));
   c->have_proposal = true;
   c->have_scores = false;
   c->proposal_step = step;
@@ -248,41 +242,43 @@ mc3_status do_score(mc3_ctx* c, double* E_out) {
 
 mc3_status launch_score_kernel(mc3_ctx* c) {
   const Dims& d = c->d;
+  const uint32_t t = c->proposal_step;
   if (c->cfg.precision == MC3_SPLIT_BF16) {
     const int TN = 128 * c->split_cf;
     const int CT = d.Bp / TN;
     const int U = d.P * CT;
     const int grid = 8 * ((U + 7) / 8);
     if (c->split_cf == 4)
-      hipLaunchKernelGGL(mc3::k_score_split<4>, dim3(grid), dim3(256), 0, c->stream,
-                         c->at<const uint4>(c->L.Jpack), c->at<const uint32_t>(c->L.candT),
-                         c->at<double>(c->L.partial), d.Np, d.Bp, d.NB, d.P, CT);
+      hipLaunchKernelGGL(mc3::k_score_split<4>, dim3(grid), dim3(256), 0, c->stream, c->at<const uint4>(c->L.Jpack),
+                         c->flips(t), c->base(t), c->roots(t), c->at<double>(c->L.partial), d.chains, d.M, d.Np,
+                         d.Bp, d.NB, d.P, CT);
     else
-      hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(256), 0, c->stream,
-                         c->at<const uint4>(c->L.Jpack), c->at<const uint32_t>(c->L.candT),
-                         c->at<double>(c->L.partial), d.Np, d.Bp, d.NB, d.P, CT);
+      hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(256), 0, c->stream, c->at<const uint4>(c->L.Jpack),
+                         c->flips(t), c->base(t), c->roots(t), c->at<double>(c->L.partial), d.chains, d.M, d.Np,
+                         d.Bp, d.NB, d.P, CT);
   } else {
     const int CT = d.Bp / 128;
     const int U = d.P * CT;
     const int grid = 8 * ((U + 7) / 8);
     hipLaunchKernelGGL(mc3::k_score_f64, dim3(grid), dim3(256), 0, c->stream, c->at<const double>(c->L.Jpack),
-                       c->at<const uint32_t>(c->L.candT), c->at<double>(c->L.partial), d.Np, d.Bp, d.NB, d.P, CT);
+                       c->flips(t), c->base(t), c->roots(t), c->at<double>(c->L.partial), d.chains, d.M, d.Np, d.Bp,
+                       d.NB, d.P, CT);
   }
   return check_launch(c, "score kernel");
 }
 
-// Selection of step `step`; with build_next, also the candidates of step+1 (whose
+// Selection of step `step`; with next_base, also the base words of step+1 (whose
 // flip sets and roots must already be proposed).
-mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool build_next = false) {
+mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = false) {
   const Dims& d = c->d;
   const size_t lds = (size_t)(d.M + 1) * 16 + (size_t)d.W * 4;
   hipLaunchKernelGGL(mc3::k_select, dim3(d.chains), dim3(256), lds, c->stream, c->at<uint32_t>(c->L.spins),
-                     c->at<double>(c->L.e_cur), c->at<uint32_t>(c->L.candT), c->at<const double>(c->L.partial), d.P,
+                     c->at<double>(c->L.e_cur), c->flips(step), c->base(step), c->at<const double>(c->L.partial), d.P,
                      c->scale, c->roots(step), c->at<mc3::Record>(c->L.ring), c->at<unsigned long long>(c->L.moves),
                      c->at<unsigned long long>(c->L.near), c->at<double>(c->L.minm), c->at<double>(c->L.e_bar),
                      d.chains, d.M, d.W, d.Bp, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, beta, c->tol, c->key(),
-                     c->cfg.chain_base, step, c->cfg.trace_steps, build_next ? 1 : 0, c->flips(step + 1u),
-                     c->roots(step + 1u));
+                     c->cfg.chain_base, step, c->cfg.trace_steps, next_base ? 1 : 0, c->flips(step + 1u),
+                     c->roots(step + 1u), c->base(step + 1u));
   MC3_TRY(check_launch(c, "select kernel"));
   if (c->cfg.mean_steps > 0) {
     hipLaunchKernelGGL(mc3::k_chain_means, dim3(1), dim3(256), 0, c->stream, c->at<double>(c->L.means),
@@ -290,9 +286,9 @@ mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool build_next = f
                        step % (uint32_t)c->cfg.mean_steps, step);
     MC3_TRY(check_launch(c, "means kernel"));
   }
-  c->have_proposal = build_next;
+  c->have_proposal = next_base;
   c->have_scores = false;
-  if (build_next) c->proposal_step = step + 1u;
+  if (next_base) c->proposal_step = step + 1u;
   c->steps_done += 1;
   return MC3_OK;
 }
@@ -303,19 +299,18 @@ double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
 }
 
 // n steps with the proposal of step t+1 on the auxiliary stream, overlapping the
-// scoring of step t; the selection of step t also builds the candidates of step t+1.
-// Flip sets and roots are double-buffered by step parity: propose(t+1) waits for
-// select(t-1) (the last reader of its buffers); select(t) waits for propose(t+1).
-// Everything joins back into the caller's stream.
+// scoring of step t; the selection of step t also forms the base words of step t+1.
+// Flip sets, roots and base words are double-buffered by step parity: propose(t+1)
+// waits for select(t-1) (the last reader of its buffers); select(t) waits for
+// propose(t+1).  Everything joins back into the caller's stream.
 mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
   if (n <= 0) return MC3_OK;
   MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[0], c->stream), "event"));
   MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[1], c->stream), "event"));
   MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[step0 & 1u], 0), "wait"));
-  MC3_TRY(launch_propose(c, step0, c->aux));
+  MC3_TRY(launch_propose(c, step0, c->aux, true));
   MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[step0 & 1u], c->aux), "event"));
   MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_prop[step0 & 1u], 0), "wait"));
-  MC3_TRY(launch_build(c, step0));
   c->have_proposal = true;
   c->proposal_step = step0;
   for (int64_t i = 0; i < n; ++i) {
@@ -324,7 +319,7 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
     if (!last) {
       const uint32_t t1 = t + 1u;
       MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[t1 & 1u], 0), "wait"));
-      MC3_TRY(launch_propose(c, t1, c->aux));
+      MC3_TRY(launch_propose(c, t1, c->aux, false));
       MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[t1 & 1u], c->aux), "event"));
     }
     MC3_TRY(do_score(c, nullptr));
@@ -456,6 +451,10 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
     MC3_TRY(check_launch(c, "init spins kernel"));
   }
   MC3_TRY(launch_energy(c, c->at<double>(c->L.e_cur)));
+  // flip-set padding columns and the zero base row must read as zero
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.flips), 0, (size_t)2 * d.W * d.Bp * 4, c->stream), "clear"));
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.base), 0, (size_t)2 * (d.chains + 1) * d.W * 4, c->stream),
+                 "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.moves), 0, (size_t)d.chains * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.near), 0, (size_t)d.chains * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.drift), 0, (size_t)d.chains * 8, c->stream), "clear"));
@@ -603,6 +602,11 @@ mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
   const Dims& d = c->d;
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_candidates sync"));
   if (bits) {
+    const uint32_t st = c->proposal_step;
+    hipLaunchKernelGGL(mc3::k_build_candidates, dim3(d.Bp / 256, d.W), dim3(256), 0, c->stream,
+                       c->at<uint32_t>(c->L.candT), c->flips(st), c->base(st), c->roots(st), d.chains, d.M, d.W, d.Bp);
+    MC3_TRY(check_launch(c, "candidate kernel"));
+    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_candidates sync"));
     std::vector<uint32_t> t((size_t)d.W * d.Bp);
     MC3_TRY(hip_ok(c, hipMemcpy(t.data(), c->at<uint32_t>(c->L.candT), t.size() * 4, hipMemcpyDeviceToHost), "read"));
     for (int col = 0; col < d.B; ++col)

@@ -29,12 +29,17 @@ def gpu_spins(ctx) -> np.ndarray:
     return native.bits_to_spins(bits, ctx.N)
 
 
+def column_nodes(M, r):
+    """Node held by each candidate column: column m is node m+1, except that for a
+    root r >= 1 column r-1 holds the hub (node 0)."""
+    return [0 if (r >= 1 and m == r - 1) else m + 1 for m in range(M)]
+
+
 def oracle_candidates(seed, chain, step, N, M, kmin, kmax, s, rule="mcmcmc"):
     """Root and the M non-current node configurations in column order."""
     r, nodes = oracle.propose_nodes(seed, chain, step, N, M, kmin, kmax, s,
                                     rule=oracle.RULE_METROPOLIS if rule == "metropolis" else oracle.RULE_MCMCMC)
-    cols = [v for v in range(M + 1) if v != r]
-    return r, nodes[cols]
+    return r, nodes[column_nodes(M, r)]
 
 
 def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas, rule, energy_rtol,
