@@ -431,10 +431,63 @@ __global__ void k_pack_f64(double* __restrict__ Apack, const double* __restrict_
   Apack[gid] = (k > i) ? J64[(size_t)i * Np + k] : 0.0;
 }
 
-// Energies of candidate columns on the FP64 matrix cores (16x16x4).  Same work
-// units as the split kernel (row-block pair of 128 rows x column tile); the four
-// waves form a 2 x 2 grid of 64 x 64 tiles; A (J) is staged through LDS, 16 k per
-// stage, double-buffered; B (+-1) is built from the candidate bitsets.
+// LDS stage of the FP64 scoring loop (one 32-k chunk): 8 row fragments x 8 k-steps
+// of A (64 doubles each) and the flip/base words of the 128 columns of the tile.
+struct F64Stage {
+  double a[8][8][64];
+  uint32_t flip[128];
+  uint32_t base[128];
+};
+
+// Copies of chunk `cn` into `st` by wave `wave`: row fragments 2*wave, 2*wave+1 (each
+// 8 k-step fragments = 4 KiB contiguous, four 1-KiB copies), and one 64-word slice of
+// the flip (waves 0, 1) or base (waves 2, 3) words.  Nine vector-memory operations.
+__device__ __forceinline__ void f64_copy(F64Stage& st, const double* a_blk, int KS, const uint32_t* fsrc,
+                                         const uint32_t* bsrc, int cn, int Bp, int lane, int wave) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int rf = 2 * wave + h;
+    const double* src = a_blk + ((size_t)rf * KS + (size_t)cn * 8) * 64 + 2 * lane;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      lds_dma16(reinterpret_cast<const uint4*>(src + q * 128), reinterpret_cast<uint4*>(&st.a[rf][2 * q][0]));
+  }
+  if (wave < 2) lds_dma4(fsrc + (size_t)cn * Bp + 64 * wave, &st.flip[64 * wave]);
+  else lds_dma4(bsrc + cn, &st.base[64 * (wave - 2)]);
+}
+
+// MFMAs of one chunk: 8 k-steps x 4 row fragments x 4 column fragments of 16x16x4.
+__device__ __forceinline__ void f64_mfma(f64x4 (&acc)[4][4], const F64Stage& st, uint32_t rootmask, int lane,
+                                         int wr, int wc) {
+  uint32_t w[4];
+#pragma unroll
+  for (int cf = 0; cf < 4; ++cf) {
+    const int j = wc * 64 + cf * 16 + (lane & 15);
+    w[cf] = st.base[j] ^ (((rootmask >> cf) & 1u) ? 0u : st.flip[j]);
+  }
+  const double one = 1.0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    double b[4];
+#pragma unroll
+    for (int cf = 0; cf < 4; ++cf) {
+      const uint32_t bit = (w[cf] >> (4 * s + (lane >> 4))) & 1u;
+      b[cf] = __longlong_as_double(__double_as_longlong(one) | ((long long)bit << 63));
+    }
+#pragma unroll
+    for (int rf = 0; rf < 4; ++rf) {
+      const double a = st.a[wr * 4 + rf][s][lane];
+#pragma unroll
+      for (int cf = 0; cf < 4; ++cf)
+        acc[rf][cf] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cf], acc[rf][cf], 0, 0, 0);
+    }
+  }
+}
+
+// Energies of candidate columns on the FP64 matrix cores (16x16x4).  Same work units
+// as the split kernel (row-block pair of 128 rows x 128-column tile); the four waves
+// form a 2 x 2 grid of 64 x 64 tiles; A (J) and the columns' flip/base words are
+// staged through LDS by direct global->LDS copies one 32-k chunk ahead (two stages).
 // Output layout of the 16x16x4 f64 instruction: C[i][j] is element i/4 of lane
 // j + 16 (i % 4).
 __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__ Apack,
@@ -444,104 +497,77 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__
                                                       double* __restrict__ partial, int chains, int M, int Np,
                                                       int Bp, int NB, int P, int CT) {
   constexpr int TN = 128;
-  __shared__ double lds[2][8][4][64];
+  __shared__ F64Stage fs0, fs1;
   const int U = P * CT;
   const int per = (U + 7) / 8;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int u = xcd * per + slot;
   if (slot >= per || u >= U) return;
   const int p = u / CT, ct = u % CT;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const int col_w = ct * TN + wc * 64;
+  const int col_t = ct * TN;
   const int KS = Np / 4;
   const int W = Np / 32;
   const int B = chains * M;
-  const double one = 1.0;
-  // per-lane column data: base row and root-column flag of the 4 columns of this lane
-  const uint32_t* brow[4];
-  bool isroot[4];
+  // per-lane column data: root-column mask of this lane's 4 columns, base row of the
+  // column this lane copies (waves 2, 3)
+  uint32_t rootmask = 0u;
 #pragma unroll
   for (int cf = 0; cf < 4; ++cf) {
-    const int col = col_w + cf * 16 + (lane & 15);
-    brow[cf] = base + (size_t)(col < B ? col / M : chains) * W;
-    isroot[cf] = false;
+    const int col = col_t + wc * 64 + cf * 16 + (lane & 15);
     if (col < B) {
       const int c = col / M, r = roots[c];
-      isroot[cf] = r >= 1 && col - c * M == r - 1;
+      if (r >= 1 && col - c * M == r - 1) rootmask |= 1u << cf;
     }
   }
+  const int ccol = col_t + 64 * (wave & 1) + lane;
+  const uint32_t* brow = base + (size_t)(ccol < B ? ccol / M : chains) * W;
 
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int nblk = (p == NB - 1 - p) ? 1 : 2;
   for (int bi = 0; bi < nblk; ++bi) {
     const int I = bi == 0 ? p : NB - 1 - p;
     const int k0 = I * kRowBlock;
-    const int nchunk = (Np - k0) / 16;
+    const int kw0 = k0 >> 5;
+    const int nchunk = (Np - k0) / 32;   // a multiple of 4
     f64x4 acc[4][4];
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
       for (int cf = 0; cf < 4; ++cf) acc[rf][cf] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    // staging: thread stages local row fragment tid/32 (of 8), 4 fragments x 64 lanes
-    // = 256 doubles per piece; this thread copies doubles (tid%32)*8 .. +7 of it.
-    const int piece = tid >> 5, off = (tid & 31) * 8;
-    const double* src = Apack + ((size_t)(8 * I + piece) * KS + (k0 / 4)) * 64 + off;
-    double2 stage[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) stage[q] = *(const double2*)(src + 2 * q);
-    double* ldsflat0 = &lds[0][piece][0][0] + off;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) *(double2*)(ldsflat0 + 2 * q) = stage[q];
+    // fragment (R = 8I + rf, S = k0/4 + 8 cn + s): a_blk + ((rf*KS + 8 cn + s) * 64)
+    const double* a_blk = Apack + ((size_t)(8 * I) * KS + (size_t)(k0 / 4)) * 64;
+    const uint32_t* fsrc = flipsT + (size_t)kw0 * Bp + col_t + lane;
+    const uint32_t* bsrc = brow + kw0;
+    f64_copy(fs0, a_blk, KS, fsrc, bsrc, 0, Bp, lane, wave);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int c = 0; c < nchunk; ++c) {
-      const int buf = c & 1;
-      if (c + 1 < nchunk) {
-        const double* s2 = src + (size_t)(c + 1) * 4 * 64;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) stage[q] = *(const double2*)(s2 + 2 * q);
-      }
-      // spins of the chunk's 16 rows of k for this wave's 64 columns
-      const int kbase = k0 + 16 * c;
-      uint32_t bw[4];
-#pragma unroll
-      for (int cf = 0; cf < 4; ++cf) {
-        const int kw = kbase >> 5;
-        const uint32_t b0 = brow[cf][kw];
-        bw[cf] = isroot[cf] ? b0 : (b0 ^ flipsT[(size_t)kw * Bp + col_w + cf * 16 + (lane & 15)]);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        double b[4];
-#pragma unroll
-        for (int cf = 0; cf < 4; ++cf) {
-          const uint32_t bit = (bw[cf] >> ((kbase & 31) + 4 * s + (lane >> 4))) & 1u;
-          b[cf] = __longlong_as_double(__double_as_longlong(one) | ((long long)bit << 63));
-        }
-#pragma unroll
-        for (int rf = 0; rf < 4; ++rf) {
-          const double a = lds[buf][wr * 4 + rf][s][lane];
-#pragma unroll
-          for (int cf = 0; cf < 4; ++cf)
-            acc[rf][cf] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cf], acc[rf][cf], 0, 0, 0);
-        }
-      }
-      if (c + 1 < nchunk) {
-        double* d = &lds[buf ^ 1][piece][0][0] + off;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *(double2*)(d + 2 * q) = stage[q];
-      }
+    for (int c = 0; c < nchunk; c += 2) {
+      f64_copy(fs1, a_blk, KS, fsrc, bsrc, c + 1, Bp, lane, wave);
+      __builtin_amdgcn_sched_barrier(0);
+      f64_mfma(acc, fs0, rootmask, lane, wr, wc);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      // past the end the copy re-reads the last chunk (in bounds; fs0 is not read again
+      // before the next row block refills it after a barrier)
+      f64_copy(fs0, a_blk, KS, fsrc, bsrc, (c + 2 < nchunk) ? c + 2 : nchunk - 1, Bp, lane, wave);
+      __builtin_amdgcn_sched_barrier(0);
+      f64_mfma(acc, fs1, rootmask, lane, wr, wc);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
     // epilogue: lane holds rows 4e + lane/16 (e = 0..3) of column lane%16
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf) {
       const int row0 = k0 + wr * 64 + rf * 16;
+      const int rw = row0 >> 5;
 #pragma unroll
       for (int cf = 0; cf < 4; ++cf) {
-        const int rw = row0 >> 5;
-        const uint32_t b0 = brow[cf][rw];
-        const uint32_t rb = isroot[cf] ? b0 : (b0 ^ flipsT[(size_t)rw * Bp + col_w + cf * 16 + (lane & 15)]);
+        const int col = col_t + wc * 64 + cf * 16 + (lane & 15);
+        const uint32_t bw = col < B ? base[(size_t)(col / M) * W + rw] : 0u;
+        const uint32_t rb = ((rootmask >> cf) & 1u) ? bw : (bw ^ flipsT[(size_t)rw * Bp + col]);
         double sum = 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -563,7 +589,7 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__
   }
   // the two row-halves (wr = 0, 1) of the tile are combined through LDS
   __syncthreads();
-  double* red = &lds[0][0][0][0];
+  double* red = &fs0.a[0][0][0];
   if (wr == 1 && lane < 16) {
 #pragma unroll
     for (int cf = 0; cf < 4; ++cf) red[wc * 64 + cf * 16 + lane] = part[cf];
@@ -572,7 +598,7 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__
   if (wr == 0 && lane < 16) {
 #pragma unroll
     for (int cf = 0; cf < 4; ++cf)
-      partial[(size_t)p * Bp + col_w + cf * 16 + lane] = part[cf] + red[wc * 64 + cf * 16 + lane];
+      partial[(size_t)p * Bp + col_t + wc * 64 + cf * 16 + lane] = part[cf] + red[wc * 64 + cf * 16 + lane];
   }
 }
 
