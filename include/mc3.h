@@ -81,6 +81,29 @@ typedef struct {
     double near_tie_tol;     /* selection margin below which a step is flagged; < 0 => default */
 } mc3_config;
 
+/* One instance of a batch: its size, graph size, chains and flip-set range, with the
+ * constraints of mc3_config. */
+typedef struct {
+    int32_t N, M, chains, kmin, kmax;
+} mc3_instance_desc;
+
+/* A batch of independent SK instances sharing precision, rule, seed and ring sizes
+ * (many small instances in one set of launches).  The chains of all instances are
+ * numbered consecutively in instance order ("global chains"): global chain g uses
+ * Philox chain index chain_base + g, so instance i with first global chain g_i runs
+ * exactly as a single-instance context with chain_base + g_i would. */
+typedef struct {
+    int32_t n_instances;     /* 1 .. 2^20 */
+    int32_t precision;       /* mc3_precision */
+    int32_t rule;            /* mc3_rule */
+    int32_t trace_steps;     /* record ring capacity (steps), records of all global chains */
+    int32_t mean_steps;      /* chain-mean trace capacity (means over all global chains) */
+    uint32_t chain_base;     /* Philox chain index of global chain 0 */
+    uint64_t seed;           /* Philox key */
+    double near_tie_tol;     /* < 0 => default */
+    const mc3_instance_desc* instances;  /* [n_instances], copied by mc3_batch_create */
+} mc3_batch_config;
+
 /* Per-step, per-chain record (40 bytes). */
 typedef struct {
     int32_t r;          /* position of the state the graph was generated from (root) */
@@ -117,6 +140,15 @@ mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes);
  * all work joins back into `stream`.  Validates the configuration before any HIP call. */
 mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out);
 
+/* Batch forms of mc3_workspace_size and mc3_create (same contracts).  Every call
+ * below works on a batch context: per-chain arrays span the global chains, the
+ * energies of mc3_score_candidates are the instances' [chains][M] blocks one after
+ * another, and spins passed to mc3_init_chains are the instances' [chains][N] blocks
+ * one after another.  A single-instance context is a batch of one. */
+mc3_status mc3_batch_workspace_size(const mc3_batch_config* cfg, size_t* bytes);
+mc3_status mc3_batch_create(const mc3_batch_config* cfg, void* workspace, size_t bytes, void* stream,
+                            mc3_ctx** out);
+
 /* Release the host-side context (the workspace stays the caller's). */
 mc3_status mc3_destroy(mc3_ctx* ctx);
 
@@ -128,6 +160,11 @@ mc3_status mc3_destroy(mc3_ctx* ctx);
  * precision, as three BF16 terms hi = bf16(J), mid = bf16(J - hi),
  * lo = bf16(J - hi - mid), each packed in matrix-core fragment order. */
 mc3_status mc3_init_couplings(mc3_ctx* ctx, const double* J, int64_t ld, double scale);
+
+/* mc3_init_couplings for instance `instance` of a batch (mc3_init_couplings loads
+ * instance 0).  Every instance needs its couplings before mc3_init_chains. */
+mc3_status mc3_init_couplings_instance(mc3_ctx* ctx, int32_t instance, const double* J, int64_t ld,
+                                       double scale);
 
 /* Set the chains' states: spins is a host array [chains][N] of +-1 (int8), or NULL to
  * draw them from the init stream (bit i%32 of word i/32 of stream (tag 1, chain,
@@ -167,13 +204,23 @@ mc3_status mc3_select(mc3_ctx* ctx, uint32_t step, double beta);
  * (beta0 if total <= 1). */
 mc3_status mc3_step_n(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
 
+/* The steps of mc3_step_n, launched instance by instance (propose, score and select
+ * of instance 0, then of instance 1, ...) on the context's stream, without the
+ * overlap of proposal and scoring.  Same results as mc3_step_n; it is the cost of
+ * running the instances one at a time, against which the batched launches are
+ * measured. */
+mc3_status mc3_step_n_per_instance(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1,
+                                   int64_t total);
+
 /* Recompute every chain's energy from its spins in FP64 (plain pair sum on the
  * device), record max |carried - recomputed| in the summary, and replace the
  * carried energy by the recomputed one. */
 mc3_status mc3_recompute(mc3_ctx* ctx);
 
 /* Synchronise; copy the chains' energies (host [chains], may be NULL), spins (host
- * bitsets [chains][ceil(N/32)] uint32, may be NULL) and the summary (may be NULL). */
+ * bitsets [chains][ceil(N/32)] uint32, may be NULL) and the summary (may be NULL).
+ * In a batch: [global chains], and the bitset row length is ceil(max N / 32) words
+ * (zero beyond each instance's own). */
 mc3_status mc3_measure(mc3_ctx* ctx, double* e_cur, uint32_t* spin_bits, mc3_summary* summary);
 
 /* Synchronise and copy `n` steps of records starting at global step `first`
@@ -181,7 +228,8 @@ mc3_status mc3_measure(mc3_ctx* ctx, double* e_cur, uint32_t* spin_bits, mc3_sum
 mc3_status mc3_read_records(mc3_ctx* ctx, uint32_t first, int32_t n, mc3_record* out);
 
 /* Synchronise and copy the candidate bitsets of the last mc3_propose into host
- * [chains][M][ceil(N/32)] uint32, and the roots into host [chains] (either may be NULL). */
+ * [chains][M][ceil(N/32)] uint32, and the roots into host [chains] (either may be NULL).
+ * Single-instance contexts only (MC3_E_UNSUPPORTED for a batch of several). */
 mc3_status mc3_read_candidates(mc3_ctx* ctx, uint32_t* bits, int32_t* roots);
 
 /* Synchronise and copy the chain means of steps first .. first+n-1 (still in the

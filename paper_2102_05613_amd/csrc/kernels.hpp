@@ -34,23 +34,55 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kRowBlock = 128;  // rows of J per scoring work unit (4 fragments of 32)
 
+// One SK instance of a batch, as the kernels see it.  Byte offsets are into the
+// workspace; the per-chain arrays (energies, roots, counters, records) are global over
+// the batch and indexed by chain0 + c.
+struct Inst {
+  int32_t N, Np, W, M;
+  int32_t chains, kmin, kmax, B;
+  int32_t Bp, NB, P, chain0;
+  double scale;
+  uint64_t J64, Jpack, flips[2], base[2], partial, spins;
+};
+
+// A scoring work unit (row-block pair p, column tile ct of instance inst); inst < 0 is
+// an idle slot of the launch grid.
+struct Unit {
+  int32_t inst, p, ct, pad;
+};
+
+// A proposal block: edges edge0 .. edge0 + blockDim.x - 1 (flattened chain*M + e-1) of
+// instance inst.
+struct PBlock {
+  int32_t inst, edge0;
+};
+
+template <class T>
+__device__ __forceinline__ T* ws_at(char* ws, uint64_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
 // ------------------------------------------------------------------- init spins
 
 // Spins of every chain from the init stream: word w of the chain's bitset is word w
-// of stream (init, chain, step 0, edge 0); bits at and beyond N are cleared.
-__global__ void k_init_spins(uint32_t* __restrict__ spins, int chains, int N, int W, Key key,
-                             uint32_t chain_base) {
-  int c = blockIdx.y;
-  int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= chains || w >= W) return;
+// of stream (init, chain_base + global chain, step 0, edge 0); bits at and beyond N
+// are cleared.  Grid: x over words (up to the largest W), y over global chains.
+__global__ void k_init_spins(char* __restrict__ ws, const Inst* __restrict__ insts,
+                             const int32_t* __restrict__ chain_inst, int total_chains, Key key, uint32_t chain_base) {
+  const int g = blockIdx.y;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total_chains) return;
+  const Inst in = insts[chain_inst[g]];
+  if (w >= in.W) return;
+  const int c = g - in.chain0;
   uint32_t v = 0;
-  if (w * 32 < N) {
-    uint4 b = stream_block(key, kTagInit, chain_base + (uint32_t)c, 0u, 0u, (uint32_t)w / 4u);
+  if (w * 32 < in.N) {
+    uint4 b = stream_block(key, kTagInit, chain_base + (uint32_t)g, 0u, 0u, (uint32_t)w / 4u);
     v = pick(b, (uint32_t)w % 4u);
-    int rem = N - w * 32;
+    int rem = in.N - w * 32;
     if (rem < 32) v &= (1u << rem) - 1u;
   }
-  spins[(size_t)c * W + w] = v;
+  ws_at<uint32_t>(ws, in.spins)[(size_t)c * in.W + w] = v;
 }
 
 // ------------------------------------------------------------------- propose
@@ -62,30 +94,32 @@ __device__ __forceinline__ int root_of(Key key, uint32_t gc, uint32_t step, int 
   return (int)randint(rb.x, (uint32_t)(M + 1));
 }
 
-// One thread per (chain, edge): k_e and Floyd's k-of-N draw into the thread's own
-// LDS bitset (row stride `stride` >= W words; W+1 where it fits, so the final copy
-// does not collide on banks), then every word written to flipsT[w][chain*M + e-1]
-// (consecutive threads, consecutive addresses).  Thread (chain, edge 1) stores the
-// chain's root.  With write_base, the thread of edge r (edge 1 if r = 0) also
-// writes base = s ^ F_r from the chain's current spins.  Dynamic LDS:
-// blockDim.x * stride words.
-__global__ void k_propose(uint32_t* __restrict__ flipsT, int32_t* __restrict__ roots, uint32_t* __restrict__ base,
-                          const uint32_t* __restrict__ spins, int write_base, int chains, int M, int N, int W, int Bp,
-                          int stride, int kmin, int kmax, int metropolis, Key key, uint32_t chain_base,
-                          uint32_t step) {
+// One thread per (chain, edge) of one instance (block table): k_e and Floyd's k-of-N
+// draw into the thread's own LDS bitset (row stride `stride` >= W words; W+1 where it
+// fits, so the final copy does not collide on banks), then every word written to
+// flipsT[w][chain*M + e-1] (consecutive threads, consecutive addresses).  Thread
+// (chain, edge 1) stores the chain's root.  With write_base, the thread of edge r
+// (edge 1 if r = 0) also writes base = s ^ F_r from the chain's current spins.
+// Dynamic LDS: blockDim.x * stride words.
+__global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts, const PBlock* __restrict__ blocks,
+                          int32_t* __restrict__ roots, int write_base, int stride, int metropolis, Key key,
+                          uint32_t chain_base, uint32_t step) {
   extern __shared__ uint32_t lds_bits[];
   const int T = blockDim.x;
-  const long long total = (long long)chains * M;
+  const PBlock blk0 = blocks[blockIdx.x];
+  const Inst in = insts[blk0.inst];
+  const int N = in.N, M = in.M, W = in.W, Bp = in.Bp;
+  const long long total = (long long)in.chains * M;
   for (int i = threadIdx.x; i < T * stride; i += T) lds_bits[i] = 0u;
   __syncthreads();
-  const long long g = (long long)blockIdx.x * T + threadIdx.x;
+  const long long g = (long long)blk0.edge0 + threadIdx.x;
   if (g >= total) return;
   const int c = (int)(g / M);
   const uint32_t e = (uint32_t)(g % M) + 1u;
-  const uint32_t gc = chain_base + (uint32_t)c;
+  const uint32_t gc = chain_base + (uint32_t)(in.chain0 + c);
   uint32_t* mine = lds_bits + (size_t)threadIdx.x * stride;
   uint4 blk = stream_block(key, kTagEdge, gc, step, e, 0u);
-  const int k = kmin + (int)randint(blk.x, (uint32_t)(kmax - kmin + 1));
+  const int k = in.kmin + (int)randint(blk.x, (uint32_t)(in.kmax - in.kmin + 1));
   for (int idx = 0; idx < k; ++idx) {
     const uint32_t n = 1u + (uint32_t)idx;
     if ((n & 3u) == 0u) blk = stream_block(key, kTagEdge, gc, step, e, n >> 2);
@@ -96,9 +130,12 @@ __global__ void k_propose(uint32_t* __restrict__ flipsT, int32_t* __restrict__ r
     mine[pos >> 5] |= 1u << (pos & 31u);
   }
   const int r = root_of(key, gc, step, M, metropolis);
-  if (e == 1u) roots[c] = (int32_t)r;
+  if (e == 1u) roots[in.chain0 + c] = (int32_t)r;
+  uint32_t* flipsT = ws_at<uint32_t>(ws, in.flips[step & 1u]);
   for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = mine[w];
   if (write_base && (int)e == (r == 0 ? 1 : r)) {
+    uint32_t* base = ws_at<uint32_t>(ws, in.base[step & 1u]);
+    const uint32_t* spins = ws_at<const uint32_t>(ws, in.spins);
     for (int w = 0; w < W; ++w) base[(size_t)c * W + w] = spins[(size_t)c * W + w] ^ (r ? mine[w] : 0u);
   }
 }
@@ -277,23 +314,26 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
 // wave owns 32*CF columns whose flip-set and base words come through LDS the same way
 // and are combined and expanded to +-1 in registers.  The epilogue multiplies h by
 // the column's spins and sums over rows in FP64; the unit writes one FP64 value per
-// column.  Units are laid out XCD-major so the blocks of one XCD share few row pairs
-// of J.
+// column.  Each block takes its unit from a table built by the host (the order of
+// the table decides which XCD runs which unit).
 template <int CF>
 __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
-    const uint4* __restrict__ Apack, const uint32_t* __restrict__ flipsT, const uint32_t* __restrict__ base,
-    const int32_t* __restrict__ roots, double* __restrict__ partial, int chains, int M, int Np, int Bp, int NB, int P,
-    int CT) {
+    char* __restrict__ ws, const Inst* __restrict__ insts, const Unit* __restrict__ units,
+    const int32_t* __restrict__ roots_all, uint32_t parity) {
   static_assert(CF % 2 == 0, "CF must be even (64-column copies)");
   constexpr int TN = 4 * 32 * CF;
   __shared__ SplitStage<CF> st0;
   __shared__ SplitStage<CF> st1;
-  const int U = P * CT;
-  const int per = (U + 7) / 8;
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int u = xcd * per + slot;
-  if (slot >= per || u >= U) return;
-  const int p = u / CT, ct = u % CT;
+  const Unit un = units[blockIdx.x];
+  if (un.inst < 0) return;
+  const Inst in = insts[un.inst];
+  const uint4* __restrict__ Apack = ws_at<const uint4>(ws, in.Jpack);
+  const uint32_t* __restrict__ flipsT = ws_at<const uint32_t>(ws, in.flips[parity]);
+  const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[parity]);
+  const int32_t* __restrict__ roots = roots_all + in.chain0;
+  double* __restrict__ partial = ws_at<double>(ws, in.partial);
+  const int chains = in.chains, M = in.M, Np = in.Np, Bp = in.Bp, NB = in.NB;
+  const int p = un.p, ct = un.ct;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col_w = ct * TN + wave * 32 * CF;   // first column of this wave
@@ -490,20 +530,21 @@ __device__ __forceinline__ void f64_mfma(f64x4 (&acc)[4][4], const F64Stage& st,
 // staged through LDS by direct global->LDS copies one 32-k chunk ahead (two stages).
 // Output layout of the 16x16x4 f64 instruction: C[i][j] is element i/4 of lane
 // j + 16 (i % 4).
-__global__ __launch_bounds__(256, 2) void k_score_f64(const double* __restrict__ Apack,
-                                                      const uint32_t* __restrict__ flipsT,
-                                                      const uint32_t* __restrict__ base,
-                                                      const int32_t* __restrict__ roots,
-                                                      double* __restrict__ partial, int chains, int M, int Np,
-                                                      int Bp, int NB, int P, int CT) {
+__global__ __launch_bounds__(256, 2) void k_score_f64(char* __restrict__ ws, const Inst* __restrict__ insts,
+                                                      const Unit* __restrict__ units,
+                                                      const int32_t* __restrict__ roots_all, uint32_t parity) {
   constexpr int TN = 128;
   __shared__ F64Stage fs0, fs1;
-  const int U = P * CT;
-  const int per = (U + 7) / 8;
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int u = xcd * per + slot;
-  if (slot >= per || u >= U) return;
-  const int p = u / CT, ct = u % CT;
+  const Unit un = units[blockIdx.x];
+  if (un.inst < 0) return;
+  const Inst in = insts[un.inst];
+  const double* __restrict__ Apack = ws_at<const double>(ws, in.Jpack);
+  const uint32_t* __restrict__ flipsT = ws_at<const uint32_t>(ws, in.flips[parity]);
+  const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[parity]);
+  const int32_t* __restrict__ roots = roots_all + in.chain0;
+  double* __restrict__ partial = ws_at<double>(ws, in.partial);
+  const int chains = in.chains, M = in.M, Np = in.Np, Bp = in.Bp, NB = in.NB;
+  const int p = un.p, ct = un.ct;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
@@ -666,25 +707,35 @@ __global__ void k_column_energies(double* __restrict__ Ecol, const double* __res
 // Without a log-prior the largest exponent is -0, so exp(l - lmax) = exp(l) bit for
 // bit and that shift is not formed.  Dynamic LDS: 16 (M+1) + 4 W bytes.
 __global__ __launch_bounds__(256) void k_select(
-    uint32_t* __restrict__ spins, double* __restrict__ e_cur, const uint32_t* __restrict__ flipsT,
-    const uint32_t* __restrict__ base, const double* __restrict__ partial, int P, double scale,
-    const int32_t* __restrict__ roots,
-    Record* __restrict__ ring, unsigned long long* __restrict__ moves, unsigned long long* __restrict__ near_ties,
-    double* __restrict__ min_margin, double* __restrict__ e_bar_out, int chains, int M, int W, int Bp,
+    char* __restrict__ ws, const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
+    int total_chains, double* __restrict__ e_cur, const int32_t* __restrict__ roots_all,
+    const int32_t* __restrict__ roots_next_all, Record* __restrict__ ring, unsigned long long* __restrict__ moves,
+    unsigned long long* __restrict__ near_ties, double* __restrict__ min_margin, double* __restrict__ e_bar_out,
     int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, int trace_steps,
-    int next_base, const uint32_t* __restrict__ flipsT_next, const int32_t* __restrict__ roots_next,
-    uint32_t* __restrict__ base_next) {
+    int next_base) {
   extern __shared__ double sel_lds[];
   __shared__ int sh_vstar;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c = blockIdx.x;
-  if (c >= chains) return;
+  const int g = chain_off + blockIdx.x;   // global chain
+  if (g >= total_chains) return;
+  const Inst in = insts[chain_inst[g]];
+  const int c = g - in.chain0;            // chain within the instance
+  const int M = in.M, W = in.W, Bp = in.Bp, P = in.P;
+  const double scale = in.scale;
+  uint32_t* __restrict__ spins = ws_at<uint32_t>(ws, in.spins);
+  const uint32_t* __restrict__ flipsT = ws_at<const uint32_t>(ws, in.flips[step & 1u]);
+  const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[step & 1u]);
+  const uint32_t* __restrict__ flipsT_next = ws_at<const uint32_t>(ws, in.flips[(step + 1u) & 1u]);
+  uint32_t* __restrict__ base_next = ws_at<uint32_t>(ws, in.base[(step + 1u) & 1u]);
+  const double* __restrict__ partial = ws_at<const double>(ws, in.partial);
+  const int32_t* __restrict__ roots = roots_all + in.chain0;
+  const int32_t* __restrict__ roots_next = roots_next_all + in.chain0;
   const int nodes = M + 1;
   double* En = sel_lds;                                                              // [nodes]
   unsigned long long* Qn = reinterpret_cast<unsigned long long*>(sel_lds + nodes);   // [nodes]
   uint32_t* snew = reinterpret_cast<uint32_t*>(sel_lds + 2 * (size_t)nodes);        // [W]
   const int r = metropolis ? 0 : roots[c];
-  const double ecur = e_cur[c];
+  const double ecur = e_cur[g];
 
   // 1. node energies
   for (int m = tid; m < M; m += 256) {
@@ -698,7 +749,7 @@ __global__ __launch_bounds__(256) void k_select(
 
   // 2. the rule (wave 0)
   if (wave == 0) {
-    const uint32_t gc = chain_base + (uint32_t)c;
+    const uint32_t gc = chain_base + (uint32_t)g;
     uint4 ub = stream_block(key, kTagSelect, gc, step, 0u, 0u);
     const uint64_t u53 = u53_of(ub.x, ub.y);
     int vstar;
@@ -776,11 +827,11 @@ __global__ __launch_bounds__(256) void k_select(
       const bool moved = vstar != r;
       const bool near = margin < tol;
       sh_vstar = vstar;
-      e_cur[c] = e_new;
-      e_bar_out[c] = ebar;
-      moves[c] += moved ? 1ull : 0ull;
-      near_ties[c] += near ? 1ull : 0ull;
-      min_margin[c] = margin < min_margin[c] ? margin : min_margin[c];
+      e_cur[g] = e_new;
+      e_bar_out[g] = ebar;
+      moves[g] += moved ? 1ull : 0ull;
+      near_ties[g] += near ? 1ull : 0ull;
+      min_margin[g] = margin < min_margin[g] ? margin : min_margin[g];
       if (trace_steps > 0) {
         Record rec;
         rec.r = r;
@@ -790,7 +841,7 @@ __global__ __launch_bounds__(256) void k_select(
         rec.margin = margin;
         rec.flags = (near ? 1u : 0u) | (moved ? 2u : 0u);
         rec.step = step;
-        ring[(size_t)(step % (uint32_t)trace_steps) * chains + c] = rec;
+        ring[(size_t)(step % (uint32_t)trace_steps) * total_chains + g] = rec;
       }
     }
   }
@@ -854,15 +905,20 @@ __global__ __launch_bounds__(256) void k_chain_means(double* __restrict__ trace,
 
 // ------------------------------------------------------------------- FP64 energy
 
-// E(s) = -scale * sum_{i<j} J_ij s_i s_j in FP64, one block (256 threads) per chain.
-// Thread t owns columns j = t, t+256, ...; row i is read coalesced; a fixed-order
-// tree combines the threads.
-__global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, const uint32_t* __restrict__ spins,
-                                                    const double* __restrict__ J64, int N, int Np, int W,
-                                                    double scale) {
+// E(s) = -scale * sum_{i<j} J_ij s_i s_j in FP64, one block (256 threads) per global
+// chain.  Thread t owns columns j = t, t+256, ...; row i is read coalesced; a
+// fixed-order tree combines the threads.
+__global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, char* __restrict__ ws,
+                                                    const Inst* __restrict__ insts,
+                                                    const int32_t* __restrict__ chain_inst) {
   __shared__ double red[256];
-  const int c = blockIdx.x;
-  const uint32_t* s = spins + (size_t)c * W;
+  const int g = blockIdx.x;
+  const Inst in = insts[chain_inst[g]];
+  const int c = g - in.chain0;
+  const int N = in.N, Np = in.Np, W = in.W;
+  const double scale = in.scale;
+  const double* __restrict__ J64 = ws_at<const double>(ws, in.J64);
+  const uint32_t* s = ws_at<const uint32_t>(ws, in.spins) + (size_t)c * W;
   double acc = 0.0;
   for (int i = 0; i < N; ++i) {
     const double si = ((s[i >> 5] >> (i & 31)) & 1u) ? -1.0 : 1.0;
@@ -882,7 +938,7 @@ __global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, co
     if ((int)threadIdx.x < o) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[c] = -(scale * red[0]);
+  if (threadIdx.x == 0) out[g] = -(scale * red[0]);
 }
 
 }  // namespace mc3

@@ -1,7 +1,14 @@
 // mc3.hip -- C ABI of the MI355X MCMCMC hot path for the SK spin glass.
 // The declarations and their contracts are in include/mc3.h.
+//
+// A context holds a batch of SK instances (a single-instance context is a batch of
+// one).  Every kernel reads its instance from a device table, so one launch covers
+// the whole batch: propose over a table of (instance, first edge) blocks, score over
+// a table of (instance, row-block pair, column tile) work units, select over the
+// global chain range.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,102 +24,215 @@
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kColTile = 512;  // candidate columns are padded to this (split tile width)
+constexpr int kColPad = 512;     // candidate columns of an instance are padded to this
+constexpr int kTileSplit = 256;  // columns per split-scoring unit (4 waves x 64)
+constexpr int kTileF64 = 128;    // columns per FP64-scoring unit
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-struct Dims {
-  int N, M, chains, Np, W, Wn, B, Bp, NB, P;
+struct InstH {
+  mc3_instance_desc desc;
+  int Np, W, Wn, B, Bp, NB, P, chain0, col0;
+  size_t J64, Jpack, flips[2], base[2], partial, spins;  // byte offsets into the workspace
+  double scale = 1.0;
+  bool have_J = false;
+  int unit_off = 0, unit_grid = 0;     // this instance's own unit table (per-instance launches)
+  int pblock_off = 0, pblock_cnt = 0;  // its proposal blocks
 };
 
-Dims dims_of(const mc3_config& c) {
-  Dims d;
-  d.N = c.N;
-  d.M = c.M;
-  d.chains = c.chains;
-  d.Np = (c.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock;
-  d.W = d.Np / 32;
-  d.Wn = (c.N + 31) / 32;
-  d.B = c.chains * c.M;
-  d.Bp = (d.B + kColTile - 1) / kColTile * kColTile;
-  d.NB = d.Np / mc3::kRowBlock;
-  d.P = (d.NB + 1) / 2;
-  return d;
+struct Plan {
+  std::vector<InstH> inst;
+  int total_chains = 0, total_cols = 0, Wmax = 0, Wn_max = 0, Mmax = 0;
+  int prop_T = 256, prop_stride = 1;
+  std::vector<mc3::Unit> units_global, units_local;
+  std::vector<mc3::PBlock> pblocks;
+  std::vector<int32_t> chain_inst;
+  size_t insts = 0, chain_inst_off = 0, units_global_off = 0, units_local_off = 0, pblocks_off = 0;
+  size_t e_cur = 0, e_bar = 0, roots = 0, candT = 0, ring = 0, means = 0, moves = 0, near = 0, minm = 0, drift = 0,
+         erecomp = 0, total = 0;
+};
+
+const char* validate_instance(const mc3_instance_desc& d, int rule) {
+  if (d.N < 2 || d.N > 8192) return "N must be in [2, 8192]";
+  if (d.M < 1 || d.M > 4000) return "M must be in [1, 4000]";
+  if (d.chains < 1) return "chains must be >= 1";
+  if ((long long)d.chains * d.M > (1ll << 24)) return "chains * M must be <= 2^24";
+  if (d.kmin < 1 || d.kmax < d.kmin || d.kmax > d.N) return "need 1 <= kmin <= kmax <= N";
+  if (rule == MC3_RULE_METROPOLIS && d.M != 1) return "rule METROPOLIS requires M == 1";
+  return nullptr;
 }
 
-struct Layout {
-  size_t J64, Jpack, spins, e_cur, e_bar, flips, roots, base, candT, partial, Ecol, ring, means, moves, near, minm,
-      drift, erecomp, total;
-};
+const char* validate_batch(const mc3_batch_config* c) {
+  if (!c) return "config is NULL";
+  if (c->n_instances < 1 || c->n_instances > (1 << 20)) return "n_instances must be in [1, 2^20]";
+  if (!c->instances) return "instances is NULL";
+  if (c->precision != MC3_FP64 && c->precision != MC3_SPLIT_BF16) return "unknown precision";
+  if (c->rule != MC3_RULE_MCMCMC && c->rule != MC3_RULE_METROPOLIS) return "unknown rule";
+  if (c->trace_steps < 0) return "trace_steps must be >= 0";
+  if (c->mean_steps < 0) return "mean_steps must be >= 0";
+  if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
+  long long chains = 0, cols = 0;
+  for (int i = 0; i < c->n_instances; ++i) {
+    if (const char* e = validate_instance(c->instances[i], c->rule)) return e;
+    chains += c->instances[i].chains;
+    cols += (long long)c->instances[i].chains * c->instances[i].M;
+  }
+  if (chains + c->chain_base > (1ll << 28)) return "chain_base + total chains must be <= 2^28";
+  if (cols > (1ll << 31) - 1) return "total candidate columns must be < 2^31";
+  if (chains * (long long)c->trace_steps > (1ll << 31)) return "total chains * trace_steps must be <= 2^31";
+  return nullptr;
+}
 
-Layout layout_of(const mc3_config& c) {
-  const Dims d = dims_of(c);
-  Layout L;
+// Cost of a scoring unit in 128x128 K blocks: the pair (p, NB-1-p) spans NB+1 blocks
+// of the upper triangle, the self-paired middle block row NB-p.
+int unit_cost(int NB, int p) { return p == NB - 1 - p ? NB - p : NB + 1; }
+
+// The batch plan: dimensions, tables and the workspace layout.
+Plan make_plan(const mc3_batch_config& cfg) {
+  Plan pl;
+  const int n = cfg.n_instances;
+  pl.inst.resize(n);
+  for (int i = 0; i < n; ++i) {
+    InstH& h = pl.inst[i];
+    h.desc = cfg.instances[i];
+    const mc3_instance_desc& d = h.desc;
+    h.Np = (d.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock;
+    h.W = h.Np / 32;
+    h.Wn = (d.N + 31) / 32;
+    h.B = d.chains * d.M;
+    h.Bp = (h.B + kColPad - 1) / kColPad * kColPad;
+    h.NB = h.Np / mc3::kRowBlock;
+    h.P = (h.NB + 1) / 2;
+    h.chain0 = pl.total_chains;
+    h.col0 = pl.total_cols;
+    pl.total_chains += d.chains;
+    pl.total_cols += h.B;
+    pl.Wmax = std::max(pl.Wmax, h.W);
+    pl.Wn_max = std::max(pl.Wn_max, h.Wn);
+    pl.Mmax = std::max(pl.Mmax, d.M);
+  }
+  // proposal blocks: one LDS bitset per thread, row stride W+1 where 64 threads fit
+  pl.prop_stride = pl.Wmax + 1;
+  int T = (int)(65536 / ((size_t)pl.prop_stride * 4));
+  if (T < 64) {
+    pl.prop_stride = pl.Wmax;
+    T = (int)(65536 / ((size_t)pl.prop_stride * 4));
+  }
+  T = std::min(T, 256) / 64 * 64;
+  pl.prop_T = std::max(T, 64);
+  for (int i = 0; i < n; ++i) {
+    InstH& h = pl.inst[i];
+    const long long edges = (long long)h.desc.chains * h.desc.M;
+    h.pblock_off = (int)pl.pblocks.size();
+    for (long long e0 = 0; e0 < edges; e0 += pl.prop_T) pl.pblocks.push_back(mc3::PBlock{i, (int32_t)e0});
+    h.pblock_cnt = (int)pl.pblocks.size() - h.pblock_off;
+    for (int c = 0; c < h.desc.chains; ++c) pl.chain_inst.push_back(i);
+  }
+  // Scoring units.  One instance: XCD-major placement -- grid slot b runs on XCD b % 8
+  // and the units of one XCD are consecutive in (pair, tile) order, so each XCD's L2
+  // holds the J rows of few pairs; trailing slots are idle.  A batch: all units by
+  // decreasing cost (stable, so instance order breaks ties), longest first.
+  const int TN = cfg.precision == MC3_SPLIT_BF16 ? kTileSplit : kTileF64;
+  struct Cand {
+    int inst, p, ct, cost;
+  };
+  std::vector<Cand> all;
+  for (int i = 0; i < n; ++i) {
+    InstH& h = pl.inst[i];
+    const int CT = (h.B + TN - 1) / TN;  // tiles holding at least one real column
+    const int U = h.P * CT;
+    const int per = (U + 7) / 8;
+    h.unit_off = (int)pl.units_local.size();
+    h.unit_grid = 8 * per;
+    for (int b = 0; b < 8 * per; ++b) {
+      const int u = (b & 7) * per + (b >> 3);
+      mc3::Unit un{-1, 0, 0, 0};
+      if (u < U) un = mc3::Unit{i, u / CT, u % CT, 0};
+      pl.units_local.push_back(un);
+    }
+    for (int u = 0; u < U; ++u) all.push_back(Cand{i, u / CT, u % CT, unit_cost(h.NB, u / CT)});
+  }
+  if (n == 1) {
+    pl.units_global = pl.units_local;
+  } else {
+    std::stable_sort(all.begin(), all.end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
+    for (const Cand& c : all) pl.units_global.push_back(mc3::Unit{c.inst, c.p, c.ct, 0});
+  }
+  // workspace layout
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
     o = align_up(o + bytes, kAlign);
     return at;
   };
-  L.J64 = take((size_t)d.Np * d.Np * sizeof(double));
-  if (c.precision == MC3_SPLIT_BF16)
-    L.Jpack = take((size_t)d.Np * d.Np * 3 * sizeof(uint16_t));
-  else
-    L.Jpack = take((size_t)d.Np * d.Np * sizeof(double));
-  L.spins = take((size_t)d.chains * d.W * 4);
-  L.e_cur = take((size_t)d.chains * 8);
-  L.e_bar = take((size_t)d.chains * 8);
-  L.flips = take((size_t)2 * d.W * d.Bp * 4);           // two steps (by parity)
-  L.roots = take((size_t)2 * d.chains * 4);
-  L.base = take((size_t)2 * (d.chains + 1) * d.W * 4);
-  L.candT = take((size_t)d.W * d.Bp * 4);
-  L.partial = take((size_t)d.P * d.Bp * 8);
-  L.Ecol = take((size_t)d.Bp * 8);
-  L.ring = take((size_t)(c.trace_steps > 0 ? c.trace_steps : 0) * d.chains * sizeof(mc3::Record));
-  L.means = take((size_t)(c.mean_steps > 0 ? c.mean_steps : 0) * 3 * sizeof(double));
-  L.moves = take((size_t)d.chains * 8);
-  L.near = take((size_t)d.chains * 8);
-  L.minm = take((size_t)d.chains * 8);
-  L.drift = take((size_t)d.chains * 8);
-  L.erecomp = take((size_t)d.chains * 8);
-  L.total = o;
-  return L;
+  const size_t C = (size_t)pl.total_chains;
+  pl.insts = take((size_t)n * sizeof(mc3::Inst));
+  pl.chain_inst_off = take(C * 4);
+  pl.units_global_off = take(pl.units_global.size() * sizeof(mc3::Unit));
+  pl.units_local_off = take(pl.units_local.size() * sizeof(mc3::Unit));
+  pl.pblocks_off = take(pl.pblocks.size() * sizeof(mc3::PBlock));
+  pl.e_cur = take(C * 8);
+  pl.e_bar = take(C * 8);
+  pl.roots = take(2 * C * 4);  // two steps, by parity
+  pl.moves = take(C * 8);
+  pl.near = take(C * 8);
+  pl.minm = take(C * 8);
+  pl.drift = take(C * 8);
+  pl.erecomp = take(C * 8);
+  pl.ring = take((size_t)cfg.trace_steps * C * sizeof(mc3::Record));
+  pl.means = take((size_t)cfg.mean_steps * 3 * sizeof(double));
+  size_t candT = 0;
+  for (int i = 0; i < n; ++i) {
+    InstH& h = pl.inst[i];
+    const size_t np2 = (size_t)h.Np * h.Np;
+    h.J64 = take(np2 * sizeof(double));
+    h.Jpack = take(cfg.precision == MC3_SPLIT_BF16 ? np2 * 3 * sizeof(uint16_t) : np2 * sizeof(double));
+    for (int q = 0; q < 2; ++q) h.flips[q] = take((size_t)h.W * h.Bp * 4);
+    for (int q = 0; q < 2; ++q) h.base[q] = take((size_t)(h.desc.chains + 1) * h.W * 4);
+    h.partial = take((size_t)h.P * h.Bp * 8);
+    h.spins = take((size_t)h.desc.chains * h.W * 4);
+    candT = std::max(candT, (size_t)h.W * h.Bp * 4);
+  }
+  pl.candT = take(candT);
+  pl.total = o;
+  return pl;
 }
 
-const char* validate(const mc3_config* c) {
-  if (!c) return "config is NULL";
-  if (c->N < 2 || c->N > 8192) return "N must be in [2, 8192]";
-  if (c->M < 1 || c->M > 4000) return "M must be in [1, 4000]";
-  if (c->chains < 1) return "chains must be >= 1";
-  if ((long long)c->chains * c->M > (1ll << 24)) return "chains * M must be <= 2^24";
-  if ((long long)c->chains + c->chain_base > (1ll << 28)) return "chain_base + chains must be <= 2^28";
-  if (c->kmin < 1 || c->kmax < c->kmin || c->kmax > c->N) return "need 1 <= kmin <= kmax <= N";
-  if (c->precision != MC3_FP64 && c->precision != MC3_SPLIT_BF16) return "unknown precision";
-  if (c->rule != MC3_RULE_MCMCMC && c->rule != MC3_RULE_METROPOLIS) return "unknown rule";
-  if (c->rule == MC3_RULE_METROPOLIS && c->M != 1) return "rule METROPOLIS requires M == 1";
-  if (c->trace_steps < 0) return "trace_steps must be >= 0";
-  if (c->mean_steps < 0) return "mean_steps must be >= 0";
-  if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
-  return nullptr;
+mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
+  mc3_batch_config b;
+  std::memset(&b, 0, sizeof b);
+  one->N = c->N;
+  one->M = c->M;
+  one->chains = c->chains;
+  one->kmin = c->kmin;
+  one->kmax = c->kmax;
+  b.n_instances = 1;
+  b.precision = c->precision;
+  b.rule = c->rule;
+  b.trace_steps = c->trace_steps;
+  b.mean_steps = c->mean_steps;
+  b.chain_base = c->chain_base;
+  b.seed = c->seed;
+  b.near_tie_tol = c->near_tie_tol;
+  b.instances = one;
+  return b;
 }
 
 }  // namespace
 
 struct mc3_ctx {
-  mc3_config cfg;
-  Dims d;
-  Layout L;
+  mc3_batch_config cfg;
+  std::vector<mc3_instance_desc> descs;
+  Plan pl;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
-  hipStream_t aux = nullptr;          // proposals of the next step run here, overlapping scoring
+  hipStream_t aux = nullptr;  // proposals of the next step run here, overlapping scoring
   hipEvent_t ev_prop[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};
   int device = 0;
-  bool have_J = false, have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
+  bool have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
   uint32_t proposal_step = 0;
-  double scale = 1.0;
   double tol = 0.0;
   int64_t steps_done = 0;
-  int split_cf = 2;  // split scoring tile: 32*split_cf columns per wave (2 or 4)
   // optional HIP-event timing of the scoring launches
   bool timing = false;
   std::vector<hipEvent_t> t_start, t_stop;
@@ -124,10 +244,16 @@ struct mc3_ctx {
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  uint32_t* flips(uint32_t step) const { return at<uint32_t>(L.flips) + (size_t)(step & 1u) * d.W * d.Bp; }
-  int32_t* roots(uint32_t step) const { return at<int32_t>(L.roots) + (size_t)(step & 1u) * d.chains; }
-  uint32_t* base(uint32_t step) const { return at<uint32_t>(L.base) + (size_t)(step & 1u) * (d.chains + 1) * d.W; }
   mc3::Key key() const { return mc3::Key{(uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32)}; }
+  int32_t* roots(uint32_t step) const { return at<int32_t>(pl.roots) + (size_t)(step & 1u) * pl.total_chains; }
+  const mc3::Inst* insts() const { return at<const mc3::Inst>(pl.insts); }
+  const int32_t* chain_inst() const { return at<const int32_t>(pl.chain_inst_off); }
+  bool metropolis() const { return cfg.rule == MC3_RULE_METROPOLIS; }
+  bool all_J() const {
+    for (const InstH& h : pl.inst)
+      if (!h.have_J) return false;
+    return true;
+  }
 };
 
 namespace {
@@ -156,10 +282,10 @@ mc3_status hip_ok(mc3_ctx* c, hipError_t e, const char* what) {
   return MC3_OK;
 }
 
-#define MC3_TRY(expr)              \
-  do {                             \
-    mc3_status _s = (expr);        \
-    if (_s != MC3_OK) return _s;   \
+#define MC3_TRY(expr)            \
+  do {                           \
+    mc3_status _s = (expr);      \
+    if (_s != MC3_OK) return _s; \
   } while (0)
 
 mc3_status usable(mc3_ctx* c) {
@@ -169,38 +295,59 @@ mc3_status usable(mc3_ctx* c) {
   return MC3_OK;
 }
 
+// Device copy of the instance table (sizes, byte offsets, scales); synchronous.
+mc3_status upload_insts(mc3_ctx* c) {
+  const Plan& pl = c->pl;
+  std::vector<mc3::Inst> t(pl.inst.size());
+  for (size_t i = 0; i < pl.inst.size(); ++i) {
+    const InstH& h = pl.inst[i];
+    mc3::Inst& d = t[i];
+    std::memset(&d, 0, sizeof d);
+    d.N = h.desc.N;
+    d.Np = h.Np;
+    d.W = h.W;
+    d.M = h.desc.M;
+    d.chains = h.desc.chains;
+    d.kmin = h.desc.kmin;
+    d.kmax = h.desc.kmax;
+    d.B = h.B;
+    d.Bp = h.Bp;
+    d.NB = h.NB;
+    d.P = h.P;
+    d.chain0 = h.chain0;
+    d.scale = h.scale;
+    d.J64 = h.J64;
+    d.Jpack = h.Jpack;
+    d.flips[0] = h.flips[0];
+    d.flips[1] = h.flips[1];
+    d.base[0] = h.base[0];
+    d.base[1] = h.base[1];
+    d.partial = h.partial;
+    d.spins = h.spins;
+  }
+  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<char>(pl.insts), t.data(), t.size() * sizeof(mc3::Inst),
+                                   hipMemcpyHostToDevice, c->stream), "upload instance table"));
+  return hip_ok(c, hipStreamSynchronize(c->stream), "upload sync");
+}
+
 mc3_status launch_energy(mc3_ctx* c, double* out) {
-  hipLaunchKernelGGL(mc3::k_energy_f64, dim3(c->d.chains), dim3(256), 0, c->stream, out,
-                     c->at<uint32_t>(c->L.spins), c->at<double>(c->L.J64), c->d.N, c->d.Np, c->d.W, c->scale);
+  hipLaunchKernelGGL(mc3::k_energy_f64, dim3(c->pl.total_chains), dim3(256), 0, c->stream, out, c->ws, c->insts(),
+                     c->chain_inst());
   return check_launch(c, "energy kernel");
 }
 
-mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st, bool write_base) {
-  const Dims& d = c->d;
-  int stride = d.W + 1;
-  int T = (int)(65536 / ((size_t)stride * 4));
-  if (T < 64) {
-    stride = d.W;
-    T = (int)(65536 / ((size_t)stride * 4));
-  }
-  if (T > 256) T = 256;
-  T = (T / 64) * 64;
-  const size_t lds = (size_t)T * stride * 4;
-  const long long total = (long long)d.chains * d.M;
-  const int blocks = (int)((total + T - 1) / T);
-  hipLaunchKernelGGL(mc3::k_propose, dim3(blocks), dim3(T), lds, st, c->flips(step), c->roots(step), c->base(step),
-                     c->at<const uint32_t>(c->L.spins), write_base ? 1 : 0, d.chains, d.M, d.N, d.W, d.Bp, stride,
-                     c->cfg.kmin, c->cfg.kmax, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, c->key(),
-                     c->cfg.chain_base, step);
+// Proposal blocks [b0, b0 + nb) of the block table at `step`, on stream st.
+mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st, bool write_base, int b0, int nb) {
+  const Plan& pl = c->pl;
+  const size_t lds = (size_t)pl.prop_T * pl.prop_stride * 4;
+  hipLaunchKernelGGL(mc3::k_propose, dim3(nb), dim3(pl.prop_T), lds, st, c->ws, c->insts(),
+                     c->at<const mc3::PBlock>(pl.pblocks_off) + b0, c->roots(step), write_base ? 1 : 0,
+                     pl.prop_stride, c->metropolis() ? 1 : 0, c->key(), c->cfg.chain_base, step);
   return check_launch(c, "propose kernel");
 }
 
-mc3_status do_propose(mc3_ctx* c, uint32_t step) {
-  MC3_TRY(launch_propose(c, step, c->stream, true));
-  c->have_proposal = true;
-  c->have_scores = false;
-  c->proposal_step = step;
-  return MC3_OK;
+mc3_status propose_all(mc3_ctx* c, uint32_t step, hipStream_t st, bool write_base) {
+  return launch_propose(c, step, st, write_base, 0, (int)c->pl.pblocks.size());
 }
 
 mc3_status timing_collect(mc3_ctx* c, size_t i) {
@@ -214,75 +361,65 @@ mc3_status timing_collect(mc3_ctx* c, size_t i) {
   return MC3_OK;
 }
 
-mc3_status launch_score_kernel(mc3_ctx* c);
+// One scoring launch over `grid` entries of a unit table (the whole batch's, or one
+// instance's own), for the flip sets of the last proposal.
+mc3_status launch_score_units(mc3_ctx* c, size_t table_off, int grid) {
+  const uint32_t parity = c->proposal_step & 1u;
+  const mc3::Unit* units = c->at<const mc3::Unit>(table_off);
+  if (c->cfg.precision == MC3_SPLIT_BF16)
+    hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
+                       c->roots(c->proposal_step), parity);
+  else
+    hipLaunchKernelGGL(mc3::k_score_f64, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
+                       c->roots(c->proposal_step), parity);
+  return check_launch(c, "score kernel");
+}
+
+mc3_status score_timed(mc3_ctx* c, size_t table_off, int grid) {
+  if (!c->timing) return launch_score_units(c, table_off, grid);
+  const size_t i = c->t_next;
+  c->t_next = (c->t_next + 1) % c->t_start.size();
+  MC3_TRY(timing_collect(c, i));
+  MC3_TRY(hip_ok(c, hipEventRecord(c->t_start[i], c->stream), "timing event"));
+  MC3_TRY(launch_score_units(c, table_off, grid));
+  MC3_TRY(hip_ok(c, hipEventRecord(c->t_stop[i], c->stream), "timing event"));
+  c->t_pending[i] = 1;
+  return MC3_OK;
+}
 
 mc3_status do_score(mc3_ctx* c, double* E_out) {
-  const Dims& d = c->d;
-  if (c->timing) {
-    const size_t i = c->t_next;
-    c->t_next = (c->t_next + 1) % c->t_start.size();
-    MC3_TRY(timing_collect(c, i));
-    MC3_TRY(hip_ok(c, hipEventRecord(c->t_start[i], c->stream), "timing event"));
-    MC3_TRY(launch_score_kernel(c));
-    MC3_TRY(hip_ok(c, hipEventRecord(c->t_stop[i], c->stream), "timing event"));
-    c->t_pending[i] = 1;
-  } else {
-    MC3_TRY(launch_score_kernel(c));
-  }
+  const Plan& pl = c->pl;
+  MC3_TRY(score_timed(c, pl.units_global_off, (int)pl.units_global.size()));
   if (E_out) {
-    hipLaunchKernelGGL(mc3::k_column_energies, dim3((d.B + 255) / 256), dim3(256), 0, c->stream,
-                       c->at<double>(c->L.Ecol), c->at<const double>(c->L.partial), d.P, d.Bp, d.B, c->scale);
-    MC3_TRY(check_launch(c, "column energy kernel"));
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(E_out, c->at<double>(c->L.Ecol), (size_t)d.B * 8, hipMemcpyDeviceToDevice,
-                                     c->stream), "copy energies"));
+    for (const InstH& h : pl.inst) {
+      hipLaunchKernelGGL(mc3::k_column_energies, dim3((h.B + 255) / 256), dim3(256), 0, c->stream, E_out + h.col0,
+                         c->at<const double>(h.partial), h.P, h.Bp, h.B, h.scale);
+      MC3_TRY(check_launch(c, "column energy kernel"));
+    }
   }
   c->have_scores = true;
   return MC3_OK;
 }
 
-mc3_status launch_score_kernel(mc3_ctx* c) {
-  const Dims& d = c->d;
-  const uint32_t t = c->proposal_step;
-  if (c->cfg.precision == MC3_SPLIT_BF16) {
-    const int TN = 128 * c->split_cf;
-    const int CT = d.Bp / TN;
-    const int U = d.P * CT;
-    const int grid = 8 * ((U + 7) / 8);
-    if (c->split_cf == 4)
-      hipLaunchKernelGGL(mc3::k_score_split<4>, dim3(grid), dim3(256), 0, c->stream, c->at<const uint4>(c->L.Jpack),
-                         c->flips(t), c->base(t), c->roots(t), c->at<double>(c->L.partial), d.chains, d.M, d.Np,
-                         d.Bp, d.NB, d.P, CT);
-    else
-      hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(256), 0, c->stream, c->at<const uint4>(c->L.Jpack),
-                         c->flips(t), c->base(t), c->roots(t), c->at<double>(c->L.partial), d.chains, d.M, d.Np,
-                         d.Bp, d.NB, d.P, CT);
-  } else {
-    const int CT = d.Bp / 128;
-    const int U = d.P * CT;
-    const int grid = 8 * ((U + 7) / 8);
-    hipLaunchKernelGGL(mc3::k_score_f64, dim3(grid), dim3(256), 0, c->stream, c->at<const double>(c->L.Jpack),
-                       c->flips(t), c->base(t), c->roots(t), c->at<double>(c->L.partial), d.chains, d.M, d.Np, d.Bp,
-                       d.NB, d.P, CT);
-  }
-  return check_launch(c, "score kernel");
+// Selection of global chains [g0, g0 + n) at `step`; with next_base, also the base
+// words of step+1 (whose flip sets and roots must already be proposed).
+mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n) {
+  const Plan& pl = c->pl;
+  const size_t lds = (size_t)(pl.Mmax + 1) * 16 + (size_t)pl.Wmax * 4;
+  hipLaunchKernelGGL(mc3::k_select, dim3(n), dim3(256), lds, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
+                     pl.total_chains, c->at<double>(pl.e_cur), c->roots(step), c->roots(step + 1u),
+                     c->at<mc3::Record>(pl.ring), c->at<unsigned long long>(pl.moves),
+                     c->at<unsigned long long>(pl.near), c->at<double>(pl.minm), c->at<double>(pl.e_bar),
+                     c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base, step, c->cfg.trace_steps,
+                     next_base ? 1 : 0);
+  return check_launch(c, "select kernel");
 }
 
-// Selection of step `step`; with next_base, also the base words of step+1 (whose
-// flip sets and roots must already be proposed).
-mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = false) {
-  const Dims& d = c->d;
-  const size_t lds = (size_t)(d.M + 1) * 16 + (size_t)d.W * 4;
-  hipLaunchKernelGGL(mc3::k_select, dim3(d.chains), dim3(256), lds, c->stream, c->at<uint32_t>(c->L.spins),
-                     c->at<double>(c->L.e_cur), c->flips(step), c->base(step), c->at<const double>(c->L.partial), d.P,
-                     c->scale, c->roots(step), c->at<mc3::Record>(c->L.ring), c->at<unsigned long long>(c->L.moves),
-                     c->at<unsigned long long>(c->L.near), c->at<double>(c->L.minm), c->at<double>(c->L.e_bar),
-                     d.chains, d.M, d.W, d.Bp, c->cfg.rule == MC3_RULE_METROPOLIS ? 1 : 0, beta, c->tol, c->key(),
-                     c->cfg.chain_base, step, c->cfg.trace_steps, next_base ? 1 : 0, c->flips(step + 1u),
-                     c->roots(step + 1u), c->base(step + 1u));
-  MC3_TRY(check_launch(c, "select kernel"));
+mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
+  const Plan& pl = c->pl;
   if (c->cfg.mean_steps > 0) {
-    hipLaunchKernelGGL(mc3::k_chain_means, dim3(1), dim3(256), 0, c->stream, c->at<double>(c->L.means),
-                       c->at<const double>(c->L.e_cur), c->at<const double>(c->L.e_bar), d.chains,
+    hipLaunchKernelGGL(mc3::k_chain_means, dim3(1), dim3(256), 0, c->stream, c->at<double>(pl.means),
+                       c->at<const double>(pl.e_cur), c->at<const double>(pl.e_bar), pl.total_chains,
                        step % (uint32_t)c->cfg.mean_steps, step);
     MC3_TRY(check_launch(c, "means kernel"));
   }
@@ -291,6 +428,11 @@ mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = fa
   if (next_base) c->proposal_step = step + 1u;
   c->steps_done += 1;
   return MC3_OK;
+}
+
+mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = false) {
+  MC3_TRY(launch_select(c, step, beta, next_base, 0, c->pl.total_chains));
+  return after_select(c, step, next_base);
 }
 
 double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
@@ -308,7 +450,7 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
   MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[0], c->stream), "event"));
   MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[1], c->stream), "event"));
   MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[step0 & 1u], 0), "wait"));
-  MC3_TRY(launch_propose(c, step0, c->aux, true));
+  MC3_TRY(propose_all(c, step0, c->aux, true));
   MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[step0 & 1u], c->aux), "event"));
   MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_prop[step0 & 1u], 0), "wait"));
   c->have_proposal = true;
@@ -319,7 +461,7 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
     if (!last) {
       const uint32_t t1 = t + 1u;
       MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[t1 & 1u], 0), "wait"));
-      MC3_TRY(launch_propose(c, t1, c->aux, false));
+      MC3_TRY(propose_all(c, t1, c->aux, false));
       MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[t1 & 1u], c->aux), "event"));
     }
     MC3_TRY(do_score(c, nullptr));
@@ -331,24 +473,33 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
   return MC3_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* mc3_version(void) { return "mc3 0.1 (gfx950)"; }
-
-mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes) {
-  if (validate(cfg) || !bytes) return MC3_E_ARG;
-  *bytes = layout_of(*cfg).total;
+// The same steps with one propose, one score and one select launch per instance,
+// in instance order on the caller's stream: what running the instances one by one
+// costs, against which the batched launches are measured.
+mc3_status do_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1,
+                                  int64_t total) {
+  const Plan& pl = c->pl;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint32_t t = step0 + (uint32_t)i;
+    const double beta = beta_at(t, beta0, beta1, total);
+    c->proposal_step = t;
+    for (const InstH& h : pl.inst) {
+      MC3_TRY(launch_propose(c, t, c->stream, true, h.pblock_off, h.pblock_cnt));
+      MC3_TRY(score_timed(c, pl.units_local_off + (size_t)h.unit_off * sizeof(mc3::Unit), h.unit_grid));
+      MC3_TRY(launch_select(c, t, beta, false, h.chain0, h.desc.chains));
+    }
+    MC3_TRY(after_select(c, t, false));
+  }
+  c->have_proposal = false;
   return MC3_OK;
 }
 
-mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out) {
+mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out) {
   if (!out) return MC3_E_ARG;
   *out = nullptr;
-  if (validate(cfg)) return MC3_E_ARG;
-  const Layout L = layout_of(*cfg);
-  if (!workspace || bytes < L.total || ((uintptr_t)workspace % kAlign) != 0) return MC3_E_WORKSPACE;
+  if (validate_batch(cfg)) return MC3_E_ARG;
+  Plan plan = make_plan(*cfg);
+  if (!workspace || bytes < plan.total || ((uintptr_t)workspace % kAlign) != 0) return MC3_E_WORKSPACE;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MC3_E_DEVICE;
   hipPointerAttribute_t attr;
@@ -359,8 +510,9 @@ mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void
   mc3_ctx* c = new (std::nothrow) mc3_ctx();
   if (!c) return MC3_E_ARG;
   c->cfg = *cfg;
-  c->d = dims_of(*cfg);
-  c->L = L;
+  c->descs.assign(cfg->instances, cfg->instances + cfg->n_instances);
+  c->cfg.instances = c->descs.data();
+  c->pl = std::move(plan);
   c->ws = (char*)workspace;
   c->stream = (hipStream_t)stream;
   c->device = dev;
@@ -373,15 +525,99 @@ mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void
     mc3_destroy(c);
     return MC3_E_DEVICE;
   }
-  if (const char* e = std::getenv("MC3_SPLIT_CF")) {
-    if (std::strcmp(e, "4") == 0) c->split_cf = 4;
-  }
   if (cfg->near_tie_tol >= 0.0)
     c->tol = cfg->near_tie_tol;
   else
     c->tol = cfg->precision == MC3_SPLIT_BF16 ? 1e-4 : 1e-9;
+  // the static tables
+  const Plan& P = c->pl;
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return n ? hipMemcpyAsync(c->at<char>(off), src, n, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+  };
+  hipError_t e = up(P.chain_inst_off, P.chain_inst.data(), P.chain_inst.size() * 4);
+  if (e == hipSuccess) e = up(P.units_global_off, P.units_global.data(), P.units_global.size() * sizeof(mc3::Unit));
+  if (e == hipSuccess) e = up(P.units_local_off, P.units_local.data(), P.units_local.size() * sizeof(mc3::Unit));
+  if (e == hipSuccess) e = up(P.pblocks_off, P.pblocks.data(), P.pblocks.size() * sizeof(mc3::PBlock));
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess || upload_insts(c) != MC3_OK) {
+    mc3_destroy(c);
+    return MC3_E_DEVICE;
+  }
   *out = c;
   return MC3_OK;
+}
+
+mc3_status init_couplings_impl(mc3_ctx* c, int32_t instance, const double* J, int64_t ld, double scale) {
+  MC3_TRY(usable(c));
+  if (instance < 0 || instance >= (int32_t)c->pl.inst.size())
+    return fail(c, MC3_E_ARG, "instance %d is not in the batch", instance);
+  InstH& h = c->pl.inst[instance];
+  const int N = h.desc.N, Np = h.Np;
+  if (!J || ld < N) return fail(c, MC3_E_ARG, "J is NULL or ld < N");
+  if (!std::isfinite(scale)) return fail(c, MC3_E_NUMERIC, "scale is not finite");
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j)
+      if (!std::isfinite(J[(size_t)i * ld + j])) return fail(c, MC3_E_NUMERIC, "J[%d][%d] is not finite", i, j);
+  double* J64 = c->at<double>(h.J64);
+  MC3_TRY(hip_ok(c, hipMemsetAsync(J64, 0, (size_t)Np * Np * 8, c->stream), "clear J"));
+  MC3_TRY(hip_ok(c, hipMemcpy2DAsync(J64, (size_t)Np * 8, J, (size_t)ld * 8, (size_t)N * 8, N, hipMemcpyHostToDevice,
+                                     c->stream), "upload J"));
+  if (c->cfg.precision == MC3_SPLIT_BF16) {
+    const long long n = (long long)(Np / 32) * (Np / 16) * 64;
+    hipLaunchKernelGGL(mc3::k_pack_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->at<uint4>(h.Jpack), J64, Np);
+  } else {
+    const long long n = (long long)(Np / 16) * (Np / 4) * 64;
+    hipLaunchKernelGGL(mc3::k_pack_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->at<double>(h.Jpack), J64, Np);
+  }
+  MC3_TRY(check_launch(c, "pack kernel"));
+  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_couplings sync"));
+  h.scale = scale;
+  h.have_J = true;
+  c->have_chains = false;
+  return upload_insts(c);
+}
+
+mc3_status step_args(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1) {
+  MC3_TRY(usable(c));
+  if (!c->have_chains) return fail(c, MC3_E_STATE, "step_n before init_chains");
+  if (n < 0 || (uint64_t)step0 + (uint64_t)n > 0x100000000ull) return fail(c, MC3_E_ARG, "bad step range");
+  if (!std::isfinite(beta0) || !std::isfinite(beta1) || beta0 < 0.0 || beta1 < 0.0)
+    return fail(c, MC3_E_ARG, "beta must be finite and >= 0");
+  return MC3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mc3_version(void) { return "mc3 0.2 (gfx950)"; }
+
+mc3_status mc3_batch_workspace_size(const mc3_batch_config* cfg, size_t* bytes) {
+  if (validate_batch(cfg) || !bytes) return MC3_E_ARG;
+  *bytes = make_plan(*cfg).total;
+  return MC3_OK;
+}
+
+mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes) {
+  if (!cfg) return MC3_E_ARG;
+  mc3_instance_desc one;
+  const mc3_batch_config b = single_to_batch(cfg, &one);
+  return mc3_batch_workspace_size(&b, bytes);
+}
+
+mc3_status mc3_batch_create(const mc3_batch_config* cfg, void* workspace, size_t bytes, void* stream,
+                            mc3_ctx** out) {
+  return create_impl(cfg, workspace, bytes, stream, out);
+}
+
+mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out) {
+  if (out) *out = nullptr;
+  if (!cfg) return MC3_E_ARG;
+  mc3_instance_desc one;
+  const mc3_batch_config b = single_to_batch(cfg, &one);
+  return create_impl(&b, workspace, bytes, stream, out);
 }
 
 mc3_status mc3_destroy(mc3_ctx* ctx) {
@@ -401,82 +637,70 @@ mc3_status mc3_destroy(mc3_ctx* ctx) {
 }
 
 mc3_status mc3_init_couplings(mc3_ctx* c, const double* J, int64_t ld, double scale) {
-  MC3_TRY(usable(c));
-  const Dims& d = c->d;
-  if (!J || ld < d.N) return fail(c, MC3_E_ARG, "J is NULL or ld < N");
-  if (!std::isfinite(scale)) return fail(c, MC3_E_NUMERIC, "scale is not finite");
-  for (int i = 0; i < d.N; ++i)
-    for (int j = i + 1; j < d.N; ++j)
-      if (!std::isfinite(J[(size_t)i * ld + j])) return fail(c, MC3_E_NUMERIC, "J[%d][%d] is not finite", i, j);
-  double* J64 = c->at<double>(c->L.J64);
-  MC3_TRY(hip_ok(c, hipMemsetAsync(J64, 0, (size_t)d.Np * d.Np * 8, c->stream), "clear J"));
-  MC3_TRY(hip_ok(c, hipMemcpy2DAsync(J64, (size_t)d.Np * 8, J, (size_t)ld * 8, (size_t)d.N * 8, d.N,
-                                     hipMemcpyHostToDevice, c->stream), "upload J"));
-  if (c->cfg.precision == MC3_SPLIT_BF16) {
-    const long long n = (long long)(d.Np / 32) * (d.Np / 16) * 64;
-    hipLaunchKernelGGL(mc3::k_pack_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->at<uint4>(c->L.Jpack), J64, d.Np);
-  } else {
-    const long long n = (long long)(d.Np / 16) * (d.Np / 4) * 64;
-    hipLaunchKernelGGL(mc3::k_pack_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->at<double>(c->L.Jpack), J64, d.Np);
-  }
-  MC3_TRY(check_launch(c, "pack kernel"));
-  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_couplings sync"));
-  c->scale = scale;
-  c->have_J = true;
-  c->have_chains = false;
-  return MC3_OK;
+  return init_couplings_impl(c, 0, J, ld, scale);
+}
+
+mc3_status mc3_init_couplings_instance(mc3_ctx* c, int32_t instance, const double* J, int64_t ld, double scale) {
+  return init_couplings_impl(c, instance, J, ld, scale);
 }
 
 mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
   MC3_TRY(usable(c));
-  if (!c->have_J) return fail(c, MC3_E_STATE, "init_chains before init_couplings");
-  const Dims& d = c->d;
-  uint32_t* sp = c->at<uint32_t>(c->L.spins);
+  if (!c->all_J()) return fail(c, MC3_E_STATE, "init_chains before init_couplings of every instance");
+  const Plan& pl = c->pl;
+  const size_t C = (size_t)pl.total_chains;
   if (spins) {
-    std::vector<uint32_t> bits((size_t)d.chains * d.W, 0u);
-    for (int ch = 0; ch < d.chains; ++ch)
-      for (int i = 0; i < d.N; ++i) {
-        const int8_t v = spins[(size_t)ch * d.N + i];
-        if (v != 1 && v != -1) return fail(c, MC3_E_ARG, "spin [%d][%d] is not +-1", ch, i);
-        if (v == -1) bits[(size_t)ch * d.W + i / 32] |= 1u << (i % 32);
-      }
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(sp, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, c->stream),
-                   "upload spins"));
-    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
+    size_t off = 0;
+    std::vector<uint32_t> bits;
+    for (const InstH& h : pl.inst) {
+      bits.assign((size_t)h.desc.chains * h.W, 0u);
+      for (int ch = 0; ch < h.desc.chains; ++ch)
+        for (int i = 0; i < h.desc.N; ++i) {
+          const int8_t v = spins[off + (size_t)ch * h.desc.N + i];
+          if (v != 1 && v != -1) return fail(c, MC3_E_ARG, "spin [%d][%d] is not +-1", h.chain0 + ch, i);
+          if (v == -1) bits[(size_t)ch * h.W + i / 32] |= 1u << (i % 32);
+        }
+      off += (size_t)h.desc.chains * h.desc.N;
+      MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<uint32_t>(h.spins), bits.data(), bits.size() * 4,
+                                       hipMemcpyHostToDevice, c->stream), "upload spins"));
+      MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
+    }
   } else {
-    hipLaunchKernelGGL(mc3::k_init_spins, dim3((d.W + 63) / 64, d.chains), dim3(64), 0, c->stream, sp, d.chains, d.N,
-                       d.W, c->key(), c->cfg.chain_base);
+    hipLaunchKernelGGL(mc3::k_init_spins, dim3((pl.Wmax + 63) / 64, pl.total_chains), dim3(64), 0, c->stream, c->ws,
+                       c->insts(), c->chain_inst(), pl.total_chains, c->key(), c->cfg.chain_base);
     MC3_TRY(check_launch(c, "init spins kernel"));
   }
-  MC3_TRY(launch_energy(c, c->at<double>(c->L.e_cur)));
+  MC3_TRY(launch_energy(c, c->at<double>(pl.e_cur)));
   // flip-set padding columns and the zero base row must read as zero
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.flips), 0, (size_t)2 * d.W * d.Bp * 4, c->stream), "clear"));
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.base), 0, (size_t)2 * (d.chains + 1) * d.W * 4, c->stream),
-                 "clear"));
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.moves), 0, (size_t)d.chains * 8, c->stream), "clear"));
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.near), 0, (size_t)d.chains * 8, c->stream), "clear"));
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(c->L.drift), 0, (size_t)d.chains * 8, c->stream), "clear"));
+  for (const InstH& h : pl.inst) {
+    for (int q = 0; q < 2; ++q) {
+      MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.flips[q]), 0, (size_t)h.W * h.Bp * 4, c->stream), "clear"));
+      MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.base[q]), 0, (size_t)(h.desc.chains + 1) * h.W * 4, c->stream),
+                     "clear"));
+    }
+  }
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.moves), 0, C * 8, c->stream), "clear"));
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.near), 0, C * 8, c->stream), "clear"));
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift), 0, C * 8, c->stream), "clear"));
   {
-    std::vector<double> big((size_t)d.chains, HUGE_VAL);
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(c->L.minm), big.data(), big.size() * 8, hipMemcpyHostToDevice,
+    std::vector<double> big(C, HUGE_VAL);
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.minm), big.data(), big.size() * 8, hipMemcpyHostToDevice,
                                      c->stream), "init margins"));
     MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
   }
   if (c->cfg.trace_steps > 0) {
-    std::vector<mc3::Record> ring((size_t)c->cfg.trace_steps * d.chains);
+    std::vector<mc3::Record> ring((size_t)c->cfg.trace_steps * C);
     for (auto& r : ring) {
       std::memset(&r, 0, sizeof r);
       r.step = 0xFFFFFFFFu;
     }
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<mc3::Record>(c->L.ring), ring.data(), ring.size() * sizeof(mc3::Record),
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<mc3::Record>(pl.ring), ring.data(), ring.size() * sizeof(mc3::Record),
                                      hipMemcpyHostToDevice, c->stream), "clear ring"));
     MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
   }
   if (c->cfg.mean_steps > 0) {
     std::vector<double> tr((size_t)c->cfg.mean_steps * 3, -1.0);
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(c->L.means), tr.data(), tr.size() * 8, hipMemcpyHostToDevice,
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.means), tr.data(), tr.size() * 8, hipMemcpyHostToDevice,
                                      c->stream), "clear means"));
     MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
   }
@@ -489,7 +713,11 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
 mc3_status mc3_propose(mc3_ctx* c, uint32_t step) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "propose before init_chains");
-  return do_propose(c, step);
+  MC3_TRY(propose_all(c, step, c->stream, true));
+  c->have_proposal = true;
+  c->have_scores = false;
+  c->proposal_step = step;
+  return MC3_OK;
 }
 
 mc3_status mc3_score_candidates(mc3_ctx* c, double* E_out) {
@@ -501,73 +729,80 @@ mc3_status mc3_score_candidates(mc3_ctx* c, double* E_out) {
 mc3_status mc3_select(mc3_ctx* c, uint32_t step, double beta) {
   MC3_TRY(usable(c));
   if (!c->have_scores) return fail(c, MC3_E_STATE, "select before score_candidates");
-  if (step != c->proposal_step) return fail(c, MC3_E_ARG, "select step %u differs from propose step %u", step,
-                                            c->proposal_step);
+  if (step != c->proposal_step)
+    return fail(c, MC3_E_ARG, "select step %u differs from propose step %u", step, c->proposal_step);
   if (!std::isfinite(beta) || beta < 0.0) return fail(c, MC3_E_ARG, "beta must be finite and >= 0");
   return do_select(c, step, beta);
 }
 
 mc3_status mc3_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
-  MC3_TRY(usable(c));
-  if (!c->have_chains) return fail(c, MC3_E_STATE, "step_n before init_chains");
-  if (n < 0 || (uint64_t)step0 + (uint64_t)n > 0x100000000ull) return fail(c, MC3_E_ARG, "bad step range");
-  if (!std::isfinite(beta0) || !std::isfinite(beta1) || beta0 < 0.0 || beta1 < 0.0)
-    return fail(c, MC3_E_ARG, "beta must be finite and >= 0");
+  MC3_TRY(step_args(c, step0, n, beta0, beta1));
   return do_step_n(c, step0, n, beta0, beta1, total);
+}
+
+mc3_status mc3_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1,
+                                   int64_t total) {
+  MC3_TRY(step_args(c, step0, n, beta0, beta1));
+  return do_step_n_per_instance(c, step0, n, beta0, beta1, total);
 }
 
 mc3_status mc3_recompute(mc3_ctx* c) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "recompute before init_chains");
-  const Dims& d = c->d;
-  MC3_TRY(launch_energy(c, c->at<double>(c->L.erecomp)));
-  std::vector<double> er(d.chains), ec(d.chains), dr(d.chains);
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(er.data(), c->at<double>(c->L.erecomp), (size_t)d.chains * 8,
-                                   hipMemcpyDeviceToHost, c->stream), "read energies"));
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(ec.data(), c->at<double>(c->L.e_cur), (size_t)d.chains * 8, hipMemcpyDeviceToHost,
-                                   c->stream), "read energies"));
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(dr.data(), c->at<double>(c->L.drift), (size_t)d.chains * 8, hipMemcpyDeviceToHost,
-                                   c->stream), "read drift"));
+  const Plan& pl = c->pl;
+  const size_t C = (size_t)pl.total_chains;
+  MC3_TRY(launch_energy(c, c->at<double>(pl.erecomp)));
+  std::vector<double> er(C), ec(C), dr(C);
+  MC3_TRY(hip_ok(c, hipMemcpyAsync(er.data(), c->at<double>(pl.erecomp), C * 8, hipMemcpyDeviceToHost, c->stream),
+                 "read energies"));
+  MC3_TRY(hip_ok(c, hipMemcpyAsync(ec.data(), c->at<double>(pl.e_cur), C * 8, hipMemcpyDeviceToHost, c->stream),
+                 "read energies"));
+  MC3_TRY(hip_ok(c, hipMemcpyAsync(dr.data(), c->at<double>(pl.drift), C * 8, hipMemcpyDeviceToHost, c->stream),
+                 "read drift"));
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "recompute sync"));
-  for (int i = 0; i < d.chains; ++i) {
+  for (size_t i = 0; i < C; ++i) {
     const double x = std::fabs(ec[i] - er[i]);
     if (x > dr[i]) dr[i] = x;
   }
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(c->L.drift), dr.data(), (size_t)d.chains * 8, hipMemcpyHostToDevice,
-                                   c->stream), "write drift"));
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(c->L.e_cur), er.data(), (size_t)d.chains * 8, hipMemcpyHostToDevice,
-                                   c->stream), "write energies"));
+  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.drift), dr.data(), C * 8, hipMemcpyHostToDevice, c->stream),
+                 "write drift"));
+  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.e_cur), er.data(), C * 8, hipMemcpyHostToDevice, c->stream),
+                 "write energies"));
   return hip_ok(c, hipStreamSynchronize(c->stream), "recompute sync");
 }
 
 mc3_status mc3_measure(mc3_ctx* c, double* e_cur, uint32_t* spin_bits, mc3_summary* summary) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "measure before init_chains");
-  const Dims& d = c->d;
+  const Plan& pl = c->pl;
+  const size_t C = (size_t)pl.total_chains;
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "measure sync"));
   if (e_cur)
-    MC3_TRY(hip_ok(c, hipMemcpy(e_cur, c->at<double>(c->L.e_cur), (size_t)d.chains * 8, hipMemcpyDeviceToHost),
-                   "read energies"));
+    MC3_TRY(hip_ok(c, hipMemcpy(e_cur, c->at<double>(pl.e_cur), C * 8, hipMemcpyDeviceToHost), "read energies"));
   if (spin_bits) {
-    std::vector<uint32_t> b((size_t)d.chains * d.W);
-    MC3_TRY(hip_ok(c, hipMemcpy(b.data(), c->at<uint32_t>(c->L.spins), b.size() * 4, hipMemcpyDeviceToHost),
-                   "read spins"));
-    for (int ch = 0; ch < d.chains; ++ch)
-      std::memcpy(spin_bits + (size_t)ch * d.Wn, b.data() + (size_t)ch * d.W, (size_t)d.Wn * 4);
+    std::memset(spin_bits, 0, C * pl.Wn_max * 4);
+    std::vector<uint32_t> b;
+    for (const InstH& h : pl.inst) {
+      b.resize((size_t)h.desc.chains * h.W);
+      MC3_TRY(hip_ok(c, hipMemcpy(b.data(), c->at<uint32_t>(h.spins), b.size() * 4, hipMemcpyDeviceToHost),
+                     "read spins"));
+      for (int ch = 0; ch < h.desc.chains; ++ch)
+        std::memcpy(spin_bits + (size_t)(h.chain0 + ch) * pl.Wn_max, b.data() + (size_t)ch * h.W, (size_t)h.Wn * 4);
+    }
   }
   if (summary) {
-    std::vector<unsigned long long> mv(d.chains), nt(d.chains);
-    std::vector<double> mm(d.chains), dr(d.chains);
-    MC3_TRY(hip_ok(c, hipMemcpy(mv.data(), c->at<char>(c->L.moves), (size_t)d.chains * 8, hipMemcpyDeviceToHost), "read"));
-    MC3_TRY(hip_ok(c, hipMemcpy(nt.data(), c->at<char>(c->L.near), (size_t)d.chains * 8, hipMemcpyDeviceToHost), "read"));
-    MC3_TRY(hip_ok(c, hipMemcpy(mm.data(), c->at<char>(c->L.minm), (size_t)d.chains * 8, hipMemcpyDeviceToHost), "read"));
-    MC3_TRY(hip_ok(c, hipMemcpy(dr.data(), c->at<char>(c->L.drift), (size_t)d.chains * 8, hipMemcpyDeviceToHost), "read"));
+    std::vector<unsigned long long> mv(C), nt(C);
+    std::vector<double> mm(C), dr(C);
+    MC3_TRY(hip_ok(c, hipMemcpy(mv.data(), c->at<char>(pl.moves), C * 8, hipMemcpyDeviceToHost), "read"));
+    MC3_TRY(hip_ok(c, hipMemcpy(nt.data(), c->at<char>(pl.near), C * 8, hipMemcpyDeviceToHost), "read"));
+    MC3_TRY(hip_ok(c, hipMemcpy(mm.data(), c->at<char>(pl.minm), C * 8, hipMemcpyDeviceToHost), "read"));
+    MC3_TRY(hip_ok(c, hipMemcpy(dr.data(), c->at<char>(pl.drift), C * 8, hipMemcpyDeviceToHost), "read"));
     summary->steps_done = c->steps_done;
     summary->moves = 0;
     summary->near_ties = 0;
     summary->min_margin = HUGE_VAL;
     summary->max_drift = 0.0;
-    for (int i = 0; i < d.chains; ++i) {
+    for (size_t i = 0; i < C; ++i) {
       summary->moves += (int64_t)mv[i];
       summary->near_ties += (int64_t)nt[i];
       if (mm[i] < summary->min_margin) summary->min_margin = mm[i];
@@ -579,7 +814,7 @@ mc3_status mc3_measure(mc3_ctx* c, double* e_cur, uint32_t* spin_bits, mc3_summa
 
 mc3_status mc3_read_records(mc3_ctx* c, uint32_t first, int32_t n, mc3_record* out) {
   MC3_TRY(usable(c));
-  const Dims& d = c->d;
+  const size_t C = (size_t)c->pl.total_chains;
   if (n < 0 || !out) return fail(c, MC3_E_ARG, "bad arguments");
   if (n > c->cfg.trace_steps) return fail(c, MC3_E_ARG, "more steps than the ring holds");
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_records sync"));
@@ -587,11 +822,10 @@ mc3_status mc3_read_records(mc3_ctx* c, uint32_t first, int32_t n, mc3_record* o
   for (int32_t i = 0; i < n; ++i) {
     const uint32_t st = first + (uint32_t)i;
     const size_t slot = (size_t)(st % (uint32_t)c->cfg.trace_steps);
-    MC3_TRY(hip_ok(c, hipMemcpy(out + (size_t)i * d.chains, c->at<mc3::Record>(c->L.ring) + slot * d.chains,
-                                (size_t)d.chains * sizeof(mc3_record), hipMemcpyDeviceToHost), "read ring"));
-    for (int ch = 0; ch < d.chains; ++ch)
-      if (out[(size_t)i * d.chains + ch].step != st)
-        return fail(c, MC3_E_ARG, "step %u is not in the ring", st);
+    MC3_TRY(hip_ok(c, hipMemcpy(out + (size_t)i * C, c->at<mc3::Record>(c->pl.ring) + slot * C,
+                                C * sizeof(mc3_record), hipMemcpyDeviceToHost), "read ring"));
+    for (size_t ch = 0; ch < C; ++ch)
+      if (out[(size_t)i * C + ch].step != st) return fail(c, MC3_E_ARG, "step %u is not in the ring", st);
   }
   return MC3_OK;
 }
@@ -599,21 +833,25 @@ mc3_status mc3_read_records(mc3_ctx* c, uint32_t first, int32_t n, mc3_record* o
 mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
   MC3_TRY(usable(c));
   if (!c->have_proposal) return fail(c, MC3_E_STATE, "no proposal to read");
-  const Dims& d = c->d;
+  if (c->pl.inst.size() != 1) return fail(c, MC3_E_UNSUPPORTED, "read_candidates needs a single-instance context");
+  const InstH& h = c->pl.inst[0];
+  const uint32_t st = c->proposal_step;
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_candidates sync"));
   if (bits) {
-    const uint32_t st = c->proposal_step;
-    hipLaunchKernelGGL(mc3::k_build_candidates, dim3(d.Bp / 256, d.W), dim3(256), 0, c->stream,
-                       c->at<uint32_t>(c->L.candT), c->flips(st), c->base(st), c->roots(st), d.chains, d.M, d.W, d.Bp);
+    hipLaunchKernelGGL(mc3::k_build_candidates, dim3(h.Bp / 256, h.W), dim3(256), 0, c->stream,
+                       c->at<uint32_t>(c->pl.candT), c->at<const uint32_t>(h.flips[st & 1u]),
+                       c->at<const uint32_t>(h.base[st & 1u]), c->roots(st) + h.chain0, h.desc.chains, h.desc.M, h.W,
+                       h.Bp);
     MC3_TRY(check_launch(c, "candidate kernel"));
     MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_candidates sync"));
-    std::vector<uint32_t> t((size_t)d.W * d.Bp);
-    MC3_TRY(hip_ok(c, hipMemcpy(t.data(), c->at<uint32_t>(c->L.candT), t.size() * 4, hipMemcpyDeviceToHost), "read"));
-    for (int col = 0; col < d.B; ++col)
-      for (int w = 0; w < d.Wn; ++w) bits[(size_t)col * d.Wn + w] = t[(size_t)w * d.Bp + col];
+    std::vector<uint32_t> t((size_t)h.W * h.Bp);
+    MC3_TRY(hip_ok(c, hipMemcpy(t.data(), c->at<uint32_t>(c->pl.candT), t.size() * 4, hipMemcpyDeviceToHost),
+                   "read"));
+    for (int col = 0; col < h.B; ++col)
+      for (int w = 0; w < h.Wn; ++w) bits[(size_t)col * h.Wn + w] = t[(size_t)w * h.Bp + col];
   }
   if (roots)
-    MC3_TRY(hip_ok(c, hipMemcpy(roots, c->roots(c->proposal_step), (size_t)d.chains * 4, hipMemcpyDeviceToHost),
+    MC3_TRY(hip_ok(c, hipMemcpy(roots, c->roots(st) + h.chain0, (size_t)h.desc.chains * 4, hipMemcpyDeviceToHost),
                    "read roots"));
   return MC3_OK;
 }
@@ -654,7 +892,7 @@ mc3_status mc3_read_means(mc3_ctx* c, uint32_t first, int32_t n, double* out) {
   if (n > c->cfg.mean_steps) return fail(c, MC3_E_ARG, "more steps than the trace holds");
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_means sync"));
   std::vector<double> buf((size_t)c->cfg.mean_steps * 3);
-  MC3_TRY(hip_ok(c, hipMemcpy(buf.data(), c->at<double>(c->L.means), buf.size() * 8, hipMemcpyDeviceToHost),
+  MC3_TRY(hip_ok(c, hipMemcpy(buf.data(), c->at<double>(c->pl.means), buf.size() * 8, hipMemcpyDeviceToHost),
                  "read means"));
   for (int32_t i = 0; i < n; ++i) {
     const uint32_t st = first + (uint32_t)i;

@@ -102,6 +102,37 @@ def batch_instances(n_instances: int = 2000, seed: int = 0x5EED0004) -> List[Tup
     return [(int(n), int(m), int(max(1, n // 16))) for n, m in zip(Ns, Ms)]
 
 
+BATCH_CHAINS = 4       # chains per instance of the batching workload
+BATCH_BETA = 1.5
+BATCH_SEED = 0x5EED0004
+
+
+def batch_descs(n_instances: int = 2000, seed: int = BATCH_SEED, chains: int = BATCH_CHAINS):
+    """(N, M, chains, kmin, kmax) per instance of the batching workload: N = 64*U{1..32},
+    M ~ U{8..256}, `chains` chains, flip-set sizes U{1..N/16}."""
+    return [(N, M, chains, 1, kmax) for N, M, kmax in batch_instances(n_instances, seed)]
+
+
+def batch_couplings(i: int, N: int, seed: int = BATCH_SEED) -> Tuple[np.ndarray, float]:
+    """Gaussian couplings of instance i of the batching workload (its own stream)."""
+    return couplings_gauss(N, (seed << 20) + i)
+
+
+def iter_batch_couplings(descs, seed: int = BATCH_SEED, threads: int = 8):
+    """Yield (i, J, scale) for every instance in order; matrices are drawn on a small
+    thread pool (numpy's generators release the GIL while filling)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        pending = {}
+        nxt = 0
+        for i in range(len(descs)):
+            while nxt < len(descs) and nxt < i + 2 * threads:
+                pending[nxt] = pool.submit(batch_couplings, nxt, descs[nxt][0], seed)
+                nxt += 1
+            J, scale = pending.pop(i).result()
+            yield i, J, scale
+
+
 def beta_schedule(beta0: float, beta1: float, total: int, t0: int, n: int) -> np.ndarray:
     """Linear anneal beta_t = beta0 + (beta1 - beta0) * t / (total - 1), t = t0..t0+n-1."""
     t = np.arange(t0, t0 + n, dtype=np.float64)

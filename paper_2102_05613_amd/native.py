@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "MC3_OK", -1: "MC3_E_ARG", -3: "MC3_E_DEVICE", -4: "MC3_E_STA
 EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_couplings", "mc3_init_chains",
            "mc3_propose", "mc3_score_candidates", "mc3_select", "mc3_step_n", "mc3_recompute", "mc3_measure",
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
-           "mc3_sync", "mc3_last_error", "mc3_version"]
+           "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
+           "mc3_init_couplings_instance", "mc3_step_n_per_instance"]
 
 
 class Config(ctypes.Structure):
@@ -38,6 +39,18 @@ class Config(ctypes.Structure):
                 ("rule", ctypes.c_int32), ("trace_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("chain_base", ctypes.c_uint32), ("mean_steps", ctypes.c_int32),
                 ("near_tie_tol", ctypes.c_double)]
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("chains", ctypes.c_int32),
+                ("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int32), ("precision", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("trace_steps", ctypes.c_int32), ("mean_steps", ctypes.c_int32), ("chain_base", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("near_tie_tol", ctypes.c_double),
+                ("instances", ctypes.POINTER(InstanceDesc))]
 
 
 class Summary(ctypes.Structure):
@@ -86,6 +99,10 @@ def lib() -> ctypes.CDLL:
     L.mc3_timing_enable.argtypes = [vp, c.c_int32]
     L.mc3_timing_read.argtypes = [vp, P(c.c_double), P(c.c_int64)]
     L.mc3_sync.argtypes = [vp]
+    L.mc3_batch_workspace_size.argtypes = [P(BatchConfig), P(c.c_size_t)]
+    L.mc3_batch_create.argtypes = [P(BatchConfig), vp, c.c_size_t, vp, P(vp)]
+    L.mc3_init_couplings_instance.argtypes = [vp, c.c_int32, P(c.c_double), c.c_int64, c.c_double]
+    L.mc3_step_n_per_instance.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
     L.mc3_last_error.argtypes = [vp]
     L.mc3_last_error.restype = c.c_char_p
     L.mc3_version.restype = c.c_char_p
@@ -103,28 +120,49 @@ def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: st
                   mean_steps, near_tie_tol)
 
 
-def workspace_size(cfg: Config) -> int:
+def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcmcmc", trace_steps: int = 0,
+                      seed: int = 0, chain_base: int = 0, near_tie_tol: float = -1.0,
+                      mean_steps: int = 0) -> BatchConfig:
+    """instances: sequence of (N, M, chains, kmin, kmax)."""
+    arr = (InstanceDesc * len(instances))(*[InstanceDesc(*map(int, d)) for d in instances])
+    cfg = BatchConfig(len(instances), PRECISIONS[precision], RULES[rule], trace_steps, mean_steps, chain_base, seed,
+                      near_tie_tol, ctypes.cast(arr, ctypes.POINTER(InstanceDesc)))
+    cfg._keep = arr   # the descriptor array lives as long as the config
+    return cfg
+
+
+def workspace_size(cfg) -> int:
     n = ctypes.c_size_t()
-    st = lib().mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n))
+    if isinstance(cfg, BatchConfig):
+        st = lib().mc3_batch_workspace_size(ctypes.byref(cfg), ctypes.byref(n))
+    else:
+        st = lib().mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n))
     if st != MC3_OK:
         raise MC3Error(st, "mc3_workspace_size")
     return int(n.value)
 
 
 class Context:
-    """One SK instance with its chains on the current GPU."""
+    """One SK instance (Config) or a batch of instances (BatchConfig) with their
+    chains on the current GPU."""
 
-    def __init__(self, cfg: Config, device=None):
+    def __init__(self, cfg, device=None):
         import torch
         self.cfg = cfg
-        self.N, self.M, self.chains = cfg.N, cfg.M, cfg.chains
-        self.words = (cfg.N + 31) // 32
+        if isinstance(cfg, BatchConfig):
+            self.instances = [(d.N, d.M, d.chains, d.kmin, d.kmax) for d in cfg.instances[:cfg.n_instances]]
+        else:
+            self.instances = [(cfg.N, cfg.M, cfg.chains, cfg.kmin, cfg.kmax)]
+        self.N, self.M = self.instances[0][0], self.instances[0][1]
+        self.chains = sum(d[2] for d in self.instances)
+        self.words = max((d[0] + 31) // 32 for d in self.instances)
         nbytes = workspace_size(cfg)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
         self.stream = torch.cuda.current_stream(self.workspace.device)
         h = ctypes.c_void_p()
-        st = lib().mc3_create(ctypes.byref(cfg), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
-                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        create = lib().mc3_batch_create if isinstance(cfg, BatchConfig) else lib().mc3_create
+        st = create(ctypes.byref(cfg), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != MC3_OK:
             raise MC3Error(st, "mc3_create")
         self.h = h
@@ -145,17 +183,21 @@ class Context:
             pass
 
     # -- the ABI calls
-    def init_couplings(self, J: np.ndarray, scale: float):
+    def init_couplings(self, J: np.ndarray, scale: float, instance: int = 0):
+        N = self.instances[instance][0]
         J = np.ascontiguousarray(J, dtype=np.float64)
-        assert J.shape == (self.N, self.N)
-        self._check(lib().mc3_init_couplings(self.h, J.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.N,
-                                             float(scale)), "mc3_init_couplings")
+        assert J.shape == (N, N)
+        self._check(lib().mc3_init_couplings_instance(self.h, instance,
+                                                      J.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), N,
+                                                      float(scale)), "mc3_init_couplings_instance")
 
     def init_chains(self, spins: Optional[np.ndarray] = None):
+        """spins: None, or int8 [chains, N] (one instance) / the instances' blocks
+        [chains_i * N_i] one after another (a batch)."""
         p = None
         if spins is not None:
             spins = np.ascontiguousarray(spins, dtype=np.int8)
-            assert spins.shape == (self.chains, self.N)
+            assert spins.size == sum(d[0] * d[2] for d in self.instances)
             p = spins.ctypes.data
         self._check(lib().mc3_init_chains(self.h, p), "mc3_init_chains")
 
@@ -172,6 +214,10 @@ class Context:
 
     def step_n(self, step0: int, n: int, beta0: float, beta1: float, total: int):
         self._check(lib().mc3_step_n(self.h, step0, n, float(beta0), float(beta1), total), "mc3_step_n")
+
+    def step_n_per_instance(self, step0: int, n: int, beta0: float, beta1: float, total: int):
+        self._check(lib().mc3_step_n_per_instance(self.h, step0, n, float(beta0), float(beta1), total),
+                    "mc3_step_n_per_instance")
 
     def recompute(self):
         self._check(lib().mc3_recompute(self.h), "mc3_recompute")

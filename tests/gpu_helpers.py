@@ -43,7 +43,7 @@ def oracle_candidates(seed, chain, step, N, M, kmin, kmax, s, rule="mcmcmc"):
 
 
 def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas, rule, energy_rtol,
-                       exact=False):
+                       exact=False, chain_base=0):
     """Run the oracle over the same steps, taking the GPU's pick at the steps the GPU
     flagged as near ties (guided replay), and compare every record."""
     steps = len(betas)
@@ -52,7 +52,7 @@ def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas,
         forced[:] = -1
     ro = oracle.run(J, scale, N, M, chains, kmin, kmax, seed, betas,
                     rule=oracle.RULE_METROPOLIS if rule == "metropolis" else oracle.RULE_MCMCMC,
-                    forced=forced)
+                    forced=forced, chain_base=chain_base)
     orec = ro["rec"]
     assert np.array_equal(gpu_rec["r"], orec["r"]), "roots differ"
     bad = np.argwhere(gpu_rec["vstar"] != orec["vstar"])

@@ -46,6 +46,9 @@ def test_struct_layout_matches_header():
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mc3_config), offsetof(mc3_config, seed),
          offsetof(mc3_config, near_tie_tol), sizeof(mc3_record), offsetof(mc3_record, margin), sizeof(mc3_summary));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(mc3_instance_desc), sizeof(mc3_batch_config),
+         offsetof(mc3_batch_config, chain_base), offsetof(mc3_batch_config, seed),
+         offsetof(mc3_batch_config, instances));
   return 0;
 }
 '''
@@ -57,7 +60,10 @@ int main(void) {
         vals = [int(x) for x in subprocess.check_output([exe]).split()]
     assert vals == [ctypes.sizeof(native.Config), native.Config.seed.offset, native.Config.near_tie_tol.offset,
                     native.RECORD_DTYPE.itemsize, native.RECORD_DTYPE.fields["margin"][1],
-                    ctypes.sizeof(native.Summary)]
+                    ctypes.sizeof(native.Summary),
+                    ctypes.sizeof(native.InstanceDesc), ctypes.sizeof(native.BatchConfig),
+                    native.BatchConfig.chain_base.offset, native.BatchConfig.seed.offset,
+                    native.BatchConfig.instances.offset]
 
 
 def test_version(lib):
@@ -103,3 +109,57 @@ def test_bitset_helpers_roundtrip():
     rng = np.random.Generator(np.random.PCG64(0))
     s = np.where(rng.random((3, 77)) < 0.5, -1, 1).astype(np.int8)
     assert np.array_equal(native.bits_to_spins(native.spins_to_bits(s), 77), s)
+
+
+def _batch_ws(lib, cfg):
+    n = ctypes.c_size_t()
+    return lib.mc3_batch_workspace_size(ctypes.byref(cfg), ctypes.byref(n)), n.value
+
+
+def test_batch_single_instance_matches_single_config(lib):
+    for prec in ("fp64", "split_bf16"):
+        for shape in [(64, 4, 2, 1, 4), (1024, 128, 256, 1, 128), (8192, 1024, 32, 256, 256)]:
+            single = native.workspace_size(native.make_config(*shape, precision=prec, trace_steps=3, mean_steps=5))
+            st, n = _batch_ws(lib, native.make_batch_config([shape], precision=prec, trace_steps=3, mean_steps=5))
+            assert st == native.MC3_OK and n == single
+
+
+def test_batch_workspace_grows_with_instances(lib):
+    one = (64, 8, 4, 1, 8)
+    sizes = []
+    for k in (1, 2, 10, 2000):
+        st, n = _batch_ws(lib, native.make_batch_config([one] * k, precision="split_bf16"))
+        assert st == native.MC3_OK
+        sizes.append(n)
+    assert sizes == sorted(sizes) and sizes[-1] < 2000 * sizes[0] + 2 ** 20
+
+
+@pytest.mark.parametrize("bad", [dict(N=1), dict(M=0), dict(kmax=65), dict(chains=0), dict(M=2, rule="metropolis")])
+def test_batch_rejects_any_invalid_instance(lib, bad):
+    good = dict(N=64, M=4, chains=2, kmin=1, kmax=4)
+    b = dict(good)
+    rule = bad.pop("rule", "mcmcmc")
+    b.update(bad)
+    if rule == "metropolis":
+        good = dict(good, M=1)
+    descs = [tuple(good.values()), tuple(b.values()), tuple(good.values())]
+    cfg = native.make_batch_config(descs, rule=rule)
+    assert _batch_ws(lib, cfg)[0] == native.MC3_E_ARG
+    h = ctypes.c_void_p()
+    assert lib.mc3_batch_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h)) == native.MC3_E_ARG
+
+
+def test_batch_rejects_bad_header_fields(lib):
+    descs = [(64, 4, 2, 1, 4)]
+    cfg = native.make_batch_config(descs)
+    cfg.n_instances = 0
+    assert _batch_ws(lib, cfg)[0] == native.MC3_E_ARG
+    cfg = native.make_batch_config(descs)
+    cfg.instances = ctypes.POINTER(native.InstanceDesc)()
+    assert _batch_ws(lib, cfg)[0] == native.MC3_E_ARG
+    cfg = native.make_batch_config(descs, chain_base=2 ** 28 - 1)
+    assert _batch_ws(lib, cfg)[0] == native.MC3_E_ARG
+    cfg = native.make_batch_config(descs, trace_steps=-2)
+    assert _batch_ws(lib, cfg)[0] == native.MC3_E_ARG
+    assert lib.mc3_init_couplings_instance(None, 0, None, 0, 1.0) == native.MC3_E_ARG
+    assert lib.mc3_step_n_per_instance(None, 0, 1, 1.0, 1.0, 1) == native.MC3_E_ARG
