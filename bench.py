@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "candidate configs scored/s + steps-to-thermalize, SK N=1024, mixed vs FP64"
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix peak
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
 def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0):
@@ -132,6 +133,120 @@ def _thermalize(w, J, scale, T):
     }
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed_steps(ctx, step0, n, beta0, beta1, total):
+    """Wall time (torch events on the context's stream) of n steps of mc3_step_n."""
+    import torch
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    ctx.step_n(step0, n, beta0, beta1, total)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end)
+
+
+def _small_workload(w, steps):
+    """Latency-bound shapes: microseconds per step of the whole path (propose, score,
+    select) for the configured rule and, at N = 32, the two M = 1 rules as well."""
+    J, scale = w.couplings_matrix()
+    variants = [("mcmcmc_m%d" % w.M, "mcmcmc", w.M, w.kmin, w.kmax)]
+    if w.N == 32:
+        variants += [("mcmcmc_m1_heat_bath", "mcmcmc", 1, 1, 1), ("metropolis_m1", "metropolis", 1, 1, 1)]
+    out = {"N": w.N, "chains": w.chains, "precision": w.precision, "steps": steps,
+           "beta": [w.beta0, w.beta1], "bound": "launch latency (no roofline applies)"}
+    for name, rule, M, kmin, kmax in variants:
+        ctx = _context(w, w.precision, rule, M, kmin, kmax, J, scale)
+        ctx.step_n(0, 100, w.beta0, w.beta0, 1)
+        ms = _timed_steps(ctx, 100, steps, w.beta0, w.beta1, w.steps)
+        ctx.close()
+        out[name] = {"M": M, "us_per_step": ms * 1e3 / steps,
+                     "candidates_per_s": w.chains * M * steps / (ms / 1e3)}
+    return out
+
+
+def _batched_workload(args):
+    """2000 heterogeneous instances (N = 64..2048, M = 8..256, 4 chains each) stepped
+    by one propose, one score and one select launch per step, against one launch of
+    each per instance."""
+    from paper_2102_05613_amd import inputs, native
+    descs = inputs.batch_descs(args.batch_instances)
+    w = inputs.workload("sk_batch_rep_n1024_m128")
+    beta = inputs.BATCH_BETA
+    cfg = native.make_batch_config(descs, precision="split_bf16", seed=w.seed)
+    ctx = native.Context(cfg)
+    t0 = time.perf_counter()
+    for i, J, scale in inputs.iter_batch_couplings(descs):
+        ctx.init_couplings(J, scale, instance=i)
+    load_s = time.perf_counter() - t0
+    ctx.init_chains()
+    _log(f"batch: {len(descs)} instances loaded in {load_s:.1f} s")
+    ctx.step_n(0, 3, beta, beta, 1)
+    ctx.timing_enable(True)
+    ms = _timed_steps(ctx, 3, args.batch_steps, beta, beta, 1)
+    score_ms, launches = ctx.timing_read()
+    ctx.timing_enable(False)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_per = max(1, args.batch_steps // 4)
+    ctx.step_n_per_instance(3 + args.batch_steps, n_per, beta, beta, 1)
+    torch.cuda.synchronize()
+    per_ms = (time.perf_counter() - t0) * 1e3 / n_per
+    ctx.close()
+    Ns = np.array([d[0] for d in descs], dtype=np.float64)
+    Ms = np.array([d[1] for d in descs], dtype=np.float64)
+    Np = np.ceil(Ns / 128) * 128
+    cand = float(np.sum(Ms * inputs.BATCH_CHAINS))
+    flops = float(np.sum(3.0 * Ns * (Ns - 1) * Ms * inputs.BATCH_CHAINS))
+    jbytes = float(np.sum(3.0 * Np * (Np + 128)))   # split triangle incl. diagonal blocks, read once
+    score_s = score_ms / launches / 1e3
+    ms_step = ms / args.batch_steps
+    return {"instances": len(descs), "chains_per_instance": inputs.BATCH_CHAINS, "beta": beta,
+            "N_range": [int(Ns.min()), int(Ns.max())], "M_range": [int(Ms.min()), int(Ms.max())],
+            "candidates_per_step": cand, "steps": args.batch_steps,
+            "batched": {"ms_per_step": ms_step, "candidates_per_s": cand / (ms_step / 1e3),
+                        "score_kernel_ms": score_s * 1e3, "launches_per_step": 3},
+            "per_instance_launches": {"ms_per_step": per_ms, "candidates_per_s": cand / (per_ms / 1e3),
+                                      "steps": n_per, "launches_per_step": 3 * len(descs)},
+            "speedup_batched": per_ms / ms_step,
+            "score_roofline": {"flops_per_launch": flops, "achieved_tflops": flops / score_s / 1e12,
+                               "frac_mfma_bf16": flops / score_s / 1e12 / PEAK_BF16_TFLOPS,
+                               "j_bytes_per_launch": jbytes, "achieved_gbs_j_once": jbytes / score_s / 1e9,
+                               "frac_hbm_j_once": jbytes / score_s / 1e9 / PEAK_HBM_GBS},
+            "couplings_load_s": load_s}
+
+
+def _large_workload(args):
+    """N = 8192, 32 chains x M = 1024, 256-spin flip sets: split path timed at the
+    anneal's start, the FP64 path on a few steps."""
+    from paper_2102_05613_amd import inputs
+    w = inputs.workload("sk_n8192_m1024_split")
+    J, scale = w.couplings_matrix()
+    out = {"N": w.N, "M": w.M, "chains": w.chains, "k": [w.kmin, w.kmax], "beta": [w.beta0, w.beta1]}
+    for prec, steps in (("split_bf16", args.large_steps), ("fp64", max(2, args.large_steps // 8))):
+        ctx = _context(w, prec, "mcmcmc", w.M, w.kmin, w.kmax, J, scale)
+        ctx.step_n(0, 2, w.beta0, w.beta1, w.steps)
+        ctx.timing_enable(True)
+        ms = _timed_steps(ctx, 2, steps, w.beta0, w.beta1, w.steps)
+        score_ms, launches = ctx.timing_read()
+        ctx.close()
+        cand = w.chains * w.M
+        flops = (3.0 if prec == "split_bf16" else 1.0) * w.N * (w.N - 1) * cand
+        peak = PEAK_BF16_TFLOPS if prec == "split_bf16" else PEAK_FP64_TFLOPS
+        ach = flops / (score_ms / launches / 1e3) / 1e12
+        out[prec] = {"steps": steps, "ms_per_step": ms / steps, "candidates_per_s": cand * steps / (ms / 1e3),
+                     "score_kernel_ms": score_ms / launches, "achieved_tflops": ach, "peak_tflops": peak,
+                     "frac": ach / peak}
+        _log(f"large N=8192 {prec}: {ms / steps:.2f} ms/step")
+    return out
+
+
 def _cpu_baseline(w, J, scale, sample_chains):
     import oracle
     t0 = time.perf_counter()
@@ -152,6 +267,11 @@ def main():
     ap.add_argument("--thermalize-steps", type=int, default=20000)
     ap.add_argument("--cpu-chains", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--small-steps", type=int, default=10000,
+                    help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
+    ap.add_argument("--batch-instances", type=int, default=2000, help="0 skips the batched workload")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--large-steps", type=int, default=16, help="0 skips the N=8192 workload")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection run: one plain 512 MiB device copy (calibrates FETCH_SIZE/WRITE_SIZE), "
                          "then --steps split steps; prints nothing else")
@@ -179,7 +299,9 @@ def main():
         print(json.dumps({"profile_run": True, "copy_bytes": 512 * 2 ** 20, "steps": args.steps}))
         return
     split = _time_path(w, "split_bf16", args.steps, args.warmup, J, scale)
+    _log(f"headline split: {split['total_ms'] / args.steps:.4f} ms/step")
     fp64 = _time_path(w, "fp64", args.fp64_steps, min(args.warmup, 2), J, scale)
+    _log(f"headline fp64: {fp64['total_ms'] / args.fp64_steps:.4f} ms/step")
 
     cand = w.chains * w.M
     ms_step = split["total_ms"] / args.steps
@@ -208,8 +330,22 @@ def main():
     }
     if args.thermalize_steps > 0:
         out["steps_to_thermalize"] = _thermalize(w, J, scale, args.thermalize_steps)
+        _log("thermalization study done")
+    other = {}
+    if args.small_steps > 0:
+        for name in ("sk_n32_pm1_m4", "sk_n256_anneal_m16"):
+            other[name] = _small_workload(inputs.workload(name), args.small_steps)
+            _log(f"{name} done")
+    if args.batch_instances > 0:
+        other["sk_batch_2000_instances"] = _batched_workload(args)
+        _log("batched workload done")
+    if args.large_steps > 0:
+        other["sk_n8192_m1024_split"] = _large_workload(args)
+    if other:
+        out["other_workloads"] = other
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(w, J, scale, args.cpu_chains)
+        _log("cpu baseline done")
     print(json.dumps(out))
 
 

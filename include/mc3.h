@@ -134,10 +134,9 @@ mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes);
 
 /* Create a context on the current HIP device.  `workspace` is a device pointer of at
  * least mc3_workspace_size bytes, borrowed for the lifetime of the context; `stream`
- * is a hipStream_t (NULL = default stream), borrowed likewise.  Performs no device
- * memory allocation; creates one internal stream (default priority) and four events,
- * used by mc3_step_n to overlap the next step's proposal with the current scoring;
- * all work joins back into `stream`.  Validates the configuration before any HIP call. */
+ * is a hipStream_t (NULL = default stream), borrowed likewise; every kernel of the
+ * context runs on it.  Performs no device memory allocation and creates no stream.
+ * Validates the configuration before any HIP call. */
 mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out);
 
 /* Batch forms of mc3_workspace_size and mc3_create (same contracts).  Every call
@@ -201,7 +200,9 @@ mc3_status mc3_select(mc3_ctx* ctx, uint32_t step, double beta);
 
 /* n steps starting at global step step0: propose, score, select each step, with
  * beta_t = beta0 + (beta1 - beta0) * (t / (total - 1)) for t = step0 .. step0+n-1
- * (beta0 if total <= 1). */
+ * (beta0 if total <= 1).  Flip sets and roots do not depend on the states, so the
+ * proposals of up to 16 steps are drawn in one launch into a ring in the workspace;
+ * the results are those of the step-by-step calls. */
 mc3_status mc3_step_n(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
 
 /* The steps of mc3_step_n, launched instance by instance (propose, score and select

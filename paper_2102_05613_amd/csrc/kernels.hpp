@@ -8,11 +8,12 @@
 //           term t, stored as 64 lanes x 8 bf16 (lane l holds row 32R + l%32,
 //           k = 16S + 8(l/32) + e for e = 0..7); 1 KiB per fragment.
 //   spins   [chains][W] uint32 bitsets (set bit = spin -1).
-//   flipsT  [W][Bp] uint32: word w of the flip set F_{m+1} of edge m+1 of chain c at
-//           column c*M + m (columns contiguous, so a matrix-core B fragment's 32
-//           columns are one 128-byte line); padding columns stay zero.
-//   base    [chains+1][W] uint32: s ^ F_r (s if r = 0) per chain; row `chains` is
-//           zero (used by padding columns).
+//   flipsT  ring of slots, one step each, slot = step % slots; a slot is [W][Bp]
+//           uint32: word w of the flip set F_{m+1} of edge m+1 of chain c at column
+//           c*M + m (columns contiguous, so a matrix-core B fragment's 32 columns are
+//           one 128-byte line); padding columns stay zero.
+//   base    two [chains+1][W] uint32 buffers by step parity: s ^ F_r (s if r = 0)
+//           per chain; row `chains` is zero (used by padding columns).
 //   partial [P][Bp] double: energy contributions of row-block pair p.
 //
 // Candidate columns are never materialised on the hot path.  Column m of chain c is
@@ -42,8 +43,13 @@ struct Inst {
   int32_t chains, kmin, kmax, B;
   int32_t Bp, NB, P, chain0;
   double scale;
-  uint64_t J64, Jpack, flips[2], base[2], partial, spins;
+  uint64_t J64, Jpack, flips, flip_slot, base[2], partial, spins;
 };
+
+// Flip sets of the step held in ring slot `slot` (slots of flip_slot bytes each).
+__device__ __forceinline__ uint32_t* flips_at(char* ws, const Inst& in, uint32_t slot) {
+  return reinterpret_cast<uint32_t*>(ws + in.flips + (uint64_t)slot * in.flip_slot);
+}
 
 // A scoring work unit (row-block pair p, column tile ct of instance inst); inst < 0 is
 // an idle slot of the launch grid.
@@ -72,7 +78,7 @@ __global__ void k_init_spins(char* __restrict__ ws, const Inst* __restrict__ ins
   const int g = blockIdx.y;
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total_chains) return;
-  const Inst in = insts[chain_inst[g]];
+  const Inst& in = insts[chain_inst[g]];
   if (w >= in.W) return;
   const int c = g - in.chain0;
   uint32_t v = 0;
@@ -94,20 +100,25 @@ __device__ __forceinline__ int root_of(Key key, uint32_t gc, uint32_t step, int 
   return (int)randint(rb.x, (uint32_t)(M + 1));
 }
 
-// One thread per (chain, edge) of one instance (block table): k_e and Floyd's k-of-N
-// draw into the thread's own LDS bitset (row stride `stride` >= W words; W+1 where it
-// fits, so the final copy does not collide on banks), then every word written to
-// flipsT[w][chain*M + e-1] (consecutive threads, consecutive addresses).  Thread
-// (chain, edge 1) stores the chain's root.  With write_base, the thread of edge r
-// (edge 1 if r = 0) also writes base = s ^ F_r from the chain's current spins.
-// Dynamic LDS: blockDim.x * stride words.
+// Flip sets and roots do not depend on the chains' states, so several steps are
+// drawn in one launch: grid (proposal blocks, steps), step = step0 + blockIdx.y, its
+// results in ring slot step % nslots.  One thread per (chain, edge) of one instance
+// (block table): k_e and Floyd's k-of-N draw into the thread's own LDS bitset (row
+// stride `stride` >= W words; W+1 where it fits, so the final copy does not collide
+// on banks), then every word written to flipsT[w][chain*M + e-1] (consecutive
+// threads, consecutive addresses).  Thread (chain, edge 1) stores the chain's root in
+// roots_ring[slot][global chain].  With write_base, for the first step only, the
+// thread of edge r (edge 1 if r = 0) also writes base = s ^ F_r from the chain's
+// current spins.  Dynamic LDS: blockDim.x * stride words.
 __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts, const PBlock* __restrict__ blocks,
-                          int32_t* __restrict__ roots, int write_base, int stride, int metropolis, Key key,
-                          uint32_t chain_base, uint32_t step) {
+                          int32_t* __restrict__ roots_ring, int total_chains, uint32_t nslots, int write_base,
+                          int stride, int metropolis, Key key, uint32_t chain_base, uint32_t step0) {
   extern __shared__ uint32_t lds_bits[];
   const int T = blockDim.x;
+  const uint32_t step = step0 + blockIdx.y;
+  const uint32_t slot = step % nslots;
   const PBlock blk0 = blocks[blockIdx.x];
-  const Inst in = insts[blk0.inst];
+  const Inst& in = insts[blk0.inst];
   const int N = in.N, M = in.M, W = in.W, Bp = in.Bp;
   const long long total = (long long)in.chains * M;
   for (int i = threadIdx.x; i < T * stride; i += T) lds_bits[i] = 0u;
@@ -130,10 +141,10 @@ __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts,
     mine[pos >> 5] |= 1u << (pos & 31u);
   }
   const int r = root_of(key, gc, step, M, metropolis);
-  if (e == 1u) roots[in.chain0 + c] = (int32_t)r;
-  uint32_t* flipsT = ws_at<uint32_t>(ws, in.flips[step & 1u]);
+  if (e == 1u) roots_ring[(size_t)slot * total_chains + in.chain0 + c] = (int32_t)r;
+  uint32_t* flipsT = flips_at(ws, in, slot);
   for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = mine[w];
-  if (write_base && (int)e == (r == 0 ? 1 : r)) {
+  if (write_base && blockIdx.y == 0 && (int)e == (r == 0 ? 1 : r)) {
     uint32_t* base = ws_at<uint32_t>(ws, in.base[step & 1u]);
     const uint32_t* spins = ws_at<const uint32_t>(ws, in.spins);
     for (int w = 0; w < W; ++w) base[(size_t)c * W + w] = spins[(size_t)c * W + w] ^ (r ? mine[w] : 0u);
@@ -319,16 +330,16 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
 template <int CF>
 __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
     char* __restrict__ ws, const Inst* __restrict__ insts, const Unit* __restrict__ units,
-    const int32_t* __restrict__ roots_all, uint32_t parity) {
+    const int32_t* __restrict__ roots_all, uint32_t slot, uint32_t parity) {
   static_assert(CF % 2 == 0, "CF must be even (64-column copies)");
   constexpr int TN = 4 * 32 * CF;
   __shared__ SplitStage<CF> st0;
   __shared__ SplitStage<CF> st1;
   const Unit un = units[blockIdx.x];
   if (un.inst < 0) return;
-  const Inst in = insts[un.inst];
+  const Inst& in = insts[un.inst];
   const uint4* __restrict__ Apack = ws_at<const uint4>(ws, in.Jpack);
-  const uint32_t* __restrict__ flipsT = ws_at<const uint32_t>(ws, in.flips[parity]);
+  const uint32_t* __restrict__ flipsT = flips_at(ws, in, slot);
   const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[parity]);
   const int32_t* __restrict__ roots = roots_all + in.chain0;
   double* __restrict__ partial = ws_at<double>(ws, in.partial);
@@ -532,14 +543,15 @@ __device__ __forceinline__ void f64_mfma(f64x4 (&acc)[4][4], const F64Stage& st,
 // j + 16 (i % 4).
 __global__ __launch_bounds__(256, 2) void k_score_f64(char* __restrict__ ws, const Inst* __restrict__ insts,
                                                       const Unit* __restrict__ units,
-                                                      const int32_t* __restrict__ roots_all, uint32_t parity) {
+                                                      const int32_t* __restrict__ roots_all, uint32_t slot,
+                                                      uint32_t parity) {
   constexpr int TN = 128;
   __shared__ F64Stage fs0, fs1;
   const Unit un = units[blockIdx.x];
   if (un.inst < 0) return;
-  const Inst in = insts[un.inst];
+  const Inst& in = insts[un.inst];
   const double* __restrict__ Apack = ws_at<const double>(ws, in.Jpack);
-  const uint32_t* __restrict__ flipsT = ws_at<const uint32_t>(ws, in.flips[parity]);
+  const uint32_t* __restrict__ flipsT = flips_at(ws, in, slot);
   const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[parity]);
   const int32_t* __restrict__ roots = roots_all + in.chain0;
   double* __restrict__ partial = ws_at<double>(ws, in.partial);
@@ -711,21 +723,21 @@ __global__ __launch_bounds__(256) void k_select(
     int total_chains, double* __restrict__ e_cur, const int32_t* __restrict__ roots_all,
     const int32_t* __restrict__ roots_next_all, Record* __restrict__ ring, unsigned long long* __restrict__ moves,
     unsigned long long* __restrict__ near_ties, double* __restrict__ min_margin, double* __restrict__ e_bar_out,
-    int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, int trace_steps,
-    int next_base) {
+    int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, uint32_t slot,
+    uint32_t slot_next, int trace_steps, int next_base) {
   extern __shared__ double sel_lds[];
   __shared__ int sh_vstar;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = chain_off + blockIdx.x;   // global chain
   if (g >= total_chains) return;
-  const Inst in = insts[chain_inst[g]];
+  const Inst& in = insts[chain_inst[g]];
   const int c = g - in.chain0;            // chain within the instance
   const int M = in.M, W = in.W, Bp = in.Bp, P = in.P;
   const double scale = in.scale;
   uint32_t* __restrict__ spins = ws_at<uint32_t>(ws, in.spins);
-  const uint32_t* __restrict__ flipsT = ws_at<const uint32_t>(ws, in.flips[step & 1u]);
+  const uint32_t* __restrict__ flipsT = flips_at(ws, in, slot);
   const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[step & 1u]);
-  const uint32_t* __restrict__ flipsT_next = ws_at<const uint32_t>(ws, in.flips[(step + 1u) & 1u]);
+  const uint32_t* __restrict__ flipsT_next = flips_at(ws, in, slot_next);
   uint32_t* __restrict__ base_next = ws_at<uint32_t>(ws, in.base[(step + 1u) & 1u]);
   const double* __restrict__ partial = ws_at<const double>(ws, in.partial);
   const int32_t* __restrict__ roots = roots_all + in.chain0;
@@ -913,7 +925,7 @@ __global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, ch
                                                     const int32_t* __restrict__ chain_inst) {
   __shared__ double red[256];
   const int g = blockIdx.x;
-  const Inst in = insts[chain_inst[g]];
+  const Inst& in = insts[chain_inst[g]];
   const int c = g - in.chain0;
   const int N = in.N, Np = in.Np, W = in.W;
   const double scale = in.scale;

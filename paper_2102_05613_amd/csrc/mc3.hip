@@ -27,13 +27,16 @@ constexpr size_t kAlign = 256;
 constexpr int kColPad = 512;     // candidate columns of an instance are padded to this
 constexpr int kTileSplit = 256;  // columns per split-scoring unit (4 waves x 64)
 constexpr int kTileF64 = 128;    // columns per FP64-scoring unit
+constexpr int kMaxAhead = 16;    // steps of flip sets drawn per proposal launch, at most
+constexpr size_t kFlipBudget = size_t(512) << 20;  // bytes of flip-set ring, about
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct InstH {
   mc3_instance_desc desc;
   int Np, W, Wn, B, Bp, NB, P, chain0, col0;
-  size_t J64, Jpack, flips[2], base[2], partial, spins;  // byte offsets into the workspace
+  size_t J64, Jpack, flips, base[2], partial, spins;  // byte offsets into the workspace
+  size_t flip_slot;                                    // bytes of one step's flip sets
   double scale = 1.0;
   bool have_J = false;
   int unit_off = 0, unit_grid = 0;     // this instance's own unit table (per-instance launches)
@@ -44,6 +47,8 @@ struct Plan {
   std::vector<InstH> inst;
   int total_chains = 0, total_cols = 0, Wmax = 0, Wn_max = 0, Mmax = 0;
   int prop_T = 256, prop_stride = 1;
+  int ahead = 1;    // steps proposed per launch in mc3_step_n
+  int nslots = 2;   // flip-set and root ring slots (ahead + 1)
   std::vector<mc3::Unit> units_global, units_local;
   std::vector<mc3::PBlock> pblocks;
   std::vector<int32_t> chain_inst;
@@ -111,6 +116,12 @@ Plan make_plan(const mc3_batch_config& cfg) {
     pl.Wn_max = std::max(pl.Wn_max, h.Wn);
     pl.Mmax = std::max(pl.Mmax, d.M);
   }
+  // flip-set ring: `ahead` steps are proposed at once; one more slot holds the step
+  // being selected while the next group is written
+  size_t slot_bytes = 0;
+  for (const InstH& h : pl.inst) slot_bytes += (size_t)h.W * h.Bp * 4;
+  pl.ahead = (int)std::max<size_t>(1, std::min<size_t>(kMaxAhead, kFlipBudget / slot_bytes));
+  pl.nslots = pl.ahead + 1;
   // proposal blocks: one LDS bitset per thread, row stride W+1 where 64 threads fit
   pl.prop_stride = pl.Wmax + 1;
   int T = (int)(65536 / ((size_t)pl.prop_stride * 4));
@@ -173,7 +184,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
   pl.pblocks_off = take(pl.pblocks.size() * sizeof(mc3::PBlock));
   pl.e_cur = take(C * 8);
   pl.e_bar = take(C * 8);
-  pl.roots = take(2 * C * 4);  // two steps, by parity
+  pl.roots = take((size_t)pl.nslots * C * 4);
   pl.moves = take(C * 8);
   pl.near = take(C * 8);
   pl.minm = take(C * 8);
@@ -187,7 +198,8 @@ Plan make_plan(const mc3_batch_config& cfg) {
     const size_t np2 = (size_t)h.Np * h.Np;
     h.J64 = take(np2 * sizeof(double));
     h.Jpack = take(cfg.precision == MC3_SPLIT_BF16 ? np2 * 3 * sizeof(uint16_t) : np2 * sizeof(double));
-    for (int q = 0; q < 2; ++q) h.flips[q] = take((size_t)h.W * h.Bp * 4);
+    h.flip_slot = (size_t)h.W * h.Bp * 4;
+    h.flips = take((size_t)pl.nslots * h.flip_slot);
     for (int q = 0; q < 2; ++q) h.base[q] = take((size_t)(h.desc.chains + 1) * h.W * 4);
     h.partial = take((size_t)h.P * h.Bp * 8);
     h.spins = take((size_t)h.desc.chains * h.W * 4);
@@ -226,8 +238,6 @@ struct mc3_ctx {
   Plan pl;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
-  hipStream_t aux = nullptr;  // proposals of the next step run here, overlapping scoring
-  hipEvent_t ev_prop[2] = {nullptr, nullptr}, ev_sel[2] = {nullptr, nullptr};
   int device = 0;
   bool have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
   uint32_t proposal_step = 0;
@@ -245,7 +255,8 @@ struct mc3_ctx {
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   mc3::Key key() const { return mc3::Key{(uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32)}; }
-  int32_t* roots(uint32_t step) const { return at<int32_t>(pl.roots) + (size_t)(step & 1u) * pl.total_chains; }
+  uint32_t slot(uint32_t step) const { return step % (uint32_t)pl.nslots; }
+  int32_t* roots(uint32_t step) const { return at<int32_t>(pl.roots) + (size_t)slot(step) * pl.total_chains; }
   const mc3::Inst* insts() const { return at<const mc3::Inst>(pl.insts); }
   const int32_t* chain_inst() const { return at<const int32_t>(pl.chain_inst_off); }
   bool metropolis() const { return cfg.rule == MC3_RULE_METROPOLIS; }
@@ -318,8 +329,8 @@ mc3_status upload_insts(mc3_ctx* c) {
     d.scale = h.scale;
     d.J64 = h.J64;
     d.Jpack = h.Jpack;
-    d.flips[0] = h.flips[0];
-    d.flips[1] = h.flips[1];
+    d.flips = h.flips;
+    d.flip_slot = h.flip_slot;
     d.base[0] = h.base[0];
     d.base[1] = h.base[1];
     d.partial = h.partial;
@@ -336,18 +347,20 @@ mc3_status launch_energy(mc3_ctx* c, double* out) {
   return check_launch(c, "energy kernel");
 }
 
-// Proposal blocks [b0, b0 + nb) of the block table at `step`, on stream st.
-mc3_status launch_propose(mc3_ctx* c, uint32_t step, hipStream_t st, bool write_base, int b0, int nb) {
+// Proposal blocks [b0, b0 + nb) of the block table for steps step0 .. step0+nsteps-1
+// (at most nslots - 1 of them); with write_base, also the base words of step0.
+mc3_status launch_propose(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base, int b0, int nb) {
   const Plan& pl = c->pl;
   const size_t lds = (size_t)pl.prop_T * pl.prop_stride * 4;
-  hipLaunchKernelGGL(mc3::k_propose, dim3(nb), dim3(pl.prop_T), lds, st, c->ws, c->insts(),
-                     c->at<const mc3::PBlock>(pl.pblocks_off) + b0, c->roots(step), write_base ? 1 : 0,
-                     pl.prop_stride, c->metropolis() ? 1 : 0, c->key(), c->cfg.chain_base, step);
+  hipLaunchKernelGGL(mc3::k_propose, dim3(nb, nsteps), dim3(pl.prop_T), lds, c->stream, c->ws, c->insts(),
+                     c->at<const mc3::PBlock>(pl.pblocks_off) + b0, c->at<int32_t>(pl.roots), pl.total_chains,
+                     (uint32_t)pl.nslots, write_base ? 1 : 0, pl.prop_stride, c->metropolis() ? 1 : 0, c->key(),
+                     c->cfg.chain_base, step0);
   return check_launch(c, "propose kernel");
 }
 
-mc3_status propose_all(mc3_ctx* c, uint32_t step, hipStream_t st, bool write_base) {
-  return launch_propose(c, step, st, write_base, 0, (int)c->pl.pblocks.size());
+mc3_status propose_all(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base) {
+  return launch_propose(c, step0, nsteps, write_base, 0, (int)c->pl.pblocks.size());
 }
 
 mc3_status timing_collect(mc3_ctx* c, size_t i) {
@@ -364,14 +377,14 @@ mc3_status timing_collect(mc3_ctx* c, size_t i) {
 // One scoring launch over `grid` entries of a unit table (the whole batch's, or one
 // instance's own), for the flip sets of the last proposal.
 mc3_status launch_score_units(mc3_ctx* c, size_t table_off, int grid) {
-  const uint32_t parity = c->proposal_step & 1u;
+  const uint32_t t = c->proposal_step;
   const mc3::Unit* units = c->at<const mc3::Unit>(table_off);
   if (c->cfg.precision == MC3_SPLIT_BF16)
     hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
-                       c->roots(c->proposal_step), parity);
+                       c->roots(t), c->slot(t), t & 1u);
   else
     hipLaunchKernelGGL(mc3::k_score_f64, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
-                       c->roots(c->proposal_step), parity);
+                       c->roots(t), c->slot(t), t & 1u);
   return check_launch(c, "score kernel");
 }
 
@@ -410,8 +423,8 @@ mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base,
                      pl.total_chains, c->at<double>(pl.e_cur), c->roots(step), c->roots(step + 1u),
                      c->at<mc3::Record>(pl.ring), c->at<unsigned long long>(pl.moves),
                      c->at<unsigned long long>(pl.near), c->at<double>(pl.minm), c->at<double>(pl.e_bar),
-                     c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base, step, c->cfg.trace_steps,
-                     next_base ? 1 : 0);
+                     c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base, step, c->slot(step),
+                     c->slot(step + 1u), c->cfg.trace_steps, next_base ? 1 : 0);
   return check_launch(c, "select kernel");
 }
 
@@ -440,34 +453,24 @@ double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
   return beta0 + (beta1 - beta0) * ((double)t / (double)(total - 1));
 }
 
-// n steps with the proposal of step t+1 on the auxiliary stream, overlapping the
-// scoring of step t; the selection of step t also forms the base words of step t+1.
-// Flip sets, roots and base words are double-buffered by step parity: propose(t+1)
-// waits for select(t-1) (the last reader of its buffers); select(t) waits for
-// propose(t+1).  Everything joins back into the caller's stream.
+// n steps on the caller's stream.  Flip sets and roots do not depend on the states, so
+// they are drawn `ahead` steps per launch into the ring (slot = step % (ahead + 1));
+// the group of steps a .. a+ahead-1 is drawn just before select(a-1), which needs the
+// flip sets of step a for the base words a's scoring uses, and whose own slot is the
+// one slot the group does not touch.  Per step: one scoring launch and one selection
+// launch (which also forms the next step's base words).
 mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
   if (n <= 0) return MC3_OK;
-  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[0], c->stream), "event"));
-  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[1], c->stream), "event"));
-  MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[step0 & 1u], 0), "wait"));
-  MC3_TRY(propose_all(c, step0, c->aux, true));
-  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[step0 & 1u], c->aux), "event"));
-  MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_prop[step0 & 1u], 0), "wait"));
+  const int64_t K = c->pl.ahead;
+  MC3_TRY(propose_all(c, step0, (int)std::min<int64_t>(K, n), true));
   c->have_proposal = true;
   c->proposal_step = step0;
   for (int64_t i = 0; i < n; ++i) {
     const uint32_t t = step0 + (uint32_t)i;
     const bool last = i + 1 == n;
-    if (!last) {
-      const uint32_t t1 = t + 1u;
-      MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->aux, c->ev_sel[t1 & 1u], 0), "wait"));
-      MC3_TRY(propose_all(c, t1, c->aux, false));
-      MC3_TRY(hip_ok(c, hipEventRecord(c->ev_prop[t1 & 1u], c->aux), "event"));
-    }
     MC3_TRY(do_score(c, nullptr));
-    if (!last) MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_prop[(t + 1u) & 1u], 0), "wait"));
+    if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
     MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last));
-    MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel[t & 1u], c->stream), "event"));
   }
   c->have_proposal = false;
   return MC3_OK;
@@ -484,7 +487,7 @@ mc3_status do_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double 
     const double beta = beta_at(t, beta0, beta1, total);
     c->proposal_step = t;
     for (const InstH& h : pl.inst) {
-      MC3_TRY(launch_propose(c, t, c->stream, true, h.pblock_off, h.pblock_cnt));
+      MC3_TRY(launch_propose(c, t, 1, true, h.pblock_off, h.pblock_cnt));
       MC3_TRY(score_timed(c, pl.units_local_off + (size_t)h.unit_off * sizeof(mc3::Unit), h.unit_grid));
       MC3_TRY(launch_select(c, t, beta, false, h.chain0, h.desc.chains));
     }
@@ -516,15 +519,6 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
   c->ws = (char*)workspace;
   c->stream = (hipStream_t)stream;
   c->device = dev;
-  bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
-  for (int i = 0; i < 2 && ok; ++i) {
-    ok = hipEventCreateWithFlags(&c->ev_prop[i], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&c->ev_sel[i], hipEventDisableTiming) == hipSuccess;
-  }
-  if (!ok) {
-    mc3_destroy(c);
-    return MC3_E_DEVICE;
-  }
   if (cfg->near_tie_tol >= 0.0)
     c->tol = cfg->near_tie_tol;
   else
@@ -622,14 +616,6 @@ mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void
 
 mc3_status mc3_destroy(mc3_ctx* ctx) {
   if (!ctx) return MC3_E_ARG;
-  if (ctx->aux) {
-    (void)hipStreamSynchronize(ctx->aux);
-    (void)hipStreamDestroy(ctx->aux);
-  }
-  for (int i = 0; i < 2; ++i) {
-    if (ctx->ev_prop[i]) (void)hipEventDestroy(ctx->ev_prop[i]);
-    if (ctx->ev_sel[i]) (void)hipEventDestroy(ctx->ev_sel[i]);
-  }
   for (hipEvent_t e : ctx->t_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
   delete ctx;
@@ -673,11 +659,10 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
   MC3_TRY(launch_energy(c, c->at<double>(pl.e_cur)));
   // flip-set padding columns and the zero base row must read as zero
   for (const InstH& h : pl.inst) {
-    for (int q = 0; q < 2; ++q) {
-      MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.flips[q]), 0, (size_t)h.W * h.Bp * 4, c->stream), "clear"));
+    MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.flips), 0, (size_t)pl.nslots * h.flip_slot, c->stream), "clear"));
+    for (int q = 0; q < 2; ++q)
       MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.base[q]), 0, (size_t)(h.desc.chains + 1) * h.W * 4, c->stream),
                      "clear"));
-    }
   }
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.moves), 0, C * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.near), 0, C * 8, c->stream), "clear"));
@@ -713,7 +698,7 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
 mc3_status mc3_propose(mc3_ctx* c, uint32_t step) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "propose before init_chains");
-  MC3_TRY(propose_all(c, step, c->stream, true));
+  MC3_TRY(propose_all(c, step, 1, true));
   c->have_proposal = true;
   c->have_scores = false;
   c->proposal_step = step;
@@ -839,7 +824,7 @@ mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
   MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "read_candidates sync"));
   if (bits) {
     hipLaunchKernelGGL(mc3::k_build_candidates, dim3(h.Bp / 256, h.W), dim3(256), 0, c->stream,
-                       c->at<uint32_t>(c->pl.candT), c->at<const uint32_t>(h.flips[st & 1u]),
+                       c->at<uint32_t>(c->pl.candT), c->at<const uint32_t>(h.flips + c->slot(st) * h.flip_slot),
                        c->at<const uint32_t>(h.base[st & 1u]), c->roots(st) + h.chain0, h.desc.chains, h.desc.M, h.W,
                        h.Bp);
     MC3_TRY(check_launch(c, "candidate kernel"));

@@ -87,8 +87,8 @@ def test_invalid_configs_rejected(lib, kw):
 def test_workspace_size_and_missing_workspace(lib):
     cfg = native.make_config(1024, 128, 256, 1, 128, precision="split_bf16", trace_steps=10)
     n = native.workspace_size(cfg)
-    # J64 (8 MiB) + split J (6 MiB) + candidates (4 MiB) + ...
-    assert 18 * 2 ** 20 < n < 40 * 2 ** 20
+    # J64 (8 MiB) + split J (6 MiB) + a ring of 17 steps of flip sets (4 MiB each) + ...
+    assert 18 * 2 ** 20 + 17 * 4 * 2 ** 20 < n < 128 * 2 ** 20
     cfg2 = native.make_config(1024, 128, 512, 1, 128, precision="split_bf16", trace_steps=10)
     assert native.workspace_size(cfg2) > n
     h = ctypes.c_void_p()
