@@ -35,6 +35,38 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_score_split_sk_n1024_m128_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the device sources (kernels and RNG header), to tie counter
+    measurements to the kernel they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hpp", "device_rng.hpp"):
+        with open(os.path.join(ROOT, "paper_2102_05613_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _traffic_from_profile():
+    """HBM bytes per scoring launch from the committed FETCH_SIZE / WRITE_SIZE counter
+    runs (each scaled by the plain-copy calibration), or None when the kernel sources
+    have changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None, "no counter profile"
+    rec = None
+    for line in open(TRAFFIC_PROFILE):
+        line = line.strip()
+        if line.startswith("{") and '"source_sha256"' in line:
+            rec = json.loads(line)
+    if rec is None:
+        return None, "counter profile has no record"
+    if rec["source_sha256"] != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return rec, "measured"
+
+
 def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0):
     from paper_2102_05613_amd import native
     cfg = native.make_config(w.N, M, w.chains, kmin, kmax, precision=precision, rule=rule, seed=w.seed,
@@ -309,6 +341,13 @@ def main():
     fp64_ms_step = fp64["total_ms"] / args.fp64_steps
     flops_split = 3.0 * w.N * (w.N - 1) * cand     # three BF16 terms, strict upper triangle
     flops_fp64 = 1.0 * w.N * (w.N - 1) * cand
+    Np = -(-w.N // 128) * 128
+    Bp = -(-cand // 512) * 512
+    algo_bytes = (3.0 * Np * (Np + 128)          # split J triangle (3 BF16 terms), read once
+                  + (Np // 32) * Bp * 4.0        # flip-set words of every column
+                  + (w.chains + 1) * (Np // 32) * 4.0   # base words
+                  + (Np // 256) * Bp * 8.0)      # FP64 partial energies written
+    traffic, traffic_note = _traffic_from_profile()
     achieved = flops_split / (split["score_ms_avg"] / 1e3) / 1e12
     achieved64 = flops_fp64 / (fp64["score_ms_avg"] / 1e3) / 1e12
     out = {
@@ -318,7 +357,10 @@ def main():
         "config": {"workload": w.name, "N": w.N, "M": w.M, "chains": w.chains, "kmin": w.kmin, "kmax": w.kmax,
                    "beta": w.beta0, "precision": "split_bf16 (hi+mid+lo, fp32 accumulate, fp64 epilogue)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_BF16_TFLOPS,
+                     "traffic": None if traffic is None else traffic["fetch_bytes"] + traffic["write_bytes"],
+                     "traffic_detail": {"status": traffic_note, "algorithmic_bytes": algo_bytes,
+                                        **({} if traffic is None else traffic)},
                      "kernel": "k_score_split", "kernel_ms": split["score_ms_avg"],
                      "flops_per_launch": flops_split},
         "fp64_path": {"value": cand / (fp64_ms_step / 1e3), "unit": "candidates/s", "ms_per_step": fp64_ms_step,
