@@ -39,11 +39,11 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_score_split_sk_n1024_m128_tr
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the device sources (kernels and RNG header), to tie counter
+    """sha256 over the sources the split scoring kernel is built from, to tie counter
     measurements to the kernel they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hpp", "device_rng.hpp"):
+    for name in ("common.hpp", "device_rng.hpp", "score_split.hpp"):
         with open(os.path.join(ROOT, "paper_2102_05613_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -67,10 +67,10 @@ def _traffic_from_profile():
     return rec, "measured"
 
 
-def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0):
+def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0, scorer="gemm"):
     from paper_2102_05613_amd import native
     cfg = native.make_config(w.N, M, w.chains, kmin, kmax, precision=precision, rule=rule, seed=w.seed,
-                             mean_steps=mean_steps)
+                             mean_steps=mean_steps, scorer=scorer)
     ctx = native.Context(cfg)
     ctx.init_couplings(J, scale)
     ctx.init_chains()
@@ -121,15 +121,19 @@ def _t_within(e, ref, window, tol=0.01):
 
 
 def _thermalize_study(w, J, scale, T, beta, k_edge, label):
-    """MCMCMC (split-BF16 and FP64, M = w.M, flip sets of k_edge = (kmin, kmax)) and
-    single-flip Metropolis on the same instance, chains and initial states."""
+    """MCMCMC (split-BF16 and FP64 pair sums, and the FP64 field-update scorer where
+    the flip sets are small enough; M = w.M, flip sets of k_edge = (kmin, kmax)) and
+    single-flip Metropolis (field-update scorer) on the same instance, chains and
+    initial states."""
     import torch
     runs = {}
-    specs = [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, k_edge[0], k_edge[1]),
-             ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1]),
-             ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1)]
-    for name, prec, rule, M, kmin, kmax in specs:
-        ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T)
+    specs = [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm"),
+             ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm")]
+    if k_edge[1] <= 16:
+        specs.append(("mcmcmc_fp64_field_update", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "delta"))
+    specs.append(("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta"))
+    for name, prec, rule, M, kmin, kmax, scorer in specs:
+        ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T, scorer=scorer)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.step_n(0, T, beta, beta, 1)
@@ -137,7 +141,7 @@ def _thermalize_study(w, J, scale, T, beta, k_edge, label):
         wall = time.perf_counter() - t0
         means = ctx.read_means(0, T) / w.N
         ctx.close()
-        runs[name] = {"wall_s": wall, "e_bar": means[:, 1], "M": M}
+        runs[name] = {"wall_s": wall, "e_bar": means[:, 1], "M": M, "scorer": scorer}
     tail = {name: float(np.mean(r["e_bar"][-T // 4:])) for name, r in runs.items()}
     ref = min(tail.values())
     window = max(10, T // 100)
@@ -149,7 +153,8 @@ def _thermalize_study(w, J, scale, T, beta, k_edge, label):
         out[name] = {"t_steps": t if t is not None else f"> {T}",
                      "t_seconds": None if t is None else t * per_step_s,
                      "t_candidates": None if t is None else t * w.chains * r["M"],
-                     "tail_energy_per_spin": tail[name], "ms_per_step": per_step_s * 1e3}
+                     "tail_energy_per_spin": tail[name], "ms_per_step": per_step_s * 1e3,
+                     "scorer": r["scorer"]}
     return out
 
 
@@ -191,14 +196,18 @@ def _small_workload(w, steps):
     if w.N == 32:
         variants += [("mcmcmc_m1_heat_bath", "mcmcmc", 1, 1, 1), ("metropolis_m1", "metropolis", 1, 1, 1)]
     out = {"N": w.N, "chains": w.chains, "precision": w.precision, "steps": steps,
-           "beta": [w.beta0, w.beta1], "bound": "launch latency (no roofline applies)"}
+           "beta": [w.beta0, w.beta1], "bound": "launch latency (no roofline applies)",
+           "scorers": {"gemm": "pair sums on the matrix cores, one scoring and one selection launch per step",
+                       "delta": "FP64 field update, every step of a chain in one persistent workgroup"}}
     for name, rule, M, kmin, kmax in variants:
-        ctx = _context(w, w.precision, rule, M, kmin, kmax, J, scale)
-        ctx.step_n(0, 100, w.beta0, w.beta0, 1)
-        ms = _timed_steps(ctx, 100, steps, w.beta0, w.beta1, w.steps)
-        ctx.close()
-        out[name] = {"M": M, "us_per_step": ms * 1e3 / steps,
-                     "candidates_per_s": w.chains * M * steps / (ms / 1e3)}
+        out[name] = {"M": M}
+        for scorer in ("gemm", "delta"):
+            ctx = _context(w, w.precision, rule, M, kmin, kmax, J, scale, scorer=scorer)
+            ctx.step_n(0, 100, w.beta0, w.beta0, 1)
+            ms = _timed_steps(ctx, 100, steps, w.beta0, w.beta1, w.steps)
+            ctx.close()
+            out[name][scorer] = {"us_per_step": ms * 1e3 / steps,
+                                 "candidates_per_s": w.chains * M * steps / (ms / 1e3)}
     return out
 
 

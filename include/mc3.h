@@ -65,6 +65,26 @@ typedef enum {
     MC3_RULE_METROPOLIS = 1  /* single proposal, Metropolis rate; requires M == 1 */
 } mc3_rule;
 
+/* How node energies are obtained.
+ *   GEMM:  every candidate's energy from the dense pair sum, J.S on the matrix cores
+ *          (precision as configured); any flip-set size.
+ *   DELTA: energies as differences from the current state, in FP64: the device keeps
+ *          U = sum_{i<j} J_ij s_i s_j and the local field h = J s per chain, and node v
+ *          differs from the current node by the path flip set D = F_r xor F_v, so
+ *          dU = -2 sum_{i in D} s_i h_i + 4 sum_{i<j in D} J_ij s_i s_j (|D| + |D|^2/2
+ *          couplings per candidate instead of N^2); a move updates h with the |D|
+ *          rows of J.  All steps of a chain run in one persistent workgroup.  Limits:
+ *          kmax <= 16, M <= 512, N <= 4096 and the per-chain state within 64 KiB of
+ *          LDS (MC3_E_UNSUPPORTED otherwise); only mc3_step_n moves the chains
+ *          (mc3_propose, mc3_score_candidates, mc3_select, mc3_read_candidates and
+ *          mc3_step_n_per_instance return MC3_E_UNSUPPORTED).  `precision` is unused.
+ *   AUTO:  DELTA where its limits hold and kmax <= 8, else GEMM. */
+typedef enum {
+    MC3_SCORER_GEMM = 0,
+    MC3_SCORER_DELTA = 1,
+    MC3_SCORER_AUTO = 2
+} mc3_scorer;
+
 /* One SK instance and its chains.  Constraints: 2 <= N <= 8192, 1 <= M <= 4000,
  * 1 <= chains, 1 <= kmin <= kmax <= N, chains * M <= 2^24, rule METROPOLIS => M == 1. */
 typedef struct {
@@ -79,6 +99,7 @@ typedef struct {
     uint32_t chain_base;     /* global index of chain 0 in the Philox counter */
     int32_t mean_steps;      /* capacity of the per-step chain-mean trace ring (>= 0) */
     double near_tie_tol;     /* selection margin below which a step is flagged; < 0 => default */
+    int32_t scorer;          /* mc3_scorer */
 } mc3_config;
 
 /* One instance of a batch: its size, graph size, chains and flip-set range, with the
@@ -102,6 +123,7 @@ typedef struct {
     uint64_t seed;           /* Philox key */
     double near_tie_tol;     /* < 0 => default */
     const mc3_instance_desc* instances;  /* [n_instances], copied by mc3_batch_create */
+    int32_t scorer;          /* mc3_scorer */
 } mc3_batch_config;
 
 /* Per-step, per-chain record (40 bytes). */

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmc3.so")
 SOURCES = [os.path.join(CSRC, "mc3.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "device_rng.hpp")] + [os.path.join(ROOT, "include", "mc3.h")]
+HEADERS = ([os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hpp")]
+           + [os.path.join(ROOT, "include", "mc3.h")])
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,107 @@
+// common.hpp -- types and helpers shared by the device kernels of the SK MCMCMC hot
+// path (gfx950).
+//
+// Data layout in HBM (all sizes padded: Np = N rounded up to 128, W = Np/32 words
+// per spin bitset, B = chains*M candidate columns, Bp = B rounded up to 512):
+//   J64     [Np][Np] double, row-major, zero outside the N x N block.
+//   Jsplit  bf16 hi/mid/lo of the strict upper triangle of J, in matrix-core
+//           fragment order: fragment (R, S, t) = rows 32R..32R+31, k = 16S..16S+15,
+//           term t, stored as 64 lanes x 8 bf16 (lane l holds row 32R + l%32,
+//           k = 16S + 8(l/32) + e for e = 0..7); 1 KiB per fragment.
+//   spins   [chains][W] uint32 bitsets (set bit = spin -1).
+//   flipsT  ring of slots, one step each, slot = step % slots; a slot is [W][Bp]
+//           uint32: word w of the flip set F_{m+1} of edge m+1 of chain c at column
+//           c*M + m (columns contiguous, so a matrix-core B fragment's 32 columns are
+//           one 128-byte line); padding columns stay zero.
+//   base    two [chains+1][W] uint32 buffers by step parity: s ^ F_r (s if r = 0)
+//           per chain; row `chains` is zero (used by padding columns).
+//   partial [P][Bp] double: energy contributions of row-block pair p.
+//
+// Candidate columns are never materialised on the hot path.  Column m of chain c is
+// node m+1 of the star, except that when the root r >= 1 column r-1 holds the hub
+// (node 0) instead of leaf r (the current state).  Its bitset is therefore
+// base_c ^ F_{m+1}, or base_c alone for column r-1:
+//   r = 0:  base = s, column m = s ^ F_{m+1} = leaf m+1;
+//   r >= 1: base = s ^ F_r = hub, column m = hub ^ F_{m+1} = leaf m+1, column r-1 = hub.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_rng.hpp"
+
+namespace mc3 {
+
+constexpr int kRowBlock = 128;  // rows of J per scoring work unit (4 fragments of 32)
+
+// One SK instance of a batch, as the kernels see it.  Byte offsets are into the
+// workspace; the per-chain arrays (energies, roots, counters, records) are global over
+// the batch and indexed by chain0 + c.
+struct Inst {
+  int32_t N, Np, W, M;
+  int32_t chains, kmin, kmax, B;
+  int32_t Bp, NB, P, chain0;
+  double scale;
+  uint64_t J64, Jpack, flips, flip_slot, base[2], partial, spins;
+  uint64_t field;   // [chains][Np] FP64 local fields (field-update path only)
+};
+
+// Flip sets of the step held in ring slot `slot` (slots of flip_slot bytes each).
+__device__ __forceinline__ uint32_t* flips_at(char* ws, const Inst& in, uint32_t slot) {
+  return reinterpret_cast<uint32_t*>(ws + in.flips + (uint64_t)slot * in.flip_slot);
+}
+
+// A scoring work unit (row-block pair p, column tile ct of instance inst); inst < 0 is
+// an idle slot of the launch grid.
+struct Unit {
+  int32_t inst, p, ct, pad;
+};
+
+// A proposal block: edges edge0 .. edge0 + blockDim.x - 1 (flattened chain*M + e-1) of
+// instance inst.
+struct PBlock {
+  int32_t inst, edge0;
+};
+
+template <class T>
+__device__ __forceinline__ T* ws_at(char* ws, uint64_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+// Wave-wide reductions (64 lanes, fixed butterfly order: every lane ends with the
+// same value).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = x + __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) { double y = __shfl_xor(x, o); x = y < x ? y : x; }
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) { double y = __shfl_xor(x, o); x = y > x ? y : x; }
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    unsigned long long y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+struct Record {
+  int32_t r, vstar;
+  double e_cur, e_bar, margin;
+  uint32_t flags, step;
+};
+
+}  // namespace mc3

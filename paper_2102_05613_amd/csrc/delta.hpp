@@ -1,0 +1,242 @@
+// delta.hpp -- the field-update path: energies as differences from the current state.
+#pragma once
+#include "common.hpp"
+#include "select.hpp"
+
+namespace mc3 {
+
+// ------------------------------------------------------------------- field-update path
+//
+// Energies as differences from the current state (a scorer for small flip sets).
+// Per chain the device keeps the unscaled pair sum U = sum_{i<j} J_ij s_i s_j
+// (E = -(scale U)) and the local field h_i = sum_j J_ij s_j.  Flipping the sites of a
+// set D changes U by
+//   dU(D) = -2 sum_{i in D} s_i h_i + 4 sum_{i<j in D} J_ij s_i s_j,
+// and h by h_i -= 2 sum_{j in D} J_ij s_j (old spins).  The node v of the star differs
+// from the current state (node r) by the path flip set D_v = F_r xor F_v (F_0 = {}):
+// F_v for r = 0, F_r for the hub, F_r xor F_v for the other leaves.  With +-1
+// couplings U and h stay exact integers, so energies equal the pair sum's.
+
+constexpr int kDeltaMaxK = 16;    // flip-set size limit of the field-update path
+constexpr int kDeltaMaxM = 512;   // graph size limit (leaves)
+constexpr int kDeltaMaxN = 4096;  // spins (the field lives in LDS)
+
+__host__ __device__ constexpr size_t delta_lds_bytes(int Nmax, int Mmax, int Wmax) {
+  return 8 * (size_t)Nmax + 24 * ((size_t)Mmax + 1) + 4 * (size_t)Wmax + 2 * (size_t)kDeltaMaxK * Mmax +
+         2 * 256 * 2 * (size_t)kDeltaMaxK + (size_t)Mmax;
+}
+
+// h = J s for every chain (one block per global chain; thread i owns rows i, i+256, ..;
+// j ascending).
+__global__ __launch_bounds__(256) void k_field_init(char* __restrict__ ws, const Inst* __restrict__ insts,
+                                                    const int32_t* __restrict__ chain_inst) {
+  const int g = blockIdx.x;
+  const Inst& in = insts[chain_inst[g]];
+  const int c = g - in.chain0;
+  const int N = in.N, Np = in.Np, W = in.W;
+  const double* __restrict__ J64 = ws_at<const double>(ws, in.J64);
+  const uint32_t* s = ws_at<const uint32_t>(ws, in.spins) + (size_t)c * W;
+  double* h = ws_at<double>(ws, in.field) + (size_t)c * Np;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    const double* row = J64 + (size_t)i * Np;
+    double acc = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const double sj = ((s[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
+      acc += row[j] * sj;
+    }
+    h[i] = acc;
+  }
+}
+
+__device__ __forceinline__ double spin_of(const uint32_t* bits, int i) {
+  return ((bits[i >> 5] >> (i & 31)) & 1u) ? -1.0 : 1.0;
+}
+
+// Path flip set D_v of node v (root r) into out[]; returns |D_v|.  Sites of F_v not in
+// F_r (in F_v's order), then sites of F_r not in F_v (in F_r's order).
+__device__ __forceinline__ int path_set(const uint16_t* sites, const uint8_t* ks, int r, int v, uint16_t* out) {
+  int n = 0;
+  const uint16_t* fv = v >= 1 ? sites + (size_t)(v - 1) * kDeltaMaxK : nullptr;
+  const uint16_t* fr = r >= 1 ? sites + (size_t)(r - 1) * kDeltaMaxK : nullptr;
+  const int kv = v >= 1 ? ks[v - 1] : 0;
+  const int kr = r >= 1 ? ks[r - 1] : 0;
+  for (int a = 0; a < kv; ++a) {
+    bool both = false;
+    for (int b = 0; b < kr; ++b) both |= fr[b] == fv[a];
+    if (!both) out[n++] = fv[a];
+  }
+  for (int b = 0; b < kr; ++b) {
+    bool both = false;
+    for (int a = 0; a < kv; ++a) both |= fv[a] == fr[b];
+    if (!both) out[n++] = fr[b];
+  }
+  return n;
+}
+
+// n steps of the whole path for every chain, one block (256 threads) per global
+// chain, the chain's state, field and pair sum held in LDS across the steps:
+//   1. threads e-1 draw edge e's flip set (k_e, then Floyd's k-of-N on the same words
+//      as k_propose, the membership test scanning the list drawn so far); thread 0
+//      draws the root;
+//   2. thread v (each node v != r) forms D_v and dU(D_v), En[v] = -(scale (U + dU));
+//      En[r] = -(scale U);
+//   3. wave 0: the rule (apply_rule) and the bookkeeping;
+//   4. on a move: h -= 2 J[:, D*] s_D* (rows of J, coalesced), then the spins of D*
+//      flip and U += dU(D*).
+// beta_t = beta0 + (beta1 - beta0) (t / (total - 1)) as on the host.  Per-step chain
+// values (e_cur, e_bar) go to vals[t % mean_steps][g] for the means trace.
+// Dynamic LDS: delta_lds_bytes(Nmax, Mmax, Wmax).
+__global__ __launch_bounds__(256) void k_step_delta(
+    char* __restrict__ ws, const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst,
+    int total_chains, int Nmax, int Mmax, int Wmax,
+    double* __restrict__ e_cur, double* __restrict__ u_cur, Record* __restrict__ ring,
+    unsigned long long* __restrict__ moves, unsigned long long* __restrict__ near_ties,
+    double* __restrict__ min_margin, double* __restrict__ e_bar_out, double* __restrict__ vals, int mean_steps,
+    int metropolis, double beta0, double beta1, long long total, double tol, Key key, uint32_t chain_base,
+    uint32_t step0, int nsteps, int trace_steps) {
+  extern __shared__ double dl[];
+  __shared__ int sh_r, sh_vstar, sh_nd;
+  __shared__ uint16_t dstar[2 * kDeltaMaxK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x;
+  const Inst& in = insts[chain_inst[g]];
+  const int c = g - in.chain0;
+  const int N = in.N, Np = in.Np, W = in.W, M = in.M;
+  const double scale = in.scale;
+  const double* __restrict__ J64 = ws_at<const double>(ws, in.J64);
+  uint32_t* __restrict__ spins_g = ws_at<uint32_t>(ws, in.spins) + (size_t)c * W;
+  double* __restrict__ field_g = ws_at<double>(ws, in.field) + (size_t)c * Np;
+  // LDS carve-up
+  double* h = dl;                                                               // [Nmax]
+  double* En = h + Nmax;                                                        // [Mmax+1]
+  double* dU = En + (Mmax + 1);                                                 // [Mmax+1]
+  unsigned long long* Qn = reinterpret_cast<unsigned long long*>(dU + (Mmax + 1));  // [Mmax+1]
+  uint32_t* sbits = reinterpret_cast<uint32_t*>(Qn + (Mmax + 1));              // [Wmax]
+  uint16_t* sites = reinterpret_cast<uint16_t*>(sbits + Wmax);                 // [Mmax][K]
+  uint16_t* dbuf = sites + (size_t)Mmax * kDeltaMaxK;                          // [256][2K]
+  uint8_t* ks = reinterpret_cast<uint8_t*>(dbuf + 256 * 2 * kDeltaMaxK);       // [Mmax]
+
+  for (int i = tid; i < N; i += 256) h[i] = field_g[i];
+  for (int w = tid; w < W; w += 256) sbits[w] = spins_g[w];
+  double U = u_cur[g];
+  const uint32_t gc = chain_base + (uint32_t)g;
+  __syncthreads();
+
+  for (int it = 0; it < nsteps; ++it) {
+    const uint32_t step = step0 + (uint32_t)it;
+    const double beta = total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)step / (double)(total - 1));
+    // 1. root and flip sets
+    if (tid == 0) sh_r = root_of(key, gc, step, M, metropolis);
+    for (int e1 = tid; e1 < M; e1 += 256) {
+      const uint32_t e = (uint32_t)e1 + 1u;
+      uint16_t* my = sites + (size_t)e1 * kDeltaMaxK;
+      uint4 blk = stream_block(key, kTagEdge, gc, step, e, 0u);
+      const int k = in.kmin + (int)randint(blk.x, (uint32_t)(in.kmax - in.kmin + 1));
+      for (int idx = 0; idx < k; ++idx) {
+        const uint32_t n = 1u + (uint32_t)idx;
+        if ((n & 3u) == 0u) blk = stream_block(key, kTagEdge, gc, step, e, n >> 2);
+        const uint32_t j = (uint32_t)(N - k + idx);
+        const uint32_t t = randint(pick(blk, n & 3u), j + 1u);
+        bool seen = false;
+        for (int q = 0; q < idx; ++q) seen |= my[q] == (uint16_t)t;
+        my[idx] = (uint16_t)(seen ? j : t);
+      }
+      ks[e1] = (uint8_t)k;
+    }
+    __syncthreads();
+    const int r = sh_r;
+    // 2. node energies
+    for (int v = tid; v <= M; v += 256) {
+      if (v == r) continue;
+      uint16_t* D = dbuf + (size_t)tid * 2 * kDeltaMaxK;
+      const int nd = path_set(sites, ks, r, v, D);
+      double lin = 0.0, pair = 0.0;
+      for (int a = 0; a < nd; ++a) {
+        const int i = D[a];
+        const double si = spin_of(sbits, i);
+        lin += si * h[i];
+        const double* Ji = J64 + (size_t)i * Np;
+        double row = 0.0;
+        for (int b = a + 1; b < nd; ++b) row += Ji[D[b]] * spin_of(sbits, D[b]);
+        pair += si * row;
+      }
+      const double d = -2.0 * lin + 4.0 * pair;
+      dU[v] = d;
+      En[v] = -(scale * (U + d));
+    }
+    if (tid == 0) En[r] = -(scale * U);
+    __syncthreads();
+    // 3. the rule
+    if (wave == 0) {
+      const uint4 ub = stream_block(key, kTagSelect, gc, step, 0u, 0u);
+      const RuleOut o = apply_rule(En, Qn, M, r, -(scale * U), metropolis, beta, u53_of(ub.x, ub.y), lane);
+      if (lane == 0) {
+        sh_vstar = o.vstar;
+        record_outcome(o, g, r, tol, step, trace_steps, total_chains, e_cur, e_bar_out, moves, near_ties,
+                       min_margin, ring);
+        if (mean_steps > 0) {
+          double* vv = vals + ((size_t)(step % (uint32_t)mean_steps) * total_chains + g) * 2;
+          vv[0] = o.e_new;
+          vv[1] = o.ebar;
+        }
+        if (o.vstar != r) sh_nd = path_set(sites, ks, r, o.vstar, dstar);
+      }
+    }
+    __syncthreads();
+    // 4. the move
+    const int vstar = sh_vstar;
+    if (vstar != r) {
+      const int nd = sh_nd;
+      for (int i = tid; i < N; i += 256) {
+        double x = h[i];
+        for (int a = 0; a < nd; ++a) {
+          const int j = dstar[a];
+          x -= 2.0 * (J64[(size_t)j * Np + i] * spin_of(sbits, j));
+        }
+        h[i] = x;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int a = 0; a < nd; ++a) sbits[dstar[a] >> 5] ^= 1u << (dstar[a] & 31);
+      }
+      U += dU[vstar];
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < N; i += 256) field_g[i] = h[i];
+  for (int w = tid; w < W; w += 256) spins_g[w] = sbits[w];
+  if (tid == 0) u_cur[g] = U;
+}
+
+// Chain means of `n` consecutive steps from per-chain values vals[slot][g][2] (slot =
+// step % mean_steps): one block per step, the same fixed-order tree as k_chain_means.
+__global__ __launch_bounds__(256) void k_chain_means_steps(double* __restrict__ trace,
+                                                           const double* __restrict__ vals, int chains,
+                                                           int mean_steps, uint32_t step0) {
+  __shared__ double red[2][256];
+  const uint32_t step = step0 + blockIdx.x;
+  const uint32_t slot = step % (uint32_t)mean_steps;
+  const double* v = vals + (size_t)slot * chains * 2;
+  double a = 0.0, b = 0.0;
+  for (int c = threadIdx.x; c < chains; c += 256) {
+    a += v[2 * (size_t)c];
+    b += v[2 * (size_t)c + 1];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] = red[0][threadIdx.x] + red[0][threadIdx.x + o];
+      red[1][threadIdx.x] = red[1][threadIdx.x] + red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    trace[3 * (size_t)slot] = (double)step;
+    trace[3 * (size_t)slot + 1] = red[0][0] / (double)chains;
+    trace[3 * (size_t)slot + 2] = red[1][0] / (double)chains;
+  }
+}
+
+}  // namespace mc3

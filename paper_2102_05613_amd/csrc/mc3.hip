@@ -37,6 +37,7 @@ struct InstH {
   int Np, W, Wn, B, Bp, NB, P, chain0, col0;
   size_t J64, Jpack, flips, base[2], partial, spins;  // byte offsets into the workspace
   size_t flip_slot;                                    // bytes of one step's flip sets
+  size_t field = 0;                                    // [chains][Np] FP64 fields (field-update path)
   double scale = 1.0;
   bool have_J = false;
   int unit_off = 0, unit_grid = 0;     // this instance's own unit table (per-instance launches)
@@ -45,6 +46,8 @@ struct InstH {
 
 struct Plan {
   std::vector<InstH> inst;
+  bool delta = false;   // field-update scorer (else the matrix-core pair sum)
+  size_t delta_lds = 0;
   int total_chains = 0, total_cols = 0, Wmax = 0, Wn_max = 0, Mmax = 0;
   int prop_T = 256, prop_stride = 1;
   int ahead = 1;    // steps proposed per launch in mc3_step_n
@@ -54,7 +57,7 @@ struct Plan {
   std::vector<int32_t> chain_inst;
   size_t insts = 0, chain_inst_off = 0, units_global_off = 0, units_local_off = 0, pblocks_off = 0;
   size_t e_cur = 0, e_bar = 0, roots = 0, candT = 0, ring = 0, means = 0, moves = 0, near = 0, minm = 0, drift = 0,
-         erecomp = 0, total = 0;
+         erecomp = 0, u_cur = 0, vals = 0, total = 0;
 };
 
 const char* validate_instance(const mc3_instance_desc& d, int rule) {
@@ -73,6 +76,8 @@ const char* validate_batch(const mc3_batch_config* c) {
   if (!c->instances) return "instances is NULL";
   if (c->precision != MC3_FP64 && c->precision != MC3_SPLIT_BF16) return "unknown precision";
   if (c->rule != MC3_RULE_MCMCMC && c->rule != MC3_RULE_METROPOLIS) return "unknown rule";
+  if (c->scorer != MC3_SCORER_GEMM && c->scorer != MC3_SCORER_DELTA && c->scorer != MC3_SCORER_AUTO)
+    return "unknown scorer";
   if (c->trace_steps < 0) return "trace_steps must be >= 0";
   if (c->mean_steps < 0) return "mean_steps must be >= 0";
   if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
@@ -88,6 +93,28 @@ const char* validate_batch(const mc3_batch_config* c) {
   return nullptr;
 }
 
+// Whether the field-update scorer can run this batch (its limits), and its LDS bytes.
+bool delta_fits(const mc3_batch_config& c, size_t* lds, int kmax_limit) {
+  int Nmax = 0, Mmax = 0, Wmax = 0;
+  for (int i = 0; i < c.n_instances; ++i) {
+    const mc3_instance_desc& d = c.instances[i];
+    if (d.kmax > kmax_limit || d.M > mc3::kDeltaMaxM || d.N > mc3::kDeltaMaxN) return false;
+    Nmax = std::max(Nmax, d.N);
+    Mmax = std::max(Mmax, d.M);
+    Wmax = std::max(Wmax, (d.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock / 32);
+  }
+  *lds = mc3::delta_lds_bytes(Nmax, Mmax, Wmax);
+  return *lds <= 65536;
+}
+
+// Resolve the scorer: 1 = field update, 0 = pair sum, -1 = field update requested but
+// outside its limits.
+int resolve_delta(const mc3_batch_config& c, size_t* lds) {
+  if (c.scorer == MC3_SCORER_GEMM) return 0;
+  if (c.scorer == MC3_SCORER_DELTA) return delta_fits(c, lds, mc3::kDeltaMaxK) ? 1 : -1;
+  return delta_fits(c, lds, 8) ? 1 : 0;
+}
+
 // Cost of a scoring unit in 128x128 K blocks: the pair (p, NB-1-p) spans NB+1 blocks
 // of the upper triangle, the self-paired middle block row NB-p.
 int unit_cost(int NB, int p) { return p == NB - 1 - p ? NB - p : NB + 1; }
@@ -96,6 +123,7 @@ int unit_cost(int NB, int p) { return p == NB - 1 - p ? NB - p : NB + 1; }
 Plan make_plan(const mc3_batch_config& cfg) {
   Plan pl;
   const int n = cfg.n_instances;
+  pl.delta = resolve_delta(cfg, &pl.delta_lds) == 1;
   pl.inst.resize(n);
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
@@ -192,6 +220,10 @@ Plan make_plan(const mc3_batch_config& cfg) {
   pl.erecomp = take(C * 8);
   pl.ring = take((size_t)cfg.trace_steps * C * sizeof(mc3::Record));
   pl.means = take((size_t)cfg.mean_steps * 3 * sizeof(double));
+  if (pl.delta) {
+    pl.u_cur = take(C * 8);
+    pl.vals = take((size_t)cfg.mean_steps * C * 2 * sizeof(double));
+  }
   size_t candT = 0;
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
@@ -203,6 +235,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
     for (int q = 0; q < 2; ++q) h.base[q] = take((size_t)(h.desc.chains + 1) * h.W * 4);
     h.partial = take((size_t)h.P * h.Bp * 8);
     h.spins = take((size_t)h.desc.chains * h.W * 4);
+    if (pl.delta) h.field = take((size_t)h.desc.chains * h.Np * 8);
     candT = std::max(candT, (size_t)h.W * h.Bp * 4);
   }
   pl.candT = take(candT);
@@ -227,6 +260,7 @@ mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
   b.seed = c->seed;
   b.near_tie_tol = c->near_tie_tol;
   b.instances = one;
+  b.scorer = c->scorer;
   return b;
 }
 
@@ -335,16 +369,61 @@ mc3_status upload_insts(mc3_ctx* c) {
     d.base[1] = h.base[1];
     d.partial = h.partial;
     d.spins = h.spins;
+    d.field = h.field;
   }
   MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<char>(pl.insts), t.data(), t.size() * sizeof(mc3::Inst),
                                    hipMemcpyHostToDevice, c->stream), "upload instance table"));
   return hip_ok(c, hipStreamSynchronize(c->stream), "upload sync");
 }
 
+// FP64 energies of every chain into `out`; for the field-update path also the pair
+// sums U and the fields h.
 mc3_status launch_energy(mc3_ctx* c, double* out) {
-  hipLaunchKernelGGL(mc3::k_energy_f64, dim3(c->pl.total_chains), dim3(256), 0, c->stream, out, c->ws, c->insts(),
-                     c->chain_inst());
-  return check_launch(c, "energy kernel");
+  const Plan& pl = c->pl;
+  hipLaunchKernelGGL(mc3::k_energy_f64, dim3(pl.total_chains), dim3(256), 0, c->stream, out,
+                     pl.delta ? c->at<double>(pl.u_cur) : nullptr, c->ws, c->insts(), c->chain_inst());
+  MC3_TRY(check_launch(c, "energy kernel"));
+  if (pl.delta) {
+    hipLaunchKernelGGL(mc3::k_field_init, dim3(pl.total_chains), dim3(256), 0, c->stream, c->ws, c->insts(),
+                       c->chain_inst());
+    MC3_TRY(check_launch(c, "field kernel"));
+  }
+  return MC3_OK;
+}
+
+mc3_status no_delta(mc3_ctx* c, const char* what) {
+  if (!c->pl.delta) return MC3_OK;
+  return fail(c, MC3_E_UNSUPPORTED, "%s: not available with the field-update scorer (use mc3_step_n)", what);
+}
+
+// n steps of the field-update path: persistent per-chain launches of at most 2048
+// steps each, then the chain means of the steps still in the trace ring.
+mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
+  const Plan& pl = c->pl;
+  int Nmax = 0;
+  for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
+  for (int64_t done = 0; done < n;) {
+    const int chunk = (int)std::min<int64_t>(2048, n - done);
+    hipLaunchKernelGGL(mc3::k_step_delta, dim3(pl.total_chains), dim3(256), pl.delta_lds, c->stream, c->ws,
+                       c->insts(), c->chain_inst(), pl.total_chains, Nmax, pl.Mmax, pl.Wmax,
+                       c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->at<mc3::Record>(pl.ring),
+                       c->at<unsigned long long>(pl.moves), c->at<unsigned long long>(pl.near),
+                       c->at<double>(pl.minm), c->at<double>(pl.e_bar), c->at<double>(pl.vals), c->cfg.mean_steps,
+                       c->metropolis() ? 1 : 0, beta0, beta1, (long long)total, c->tol, c->key(),
+                       c->cfg.chain_base, step0 + (uint32_t)done, chunk, c->cfg.trace_steps);
+    MC3_TRY(check_launch(c, "field-update step kernel"));
+    done += chunk;
+  }
+  if (c->cfg.mean_steps > 0) {
+    const int64_t keep = std::min<int64_t>(n, c->cfg.mean_steps);
+    hipLaunchKernelGGL(mc3::k_chain_means_steps, dim3((unsigned)keep), dim3(256), 0, c->stream,
+                       c->at<double>(pl.means), c->at<const double>(pl.vals), pl.total_chains, c->cfg.mean_steps,
+                       step0 + (uint32_t)(n - keep));
+    MC3_TRY(check_launch(c, "means kernel"));
+  }
+  c->steps_done += n;
+  c->have_proposal = c->have_scores = false;
+  return MC3_OK;
 }
 
 // Proposal blocks [b0, b0 + nb) of the block table for steps step0 .. step0+nsteps-1
@@ -501,6 +580,8 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
   if (!out) return MC3_E_ARG;
   *out = nullptr;
   if (validate_batch(cfg)) return MC3_E_ARG;
+  size_t lds = 0;
+  if (resolve_delta(*cfg, &lds) < 0) return MC3_E_UNSUPPORTED;
   Plan plan = make_plan(*cfg);
   if (!workspace || bytes < plan.total || ((uintptr_t)workspace % kAlign) != 0) return MC3_E_WORKSPACE;
   int dev = 0;
@@ -590,6 +671,8 @@ const char* mc3_version(void) { return "mc3 0.2 (gfx950)"; }
 
 mc3_status mc3_batch_workspace_size(const mc3_batch_config* cfg, size_t* bytes) {
   if (validate_batch(cfg) || !bytes) return MC3_E_ARG;
+  size_t lds = 0;
+  if (resolve_delta(*cfg, &lds) < 0) return MC3_E_UNSUPPORTED;
   *bytes = make_plan(*cfg).total;
   return MC3_OK;
 }
@@ -698,6 +781,7 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
 mc3_status mc3_propose(mc3_ctx* c, uint32_t step) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "propose before init_chains");
+  MC3_TRY(no_delta(c, "mc3_propose"));
   MC3_TRY(propose_all(c, step, 1, true));
   c->have_proposal = true;
   c->have_scores = false;
@@ -707,12 +791,14 @@ mc3_status mc3_propose(mc3_ctx* c, uint32_t step) {
 
 mc3_status mc3_score_candidates(mc3_ctx* c, double* E_out) {
   MC3_TRY(usable(c));
+  MC3_TRY(no_delta(c, "mc3_score_candidates"));
   if (!c->have_proposal) return fail(c, MC3_E_STATE, "score_candidates before propose");
   return do_score(c, E_out);
 }
 
 mc3_status mc3_select(mc3_ctx* c, uint32_t step, double beta) {
   MC3_TRY(usable(c));
+  MC3_TRY(no_delta(c, "mc3_select"));
   if (!c->have_scores) return fail(c, MC3_E_STATE, "select before score_candidates");
   if (step != c->proposal_step)
     return fail(c, MC3_E_ARG, "select step %u differs from propose step %u", step, c->proposal_step);
@@ -722,12 +808,14 @@ mc3_status mc3_select(mc3_ctx* c, uint32_t step, double beta) {
 
 mc3_status mc3_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
   MC3_TRY(step_args(c, step0, n, beta0, beta1));
+  if (c->pl.delta) return do_step_n_delta(c, step0, n, beta0, beta1, total);
   return do_step_n(c, step0, n, beta0, beta1, total);
 }
 
 mc3_status mc3_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1,
                                    int64_t total) {
   MC3_TRY(step_args(c, step0, n, beta0, beta1));
+  MC3_TRY(no_delta(c, "mc3_step_n_per_instance"));
   return do_step_n_per_instance(c, step0, n, beta0, beta1, total);
 }
 
@@ -817,6 +905,7 @@ mc3_status mc3_read_records(mc3_ctx* c, uint32_t first, int32_t n, mc3_record* o
 
 mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
   MC3_TRY(usable(c));
+  MC3_TRY(no_delta(c, "mc3_read_candidates"));
   if (!c->have_proposal) return fail(c, MC3_E_STATE, "no proposal to read");
   if (c->pl.inst.size() != 1) return fail(c, MC3_E_UNSUPPORTED, "read_candidates needs a single-instance context");
   const InstH& h = c->pl.inst[0];

@@ -46,9 +46,9 @@ def test_struct_layout_matches_header():
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mc3_config), offsetof(mc3_config, seed),
          offsetof(mc3_config, near_tie_tol), sizeof(mc3_record), offsetof(mc3_record, margin), sizeof(mc3_summary));
-  printf("%zu %zu %zu %zu %zu\n", sizeof(mc3_instance_desc), sizeof(mc3_batch_config),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mc3_instance_desc), sizeof(mc3_batch_config),
          offsetof(mc3_batch_config, chain_base), offsetof(mc3_batch_config, seed),
-         offsetof(mc3_batch_config, instances));
+         offsetof(mc3_batch_config, instances), offsetof(mc3_batch_config, scorer), offsetof(mc3_config, scorer));
   return 0;
 }
 '''
@@ -63,7 +63,8 @@ int main(void) {
                     ctypes.sizeof(native.Summary),
                     ctypes.sizeof(native.InstanceDesc), ctypes.sizeof(native.BatchConfig),
                     native.BatchConfig.chain_base.offset, native.BatchConfig.seed.offset,
-                    native.BatchConfig.instances.offset]
+                    native.BatchConfig.instances.offset, native.BatchConfig.scorer.offset,
+                    native.Config.scorer.offset]
 
 
 def test_version(lib):
@@ -163,3 +164,24 @@ def test_batch_rejects_bad_header_fields(lib):
     assert _batch_ws(lib, cfg)[0] == native.MC3_E_ARG
     assert lib.mc3_init_couplings_instance(None, 0, None, 0, 1.0) == native.MC3_E_ARG
     assert lib.mc3_step_n_per_instance(None, 0, 1, 1.0, 1.0, 1) == native.MC3_E_ARG
+
+
+@pytest.mark.parametrize("shape,scorer,expect", [
+    ((64, 4, 2, 1, 16), "delta", native.MC3_OK), ((64, 4, 2, 1, 17), "delta", native.MC3_E_UNSUPPORTED),
+    ((4097, 4, 2, 1, 2), "delta", native.MC3_E_UNSUPPORTED), ((64, 513, 2, 1, 2), "delta", native.MC3_E_UNSUPPORTED),
+    ((4096, 512, 2, 1, 16), "delta", native.MC3_E_UNSUPPORTED),   # LDS beyond 64 KiB
+    ((64, 4, 2, 1, 17), "auto", native.MC3_OK), ((64, 4, 2, 1, 16), "gemm", native.MC3_OK)])
+def test_field_update_scorer_limits(lib, shape, scorer, expect):
+    cfg = native.make_config(*shape, precision="fp64", scorer=scorer)
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == expect
+    if expect == native.MC3_E_UNSUPPORTED:
+        h = ctypes.c_void_p()
+        assert lib.mc3_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h)) == expect
+
+
+def test_unknown_scorer_rejected(lib):
+    cfg = native.make_config(64, 4, 2, 1, 2)
+    cfg.scorer = 7
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == native.MC3_E_ARG

@@ -1,0 +1,126 @@
+"""The field-update scorer (energies as differences from the current state, one
+persistent workgroup per chain) against the oracle.
+
+Bars: +-1 couplings give the oracle's trajectories bit for bit (integer pair sums
+and fields); Gaussian couplings give the oracle's selections except at flagged near
+ties, energies within 1e-9 relative; batches equal single-instance contexts bit for
+bit; the means trace equals the per-chain records' means."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import announce, compare_trajectory
+from paper_2102_05613_amd import inputs, native
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    native.lib()
+
+
+def _ctx(N, M, chains, kmin, kmax, J, scale, rule="mcmcmc", steps=0, seed=0, chain_base=0, mean_steps=0):
+    cfg = native.make_config(N, M, chains, kmin, kmax, precision="fp64", rule=rule, trace_steps=steps, seed=seed,
+                             chain_base=chain_base, mean_steps=mean_steps, scorer="delta")
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    return ctx
+
+
+@pytest.mark.parametrize("M,rule,kmax", [(4, "mcmcmc", 1), (1, "mcmcmc", 1), (1, "metropolis", 1),
+                                         (16, "mcmcmc", 4), (7, "mcmcmc", 16)])
+def test_pm1_trajectory_bit_exact(M, rule, kmax):
+    N, chains, steps = 32, 3, 3000
+    announce(f"delta pm1 trajectory M={M} {rule} k<={kmax}")
+    J, scale = inputs.couplings_pm1(N, 0x5EED0001)
+    ctx = _ctx(N, M, chains, 1, kmax, J, scale, rule=rule, steps=steps, seed=4)
+    ctx.step_n(0, steps, 1.0, 1.0, 1)
+    rec = ctx.read_records(0, steps)
+    compare_trajectory(rec, J, scale, N, M, chains, 1, kmax, 4, np.ones(steps), rule, 0.0, exact=True)
+    e, bits, summ = ctx.measure()
+    assert summ["steps_done"] == steps and summ["moves"] > 0
+    s = native.bits_to_spins(bits, N)
+    for c in range(chains):
+        assert e[c] == oracle.energy(J, scale, s[c])
+
+
+def test_pm1_anneal_n256_bit_exact_across_launches():
+    """N=256, M=16, flip sets 1..4, beta 0.1 -> 3: 2500 steps in two calls (the second
+    spans the 2048-step launch split) equal the oracle's records."""
+    N, M, chains, steps = 256, 16, 8, 2500
+    announce("delta pm1 anneal N=256")
+    J, scale = inputs.couplings_pm1(N, 77)
+    ctx = _ctx(N, M, chains, 1, 4, J, scale, steps=steps, seed=2)
+    ctx.step_n(0, 100, 0.1, 3.0, steps)
+    ctx.step_n(100, steps - 100, 0.1, 3.0, steps)
+    rec = ctx.read_records(0, steps)
+    betas = inputs.beta_schedule(0.1, 3.0, steps, 0, steps)
+    compare_trajectory(rec, J, scale, N, M, chains, 1, 4, 2, betas, "mcmcmc", 0.0, exact=True)
+
+
+def test_gauss_anneal_guided_and_means():
+    """The anneal workload's law (N=256, M=16, k 1..4, Gaussian J, beta 0.1 -> 3) on 16
+    chains: selections equal the oracle's except at flagged near ties; the means trace
+    equals the means of the records."""
+    N, M, chains, steps = 256, 16, 16, 600
+    announce("delta gauss anneal")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0002)
+    ctx = _ctx(N, M, chains, 1, 4, J, scale, steps=steps, seed=2, mean_steps=steps)
+    ctx.step_n(0, steps, 0.1, 3.0, steps)
+    rec = ctx.read_records(0, steps)
+    betas = inputs.beta_schedule(0.1, 3.0, steps, 0, steps)
+    ro, nforced = compare_trajectory(rec, J, scale, N, M, chains, 1, 4, 2, betas, "mcmcmc", 1e-9)
+    assert nforced <= 2
+    means = ctx.read_means(0, steps)
+    np.testing.assert_allclose(means[:, 0], rec["e_cur"].mean(axis=1), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(means[:, 1], rec["e_bar"].mean(axis=1), rtol=1e-12, atol=1e-12)
+    # field and pair sum carried over 600 steps: FP64 recompute differs by rounding only
+    e_before, bits, _ = ctx.measure()
+    ctx.recompute()
+    _, _, summ = ctx.measure()
+    assert summ["max_drift"] < 1e-10
+    s = native.bits_to_spins(bits, N)
+    for c in range(chains):
+        assert e_before[c] == pytest.approx(oracle.energy(J, scale, s[c]), rel=1e-12, abs=1e-12)
+
+
+def test_delta_batch_equals_single_contexts():
+    descs = [(32, 4, 2, 1, 1), (200, 9, 3, 1, 5), (129, 16, 1, 2, 3), (64, 1, 4, 1, 2)]
+    steps = 300
+    announce("delta batch vs single contexts")
+    cfg = native.make_batch_config(descs, precision="fp64", trace_steps=steps, seed=9, chain_base=5,
+                                   scorer="delta")
+    ctx = native.Context(cfg)
+    Js = [inputs.couplings_gauss(d[0], 500 + i) for i, d in enumerate(descs)]
+    for i, (J, scale) in enumerate(Js):
+        ctx.init_couplings(J, scale, instance=i)
+    ctx.init_chains()
+    ctx.step_n(0, steps, 0.5, 2.0, steps)
+    rec = ctx.read_records(0, steps)
+    g0 = 0
+    for d, (J, scale) in zip(descs, Js):
+        N, M, chains, kmin, kmax = d
+        one = _ctx(N, M, chains, kmin, kmax, J, scale, steps=steps, seed=9, chain_base=5 + g0)
+        one.step_n(0, steps, 0.5, 2.0, steps)
+        assert np.array_equal(rec[:, g0:g0 + chains], one.read_records(0, steps))
+        one.close()
+        g0 += chains
+
+
+def test_delta_rejects_stepwise_calls():
+    J, scale = inputs.couplings_gauss(64, 1)
+    ctx = _ctx(64, 4, 2, 1, 2, J, scale)
+    for call in (lambda: ctx.propose(0), lambda: ctx.score_candidates(), lambda: ctx.select(0, 1.0),
+                 lambda: ctx.read_candidates(), lambda: ctx.step_n_per_instance(0, 1, 1.0, 1.0, 1)):
+        with pytest.raises(native.MC3Error) as ei:
+            call()
+        assert ei.value.status == native.MC3_E_UNSUPPORTED
+    ctx.step_n(0, 5, 1.0, 1.0, 1)
+    assert ctx.measure()[2]["steps_done"] == 5
