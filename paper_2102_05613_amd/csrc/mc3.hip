@@ -25,8 +25,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kColPad = 512;     // candidate columns of an instance are padded to this
-constexpr int kTileSplit = 256;  // columns per split-scoring unit (4 waves x 64)
 constexpr int kTileF64 = 128;    // columns per FP64-scoring unit
+constexpr int kClasses = 3;      // split-scoring tile widths: 128, 256, 512 columns (2, 4, 8 waves)
 constexpr int kMaxAhead = 16;    // steps of flip sets drawn per proposal launch, at most
 constexpr size_t kFlipBudget = size_t(512) << 20;  // bytes of flip-set ring, about
 
@@ -40,6 +40,7 @@ struct InstH {
   size_t field = 0;                                    // [chains][Np] FP64 fields (field-update path)
   double scale = 1.0;
   bool have_J = false;
+  int cls = 0;                         // scoring tile class (split: 64 << cls ... columns)
   int unit_off = 0, unit_grid = 0;     // this instance's own unit table (per-instance launches)
   int pblock_off = 0, pblock_cnt = 0;  // its proposal blocks
 };
@@ -52,10 +53,10 @@ struct Plan {
   int prop_T = 256, prop_stride = 1;
   int ahead = 1;    // steps proposed per launch in mc3_step_n
   int nslots = 2;   // flip-set and root ring slots (ahead + 1)
-  std::vector<mc3::Unit> units_global, units_local;
+  std::vector<mc3::Unit> units_global[kClasses], units_local;
   std::vector<mc3::PBlock> pblocks;
   std::vector<int32_t> chain_inst;
-  size_t insts = 0, chain_inst_off = 0, units_global_off = 0, units_local_off = 0, pblocks_off = 0;
+  size_t insts = 0, chain_inst_off = 0, units_global_off[kClasses] = {0, 0, 0}, units_local_off = 0, pblocks_off = 0;
   size_t e_cur = 0, e_bar = 0, roots = 0, candT = 0, ring = 0, means = 0, moves = 0, near = 0, minm = 0, drift = 0,
          erecomp = 0, u_cur = 0, vals = 0, total = 0;
 };
@@ -115,6 +116,12 @@ int resolve_delta(const mc3_batch_config& c, size_t* lds) {
   return delta_fits(c, lds, 8) ? 1 : 0;
 }
 
+// Tile class of an instance's split scoring: 512-column tiles (8 waves share each A
+// tile, half the A copies per MFMA of 4 waves) from 2048 columns up, 128-column tiles
+// (2 waves) for at most 128 columns, 256 otherwise.
+int split_class(int B) { return B >= 2048 ? 2 : (B > 128 ? 1 : 0); }
+int class_waves(int cls) { return 2 << cls; }
+
 // Cost of a scoring unit in 128x128 K blocks: the pair (p, NB-1-p) spans NB+1 blocks
 // of the upper triangle, the self-paired middle block row NB-p.
 int unit_cost(int NB, int p) { return p == NB - 1 - p ? NB - p : NB + 1; }
@@ -171,13 +178,14 @@ Plan make_plan(const mc3_batch_config& cfg) {
   // and the units of one XCD are consecutive in (pair, tile) order, so each XCD's L2
   // holds the J rows of few pairs; trailing slots are idle.  A batch: all units by
   // decreasing cost (stable, so instance order breaks ties), longest first.
-  const int TN = cfg.precision == MC3_SPLIT_BF16 ? kTileSplit : kTileF64;
   struct Cand {
     int inst, p, ct, cost;
   };
-  std::vector<Cand> all;
+  std::vector<Cand> all[kClasses];
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
+    h.cls = cfg.precision == MC3_SPLIT_BF16 ? split_class(h.B) : 0;
+    const int TN = cfg.precision == MC3_SPLIT_BF16 ? 64 * class_waves(h.cls) : kTileF64;
     const int CT = (h.B + TN - 1) / TN;  // tiles holding at least one real column
     const int U = h.P * CT;
     const int per = (U + 7) / 8;
@@ -189,13 +197,15 @@ Plan make_plan(const mc3_batch_config& cfg) {
       if (u < U) un = mc3::Unit{i, u / CT, u % CT, 0};
       pl.units_local.push_back(un);
     }
-    for (int u = 0; u < U; ++u) all.push_back(Cand{i, u / CT, u % CT, unit_cost(h.NB, u / CT)});
+    for (int u = 0; u < U; ++u) all[h.cls].push_back(Cand{i, u / CT, u % CT, unit_cost(h.NB, u / CT)});
   }
   if (n == 1) {
-    pl.units_global = pl.units_local;
+    pl.units_global[pl.inst[0].cls] = pl.units_local;
   } else {
-    std::stable_sort(all.begin(), all.end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
-    for (const Cand& c : all) pl.units_global.push_back(mc3::Unit{c.inst, c.p, c.ct, 0});
+    for (int k = 0; k < kClasses; ++k) {
+      std::stable_sort(all[k].begin(), all[k].end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
+      for (const Cand& c : all[k]) pl.units_global[k].push_back(mc3::Unit{c.inst, c.p, c.ct, 0});
+    }
   }
   // workspace layout
   size_t o = 0;
@@ -207,7 +217,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
   const size_t C = (size_t)pl.total_chains;
   pl.insts = take((size_t)n * sizeof(mc3::Inst));
   pl.chain_inst_off = take(C * 4);
-  pl.units_global_off = take(pl.units_global.size() * sizeof(mc3::Unit));
+  for (int k = 0; k < kClasses; ++k) pl.units_global_off[k] = take(pl.units_global[k].size() * sizeof(mc3::Unit));
   pl.units_local_off = take(pl.units_local.size() * sizeof(mc3::Unit));
   pl.pblocks_off = take(pl.pblocks.size() * sizeof(mc3::PBlock));
   pl.e_cur = take(C * 8);
@@ -453,35 +463,56 @@ mc3_status timing_collect(mc3_ctx* c, size_t i) {
   return MC3_OK;
 }
 
-// One scoring launch over `grid` entries of a unit table (the whole batch's, or one
-// instance's own), for the flip sets of the last proposal.
-mc3_status launch_score_units(mc3_ctx* c, size_t table_off, int grid) {
+// One scoring launch over `grid` entries of a unit table of tile class `cls` (the
+// whole batch's, or one instance's own), for the flip sets of the last proposal.
+mc3_status launch_score_units(mc3_ctx* c, size_t table_off, int grid, int cls) {
   const uint32_t t = c->proposal_step;
   const mc3::Unit* units = c->at<const mc3::Unit>(table_off);
-  if (c->cfg.precision == MC3_SPLIT_BF16)
-    hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
-                       c->roots(t), c->slot(t), t & 1u);
-  else
+  if (c->cfg.precision == MC3_SPLIT_BF16) {
+    if (cls == 2)
+      hipLaunchKernelGGL(mc3::k_score_split<8>, dim3(grid), dim3(512), 0, c->stream, c->ws, c->insts(), units,
+                         c->roots(t), c->slot(t), t & 1u);
+    else if (cls == 1)
+      hipLaunchKernelGGL(mc3::k_score_split<4>, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
+                         c->roots(t), c->slot(t), t & 1u);
+    else
+      hipLaunchKernelGGL(mc3::k_score_split<2>, dim3(grid), dim3(128), 0, c->stream, c->ws, c->insts(), units,
+                         c->roots(t), c->slot(t), t & 1u);
+  } else
     hipLaunchKernelGGL(mc3::k_score_f64, dim3(grid), dim3(256), 0, c->stream, c->ws, c->insts(), units,
                        c->roots(t), c->slot(t), t & 1u);
   return check_launch(c, "score kernel");
 }
 
-mc3_status score_timed(mc3_ctx* c, size_t table_off, int grid) {
-  if (!c->timing) return launch_score_units(c, table_off, grid);
-  const size_t i = c->t_next;
-  c->t_next = (c->t_next + 1) % c->t_start.size();
-  MC3_TRY(timing_collect(c, i));
-  MC3_TRY(hip_ok(c, hipEventRecord(c->t_start[i], c->stream), "timing event"));
-  MC3_TRY(launch_score_units(c, table_off, grid));
-  MC3_TRY(hip_ok(c, hipEventRecord(c->t_stop[i], c->stream), "timing event"));
-  c->t_pending[i] = 1;
+// Scoring launches (one per tile class in `tables`), bracketed by timing events
+// when timing is on.
+struct ScoreLaunch {
+  size_t off;
+  int grid, cls;
+};
+
+mc3_status score_timed(mc3_ctx* c, const ScoreLaunch* tables, int n) {
+  size_t i = 0;
+  if (c->timing) {
+    i = c->t_next;
+    c->t_next = (c->t_next + 1) % c->t_start.size();
+    MC3_TRY(timing_collect(c, i));
+    MC3_TRY(hip_ok(c, hipEventRecord(c->t_start[i], c->stream), "timing event"));
+  }
+  for (int k = 0; k < n; ++k)
+    if (tables[k].grid > 0) MC3_TRY(launch_score_units(c, tables[k].off, tables[k].grid, tables[k].cls));
+  if (c->timing) {
+    MC3_TRY(hip_ok(c, hipEventRecord(c->t_stop[i], c->stream), "timing event"));
+    c->t_pending[i] = 1;
+  }
   return MC3_OK;
 }
 
 mc3_status do_score(mc3_ctx* c, double* E_out) {
   const Plan& pl = c->pl;
-  MC3_TRY(score_timed(c, pl.units_global_off, (int)pl.units_global.size()));
+  ScoreLaunch tl[kClasses];
+  for (int k = 0; k < kClasses; ++k) tl[k] = ScoreLaunch{pl.units_global_off[k], (int)pl.units_global[k].size(), k};
+  MC3_TRY(score_timed(c, tl, kClasses));
   if (E_out) {
     for (const InstH& h : pl.inst) {
       hipLaunchKernelGGL(mc3::k_column_energies, dim3((h.B + 255) / 256), dim3(256), 0, c->stream, E_out + h.col0,
@@ -567,7 +598,8 @@ mc3_status do_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double 
     c->proposal_step = t;
     for (const InstH& h : pl.inst) {
       MC3_TRY(launch_propose(c, t, 1, true, h.pblock_off, h.pblock_cnt));
-      MC3_TRY(score_timed(c, pl.units_local_off + (size_t)h.unit_off * sizeof(mc3::Unit), h.unit_grid));
+      const ScoreLaunch one{pl.units_local_off + (size_t)h.unit_off * sizeof(mc3::Unit), h.unit_grid, h.cls};
+      MC3_TRY(score_timed(c, &one, 1));
       MC3_TRY(launch_select(c, t, beta, false, h.chain0, h.desc.chains));
     }
     MC3_TRY(after_select(c, t, false));
@@ -610,7 +642,8 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
     return n ? hipMemcpyAsync(c->at<char>(off), src, n, hipMemcpyHostToDevice, c->stream) : hipSuccess;
   };
   hipError_t e = up(P.chain_inst_off, P.chain_inst.data(), P.chain_inst.size() * 4);
-  if (e == hipSuccess) e = up(P.units_global_off, P.units_global.data(), P.units_global.size() * sizeof(mc3::Unit));
+  for (int k = 0; k < kClasses && e == hipSuccess; ++k)
+    e = up(P.units_global_off[k], P.units_global[k].data(), P.units_global[k].size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.units_local_off, P.units_local.data(), P.units_local.size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.pblocks_off, P.pblocks.data(), P.pblocks.size() * sizeof(mc3::PBlock));
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

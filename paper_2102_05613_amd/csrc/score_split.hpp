@@ -87,47 +87,62 @@ __device__ __forceinline__ void lds_dma4(const uint32_t* gsrc, uint32_t* lds_bas
                                    (__attribute__((address_space(3))) void*)lds_base, 4, 0, 0);
 }
 
-// LDS stage of the split scoring loop: six A fragments per wave (its row fragment)
-// and, per column of the tile, the flip-set word and the chain's base word.
-template <int CF>
+// LDS stage of the split scoring loop: the four A fragment rows of the block (six
+// fragments each: two 16-k steps x three terms) and, per column of the tile, the
+// flip-set word and the chain's base word.
+template <int WAVES>
 struct SplitStage {
   uint4 a[4][6][64];
-  uint32_t flip[4 * 32 * CF];
-  uint32_t base[4 * 32 * CF];
+  uint32_t flip[WAVES * 64];
+  uint32_t base[WAVES * 64];
 };
 
-// One 32-k chunk of the split scoring loop: DMA of the next chunk (A fragments, flip
-// words, base words) into `nxt`, then 2 k-steps x 12 A fragments x CF columns of
-// MFMAs from `cur`.  Two distinct LDS stages alternate, so the compiler can see that
-// reading one never waits for the copy into the other; nothing loaded from global
-// memory is carried in registers across chunks.  RF_LAST: row fragments rf > RF_LAST
-// of this chunk lie entirely below the diagonal (every k <= i), so their fragments
-// are zero and are neither read nor multiplied.  rootmask bit cf: this lane's column
-// of fragment cf is its chain's root column (bits = base only).
-template <int CF, int RF_LAST = 3>
-__device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitStage<CF>& cur, SplitStage<CF>& nxt,
-                                            const uint4* next_a, const uint32_t* next_flip,
-                                            const uint32_t* const (&next_base)[CF / 2], uint32_t rootmask, int lane,
-                                            int wave) {
+// This wave's share of the 24 A fragments of a chunk (4 fragment rows x 6): PER =
+// 24 / WAVES consecutive slots starting at slot wave * PER, i.e. one fragment row or
+// part of one (PER = 6 or 3), or two whole rows (PER = 12).  src points at the wave's
+// first fragment; the next fragment row is row_stride uint4 further on.
+template <int WAVES>
+__device__ __forceinline__ void copy_a(SplitStage<WAVES>& st, const uint4* src, size_t row_stride, int wave) {
+  constexpr int PER = 24 / WAVES;
+  static_assert(PER == 3 || PER == 6 || PER == 12, "2, 4 or 8 waves");
+  const int slot0 = wave * PER;
 #pragma unroll
-  for (int f = 0; f < 6; ++f) lds_dma16(next_a + f * 64, &nxt.a[wave][f][0]);
-#pragma unroll
-  for (int q = 0; q < CF / 2; ++q) {
-    lds_dma4(next_flip + 64 * q, &nxt.flip[wave * 32 * CF + 64 * q]);
-    lds_dma4(next_base[q], &nxt.base[wave * 32 * CF + 64 * q]);
+  for (int j = 0; j < PER; ++j) {
+    const int rf = (slot0 + j) / 6, f = (slot0 + j) % 6;
+    const int dr = (PER == 12) ? j / 6 : 0;
+    lds_dma16(src + (size_t)dr * row_stride + (size_t)(PER == 12 ? j % 6 : j) * 64, &st.a[rf][f][0]);
   }
+}
+
+// One 32-k chunk of the split scoring loop: DMA of the next chunk into `nxt` (the 24
+// A fragments split evenly over the waves, each wave's own 64 columns' words), then
+// 2 k-steps x 12 A fragments x 2 columns fragments of MFMAs from `cur`.  Two distinct
+// LDS stages alternate, so the compiler can see that reading one never waits for the
+// copy into the other; nothing loaded from global memory is carried in registers
+// across chunks.  RF_LAST: row fragments rf > RF_LAST of this chunk lie entirely below
+// the diagonal (every k <= i), so their fragments are zero and are neither read nor
+// multiplied.  rootmask bit cf: this lane's column of fragment cf is its chain's root
+// column (bits = base only).
+template <int WAVES, int RF_LAST = 3>
+__device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStage<WAVES>& cur,
+                                            SplitStage<WAVES>& nxt, const uint4* next_a, size_t row_stride,
+                                            const uint32_t* next_flip, const uint32_t* next_base, uint32_t rootmask,
+                                            int lane, int wave) {
+  copy_a<WAVES>(nxt, next_a, row_stride, wave);
+  lds_dma4(next_flip, &nxt.flip[64 * wave]);
+  lds_dma4(next_base, &nxt.base[64 * wave]);
   __builtin_amdgcn_sched_barrier(0);
-  uint32_t w[CF];
+  uint32_t w[2];
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) {
-    const int j = wave * 32 * CF + cf * 32 + (lane & 31);
+  for (int cf = 0; cf < 2; ++cf) {
+    const int j = wave * 64 + cf * 32 + (lane & 31);
     w[cf] = cur.base[j] ^ (((rootmask >> cf) & 1u) ? 0u : cur.flip[j]);
   }
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    bf16x8 b[CF];
+    bf16x8 b[2];
 #pragma unroll
-    for (int cf = 0; cf < CF; ++cf) b[cf] = spins_to_bf16((w[cf] >> (16 * s + 8 * (lane >> 5))) & 0xFFu);
+    for (int cf = 0; cf < 2; ++cf) b[cf] = spins_to_bf16((w[cf] >> (16 * s + 8 * (lane >> 5))) & 0xFFu);
     bf16x8 a[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
@@ -141,7 +156,7 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
     for (int i = 0; i < 12; ++i) {
       if (i % 4 > RF_LAST) continue;
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf)
+      for (int cf = 0; cf < 2; ++cf)
         acc[i % 4][cf] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[cf], acc[i % 4][cf], 0, 0, 0);
     }
   }
@@ -152,23 +167,26 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
 // Energies of candidate columns on the BF16 matrix cores.
 //
 // E(c) = -scale * sum_i c_i h_i with h_i = sum_{j>i} J_ij c_j (strict upper triangle),
-// J = hi + mid + lo.  A work unit is (row-block pair p, column tile): row blocks p and
-// NB-1-p (128 rows each; their K ranges start at the block's first row, so the pair
-// costs NB+1 blocks of K whatever p is).  Four waves share the A tiles through LDS,
-// filled by direct global->LDS copies one 32-k chunk ahead (double-buffered); each
-// wave owns 32*CF columns whose flip-set and base words come through LDS the same way
-// and are combined and expanded to +-1 in registers.  The epilogue multiplies h by
-// the column's spins and sums over rows in FP64; the unit writes one FP64 value per
-// column.  Each block takes its unit from a table built by the host (the order of
+// J = hi + mid + lo.  A work unit is (row-block pair p, column tile of 64 WAVES
+// columns; 2, 4 or 8 waves, chosen per instance so that small instances waste few
+// padding columns): row blocks p and NB-1-p (128 rows each; their K ranges start at the
+// block's first row, so the pair costs NB+1 blocks of K whatever p is).  The waves
+// share the A fragments through LDS, filled by direct global->LDS copies one 32-k
+// chunk ahead (two stages, the copy running on from one row block into the next);
+// each wave owns 64 columns whose flip-set and base words come through LDS the same
+// way and are combined and expanded to +-1 in registers.  The epilogue multiplies h
+// by the column's spins and sums over rows in FP64; the unit writes one FP64 value
+// per column.  Each block takes its unit from a table built by the host (the order of
 // the table decides which XCD runs which unit).
-template <int CF>
-__global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
     char* __restrict__ ws, const Inst* __restrict__ insts, const Unit* __restrict__ units,
     const int32_t* __restrict__ roots_all, uint32_t slot, uint32_t parity) {
-  static_assert(CF % 2 == 0, "CF must be even (64-column copies)");
-  constexpr int TN = 4 * 32 * CF;
-  __shared__ SplitStage<CF> st0;
-  __shared__ SplitStage<CF> st1;
+  constexpr int TN = 64 * WAVES;
+  constexpr int PER = 24 / WAVES;
+  static_assert(WAVES == 2 || WAVES == 4 || WAVES == 8, "2, 4 or 8 waves");
+  __shared__ SplitStage<WAVES> st0;
+  __shared__ SplitStage<WAVES> st1;
   const Unit un = units[blockIdx.x];
   if (un.inst < 0) return;
   const Inst& in = insts[un.inst];
@@ -181,21 +199,18 @@ __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
   const int p = un.p, ct = un.ct;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int col_w = ct * TN + wave * 32 * CF;   // first column of this wave
+  const int col_w = ct * TN + wave * 64;   // first column of this wave
   const int KS = Np / 16;
   const int W = Np / 32;
   const int B = chains * M;
+  const int rf_w = (wave * PER) / 6, f_w = (wave * PER) % 6;   // this wave's first A copy slot
+  const size_t row_stride = (size_t)KS * 3 * 64;                 // uint4 between fragment rows
 
-  // per-lane column data: base rows of the copied columns, root-column mask
-  const uint32_t* brow[CF / 2];
-#pragma unroll
-  for (int q = 0; q < CF / 2; ++q) {
-    const int col = col_w + 64 * q + lane;
-    brow[q] = base + (size_t)(col < B ? col / M : chains) * W;
-  }
+  // per-lane column data: base row of the copied column, root-column mask
+  const uint32_t* brow = base + (size_t)(col_w + lane < B ? (col_w + lane) / M : chains) * W;
   uint32_t rootmask = 0u;
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) {
+  for (int cf = 0; cf < 2; ++cf) {
     const int col = col_w + cf * 32 + (lane & 31);
     if (col < B) {
       const int c = col / M, r = roots[c];
@@ -203,76 +218,76 @@ __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
     }
   }
 
-  double part[CF];
-#pragma unroll
-  for (int cf = 0; cf < CF; ++cf) part[cf] = 0.0;
+  double part[2] = {0.0, 0.0};
 
+  // the unit's row blocks p and NB-1-p, in an order that alternates between units
   const int nblk = (p == NB - 1 - p) ? 1 : 2;
+  const int first = ((p + ct) & 1) ? NB - 1 - p : p;
+  const int second = NB - 1 - first;
+  // this wave's first A fragment of chunk 0 of row block I
+  auto a_src = [&](int I) {
+    return Apack + (((size_t)(4 * I + rf_w) * KS + 8 * I) * 3 + f_w) * 64 + lane;
+  };
+  {
+    const int kw = 4 * first;
+    copy_a<WAVES>(st0, a_src(first), row_stride, wave);
+    lds_dma4(flipsT + (size_t)kw * Bp + col_w + lane, &st0.flip[64 * wave]);
+    lds_dma4(brow + kw, &st0.base[64 * wave]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+
   for (int bi = 0; bi < nblk; ++bi) {
-    const int I = bi == 0 ? p : NB - 1 - p;
-    const int k0 = I * kRowBlock;
-    const int kw0 = k0 >> 5;
-    const int nchunk = (Np - k0) / 32;   // a multiple of 4
-    f32x16 acc[4][CF];
+    const int I = bi == 0 ? first : second;
+    const int kw0 = 4 * I;
+    const int nchunk = (Np - I * kRowBlock) / 32;   // a multiple of 4
+    f32x16 acc[4][2];
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf)
+      for (int cf = 0; cf < 2; ++cf)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[rf][cf][e] = 0.0f;
 
-    // this wave copies fragment row R = 4I + wave (six fragments per chunk) and the
-    // flip/base words of its own columns
-    const uint4* src = Apack + (((size_t)(4 * I + wave) * KS + (k0 / 16)) * 3) * 64 + lane;
+    const uint4* src = a_src(I);
     const uint32_t* fsrc = flipsT + (size_t)kw0 * Bp + col_w + lane;
-    const uint32_t* bsrc[CF / 2];
-#pragma unroll
-    for (int q = 0; q < CF / 2; ++q) bsrc[q] = brow[q] + kw0;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) lds_dma16(src + f * 64, &st0.a[wave][f][0]);
-#pragma unroll
-    for (int q = 0; q < CF / 2; ++q) {
-      lds_dma4(fsrc + 64 * q, &st0.flip[wave * 32 * CF + 64 * q]);
-      lds_dma4(bsrc[q], &st0.base[wave * 32 * CF + 64 * q]);
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-
+    // the chunk after this block's last: the next block's first chunk, or (none) this
+    // block's last chunk again (in bounds; not read before the next refill)
+    const bool more = bi + 1 < nblk;
+    const int kwn = more ? 4 * second : kw0 + nchunk - 1;
+    const uint4* src_n = more ? a_src(second) : src + (size_t)(nchunk - 1) * 6 * 64;
+    const uint32_t* fsrc_n = flipsT + (size_t)kwn * Bp + col_w + lane;
     // chunk c of this row block: A at src + 6*64 c, flip words at fsrc + Bp c, base
-    // words at bsrc + c.  The first four chunks cover the diagonal block: chunk c needs
-    // row fragments 0..c (nchunk is a multiple of 4; past the end a copy re-reads the
-    // last chunk, which is in bounds and not read again before the next row block
-    // refills the stage after a barrier).
-#define MC3_NEXT(cn)                                                                 \
-  const uint32_t* nb##cn[CF / 2];                                                    \
-  _Pragma("unroll") for (int q = 0; q < CF / 2; ++q) nb##cn[q] = bsrc[q] + (cn);
+    // words at brow + kw0 + c; the first four chunks cover the diagonal block: chunk c
+    // needs row fragments 0..c (nchunk is a multiple of 4)
+#define MC3_NEXT(cn)                                                                       \
+  const bool e##cn = (cn) >= nchunk;                                                       \
+  const uint4* na##cn = e##cn ? src_n : src + (size_t)(cn) * 6 * 64;                       \
+  const uint32_t* nf##cn = e##cn ? fsrc_n : fsrc + (size_t)(cn) * Bp;                      \
+  const uint32_t* nb##cn = brow + (e##cn ? kwn : kw0 + (cn));
     {
-      const int c1 = 1, c2 = 2;
-      const int c3 = 3 < nchunk - 1 ? 3 : nchunk - 1;
-      const int c4 = 4 < nchunk - 1 ? 4 : nchunk - 1;
-      MC3_NEXT(c1)
-      split_chunk<CF, 0>(acc, st0, st1, src + (size_t)c1 * 6 * 64, fsrc + (size_t)c1 * Bp, nbc1, rootmask, lane, wave);
-      MC3_NEXT(c2)
-      split_chunk<CF, 1>(acc, st1, st0, src + (size_t)c2 * 6 * 64, fsrc + (size_t)c2 * Bp, nbc2, rootmask, lane, wave);
-      MC3_NEXT(c3)
-      split_chunk<CF, 2>(acc, st0, st1, src + (size_t)c3 * 6 * 64, fsrc + (size_t)c3 * Bp, nbc3, rootmask, lane, wave);
-      MC3_NEXT(c4)
-      split_chunk<CF, 3>(acc, st1, st0, src + (size_t)c4 * 6 * 64, fsrc + (size_t)c4 * Bp, nbc4, rootmask, lane, wave);
+      MC3_NEXT(1)
+      split_chunk<WAVES, 0>(acc, st0, st1, na1, row_stride, nf1, nb1, rootmask, lane, wave);
+      MC3_NEXT(2)
+      split_chunk<WAVES, 1>(acc, st1, st0, na2, row_stride, nf2, nb2, rootmask, lane, wave);
+      MC3_NEXT(3)
+      split_chunk<WAVES, 2>(acc, st0, st1, na3, row_stride, nf3, nb3, rootmask, lane, wave);
+      MC3_NEXT(4)
+      split_chunk<WAVES, 3>(acc, st1, st0, na4, row_stride, nf4, nb4, rootmask, lane, wave);
     }
     for (int c = 4; c < nchunk; c += 2) {
-      const int ca = c + 1;
-      const int cb = (c + 2 < nchunk) ? c + 2 : nchunk - 1;
+      const int ca = c + 1, cb = c + 2;
       MC3_NEXT(ca)
-      split_chunk<CF>(acc, st0, st1, src + (size_t)ca * 6 * 64, fsrc + (size_t)ca * Bp, nbca, rootmask, lane, wave);
+      split_chunk<WAVES>(acc, st0, st1, naca, row_stride, nfca, nbca, rootmask, lane, wave);
       MC3_NEXT(cb)
-      split_chunk<CF>(acc, st1, st0, src + (size_t)cb * 6 * 64, fsrc + (size_t)cb * Bp, nbcb, rootmask, lane, wave);
+      split_chunk<WAVES>(acc, st1, st0, nacb, row_stride, nfcb, nbcb, rootmask, lane, wave);
     }
 #undef MC3_NEXT
     // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf + lane%32
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf) {
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf) {
+      for (int cf = 0; cf < 2; ++cf) {
         const int col = col_w + cf * 32 + (lane & 31);
         const int rw = 4 * I + rf;
         const uint32_t bw = col < B ? base[(size_t)(col / M) * W + rw] : 0u;
@@ -289,7 +304,7 @@ __global__ __launch_bounds__(256, (CF == 2 ? 2 : 1)) void k_score_split(
     }
   }
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) {
+  for (int cf = 0; cf < 2; ++cf) {
     const double other = __shfl_xor(part[cf], 32);
     const double tot = part[cf] + other;
     if (lane < 32) partial[(size_t)p * Bp + col_w + cf * 32 + lane] = tot;
