@@ -33,6 +33,7 @@ _LIB = os.path.join(_HERE, "libmc3_oracle.so")
 
 TAG_INIT, TAG_ROOT, TAG_EDGE, TAG_SELECT = 1, 2, 3, 4
 RULE_MCMCMC, RULE_METROPOLIS = 0, 1
+LAW_UNIFORM, LAW_LINE = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -54,7 +55,8 @@ class Cfg(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("chains", ctypes.c_int32),
                 ("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("chain_base", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64), ("scale", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("scale", ctypes.c_double), ("arity", ctypes.c_int32),
+                ("law", ctypes.c_int32)]
 
 
 REC_DTYPE = np.dtype([("r", np.int32), ("vstar", np.int32), ("e_cur", np.float64),
@@ -86,7 +88,10 @@ def lib():
         L.mc3o_edge_flips.restype = i32
         L.mc3o_root.argtypes = [u64, u32, u32, i32]
         L.mc3o_root.restype = i32
-        L.mc3o_build_nodes.argtypes = [i32, i32, i32, P(ctypes.c_int8), P(ctypes.c_uint8), P(ctypes.c_int8)]
+        L.mc3o_root_line.argtypes = [u64, u32, u32, i32]
+        L.mc3o_root_line.restype = i32
+        L.mc3o_log_prior_line.argtypes = [i32, P(dbl)]
+        L.mc3o_build_nodes.argtypes = [i32, i32, i32, i32, P(ctypes.c_int8), P(ctypes.c_uint8), P(ctypes.c_int8)]
         L.mc3o_select_mcmcmc.argtypes = [i32, P(dbl), P(dbl), dbl, u64, P(dbl), P(dbl), P(u64)]
         L.mc3o_select_mcmcmc.restype = i32
         L.mc3o_accept_metropolis.argtypes = [dbl, dbl, dbl, u64, P(dbl)]
@@ -151,19 +156,32 @@ def edge_flips(seed, chain, step, edge, N, kmin, kmax):
     return int(k), m
 
 
-def root(seed, chain, step, M) -> int:
+def root(seed, chain, step, M, law: int = LAW_UNIFORM) -> int:
+    """Root position: uniform over the M+1 nodes, or the line process's left count."""
+    if law == LAW_LINE:
+        return int(lib().mc3o_root_line(seed, chain, step, M))
     return int(lib().mc3o_root(seed, chain, step, M))
 
 
-def propose_nodes(seed, chain, step, N, M, kmin, kmax, s, rule=RULE_MCMCMC):
-    """Root and node configurations [(M+1), N] of the star graph generated from s."""
-    r = 0 if rule == RULE_METROPOLIS else root(seed, chain, step, M)
+def log_prior_line(M: int) -> np.ndarray:
+    """log C(M, v), v = 0..M: the line-graph addition process's log-prior."""
+    out = np.zeros(M + 1, dtype=np.float64)
+    lib().mc3o_log_prior_line(M, _ptr(out, ctypes.c_double))
+    return out
+
+
+def propose_nodes(seed, chain, step, N, M, kmin, kmax, s, rule=RULE_MCMCMC, arity: Optional[int] = None,
+                  law: int = LAW_UNIFORM):
+    """Root and node configurations [(M+1), N] of the tree (arity a, default the star
+    a = M) generated from s."""
+    arity = M if arity is None else arity
+    r = 0 if rule == RULE_METROPOLIS else root(seed, chain, step, M, law)
     flips = np.zeros((M + 1, N), dtype=np.uint8)
     for e in range(1, M + 1):
         flips[e] = edge_flips(seed, chain, step, e, N, kmin, kmax)[1]
     nodes = np.zeros((M + 1, N), dtype=np.int8)
     s = np.ascontiguousarray(s, dtype=np.int8)
-    lib().mc3o_build_nodes(N, M, r, _ptr(s, ctypes.c_int8), _ptr(flips, ctypes.c_uint8),
+    lib().mc3o_build_nodes(N, M, arity, r, _ptr(s, ctypes.c_int8), _ptr(flips, ctypes.c_uint8),
                            _ptr(nodes, ctypes.c_int8))
     return r, nodes
 
@@ -187,7 +205,8 @@ def accept_metropolis(e_cur: float, e_new: float, beta: float, u53_value: int):
 
 def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kmax: int, seed: int,
         betas, spins: Optional[np.ndarray] = None, step0: int = 0, rule: int = RULE_MCMCMC,
-        chain_base: int = 0, want_node_e: bool = False, forced: Optional[np.ndarray] = None):
+        chain_base: int = 0, want_node_e: bool = False, forced: Optional[np.ndarray] = None,
+        arity: Optional[int] = None, law: int = LAW_UNIFORM):
     """Run len(betas) steps.  Returns dict(spins, e_cur, rec[, node_e]).
 
     Initial spins default to the INIT stream of each chain; energies are recomputed
@@ -205,7 +224,7 @@ def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kma
     if forced is not None:
         f = np.ascontiguousarray(forced, dtype=np.int32)
         assert f.shape == (nsteps, chains)
-    cfg = Cfg(N, M, chains, kmin, kmax, rule, chain_base, 0, seed, scale)
+    cfg = Cfg(N, M, chains, kmin, kmax, rule, chain_base, 0, seed, scale, M if arity is None else arity, law)
     rc = lib().mc3o_run(ctypes.byref(cfg), _ptr(J, ctypes.c_double), _ptr(spins, ctypes.c_int8),
                         _ptr(e_cur, ctypes.c_double), step0, nsteps, _ptr(betas, ctypes.c_double),
                         rec.ctypes.data, None if node_e is None else node_e.ctypes.data,

@@ -21,8 +21,18 @@
  *    populated with a two-body generation probability.  With a uniform root and a
  *    symmetric two-body law the tree is self-thermalising: P_gen(T|c_v) is the same
  *    for every node, so P_node reduces to exp(-beta E_v) normalised over the nodes.
- *    The tree used is a star: a hub (node 0) and M leaves (nodes 1..M), edge e
- *    joining the hub and leaf e and carrying a flip set F_e.
+ *    The trees used are labelled breadth first: node 0 on top, the parent of node
+ *    v >= 1 is (v-1)/a for arity a, edge e joins node e to its parent and carries a
+ *    flip set F_e.  Arity M is the star (hub 0, leaves 1..M); the paper's k-ary trees
+ *    (Fig. fig_sk) are arities 2, 3 and 16.  Node v holds the current state with the
+ *    flip sets of every edge on the path from the root position r to v flipped.
+ *  - Line-graph addition process, App. "Line-graph addition process": starting from
+ *    the current state, M nodes are added, each at the left or right end with
+ *    probability 1/2.  With flip sets that do not depend on the state, this is the
+ *    line (arity 1) with the current state at position r ~ Binomial(M, 1/2), and
+ *    P_gen(T|c_v) carries the factor C(M, v) / 2^M (the printed prefactor is
+ *    garbled; C(L-1, k) / 2^(L-1) with L = M+1 nodes is the reading taken), which
+ *    enters the node rule as the log-prior log C(M, v).
  *  - Standard MCMC with the Metropolis rate min(1, ratio), Sec. "Problem statement",
  *    for the single-update baseline (rule METROPOLIS, M = 1).
  *  - Observables as node-weighted averages over the graph, Eq. eq_monte_carlo_graph.
@@ -207,23 +217,48 @@ int mc3o_root(uint64_t seed, uint32_t chain, uint32_t step, int M)
     return (int)mc3o_randint(mc3o_word(seed, TAG_ROOT, chain, step, 0u, 0u), (uint32_t)(M + 1));
 }
 
-/* Node configurations of the star graph generated from the current state s.
- * Root r = 0: hub = s, leaf e = s with F_e flipped.
- * Root r >= 1: leaf r = s, hub = s with F_r flipped, leaf e != r = hub with F_e
- * flipped.  nodes: [(M+1) x N] int8. */
-void mc3o_build_nodes(int N, int M, int r, const int8_t* s, const uint8_t* flips /*[M+1][N], row 0 unused*/,
-                      int8_t* nodes)
+/* Root position of the line-graph addition process: the number of the M additions
+ * that went to the left end, addition j going left iff bit j%32 of ROOT word j/32
+ * is set (j = 0..M-1). */
+int mc3o_root_line(uint64_t seed, uint32_t chain, uint32_t step, int M)
 {
+    int k = 0;
+    for (int j = 0; j < M; ++j) {
+        uint32_t w = mc3o_word(seed, TAG_ROOT, chain, step, 0u, (uint32_t)(j / 32));
+        k += (int)((w >> (j % 32)) & 1u);
+    }
+    return k;
+}
+
+/* log C(M, v) for v = 0..M: the line process's log-prior, lgamma(M+1) - lgamma(v+1)
+ * - lgamma(M-v+1) evaluated left to right. */
+void mc3o_log_prior_line(int M, double* out)
+{
+    for (int v = 0; v <= M; ++v)
+        out[v] = lgamma((double)M + 1.0) - lgamma((double)v + 1.0) - lgamma((double)(M - v) + 1.0);
+}
+
+/* Node configurations of the tree (M+1 nodes, arity a; a = M is the star) generated
+ * from the current state s sitting at node r: node v is s with the flip sets of the
+ * edges on the path between r and v flipped.  With path(v) = the edges from node 0
+ * down to v, that set is path(r) xor path(v) (the common part cancels).  For the
+ * star: r = 0 gives hub = s, leaf e = s^F_e; r >= 1 gives leaf r = s, hub = s^F_r,
+ * leaf e = s^F_r^F_e.  flips: [(M+1) x N], row 0 unused; nodes: [(M+1) x N] int8. */
+void mc3o_build_nodes(int N, int M, int arity, int r, const int8_t* s, const uint8_t* flips, int8_t* nodes)
+{
+    uint8_t* path = (uint8_t*)calloc((size_t)(M + 1) * N, 1);
+    for (int v = 1; v <= M; ++v) {
+        int par = (v - 1) / arity;
+        for (int i = 0; i < N; ++i)
+            path[(size_t)v * N + i] = path[(size_t)par * N + i] ^ flips[(size_t)v * N + i];
+    }
     for (int v = 0; v <= M; ++v) {
         for (int i = 0; i < N; ++i) {
-            int flip;
-            if (r == 0) flip = (v == 0) ? 0 : flips[(size_t)v * N + i];
-            else if (v == r) flip = 0;
-            else if (v == 0) flip = flips[(size_t)r * N + i];
-            else flip = flips[(size_t)r * N + i] ^ flips[(size_t)v * N + i];
+            int flip = path[(size_t)r * N + i] ^ path[(size_t)v * N + i];
             nodes[(size_t)v * N + i] = flip ? (int8_t)(-s[i]) : s[i];
         }
     }
+    free(path);
 }
 
 /* ------------------------------------------------------------------------ select */
@@ -301,6 +336,8 @@ typedef struct {
     uint32_t pad;
     uint64_t seed;
     double scale;          /* energy scale: E = -scale * sum_{i<j} J_ij s_i s_j */
+    int32_t arity;         /* tree arity (parent of v is (v-1)/arity); 0 = M (the star) */
+    int32_t law;           /* 0 = uniform root, 1 = line-graph addition process (arity 1) */
 } mc3o_cfg;
 
 /* Run nsteps steps starting at global step step0 for every chain.
@@ -320,6 +357,13 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
     const int N = cfg->N, M = cfg->M;
     if (N < 2 || M < 1 || cfg->chains < 1 || cfg->kmin < 1 || cfg->kmax < cfg->kmin || cfg->kmax > N) return -1;
     if (cfg->rule == 1 && M != 1) return -1;
+    const int arity = cfg->arity > 0 ? cfg->arity : M;
+    if (arity > M || cfg->law < 0 || cfg->law > 1 || (cfg->law == 1 && arity != 1)) return -1;
+    double* log_prior = NULL;
+    if (cfg->law == 1) {
+        log_prior = (double*)malloc(sizeof(double) * (size_t)(M + 1));
+        mc3o_log_prior_line(M, log_prior);
+    }
     uint8_t* flips = (uint8_t*)malloc((size_t)(M + 1) * N);
     int8_t* nodes = (int8_t*)malloc((size_t)(M + 1) * N);
     double* E = (double*)malloc(sizeof(double) * (size_t)(M + 1));
@@ -328,11 +372,12 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
         for (int c = 0; c < cfg->chains; ++c) {
             uint32_t gc = cfg->chain_base + (uint32_t)c;
             int8_t* s = spins + (size_t)c * N;
-            int r = (cfg->rule == 1) ? 0 : mc3o_root(cfg->seed, gc, step, M);
+            int r = (cfg->rule == 1) ? 0
+                    : (cfg->law == 1 ? mc3o_root_line(cfg->seed, gc, step, M) : mc3o_root(cfg->seed, gc, step, M));
             memset(flips, 0, (size_t)N);
             for (int e = 1; e <= M; ++e)
                 mc3o_edge_flips(cfg->seed, gc, step, (uint32_t)e, N, cfg->kmin, cfg->kmax, flips + (size_t)e * N);
-            mc3o_build_nodes(N, M, r, s, flips, nodes);
+            mc3o_build_nodes(N, M, arity, r, s, flips, nodes);
             for (int v = 0; v <= M; ++v) E[v] = mc3o_energy(N, J, cfg->scale, nodes + (size_t)v * N);
             uint32_t w0 = mc3o_word(cfg->seed, TAG_SELECT, gc, step, 0u, 0u);
             uint32_t w1 = mc3o_word(cfg->seed, TAG_SELECT, gc, step, 0u, 1u);
@@ -345,7 +390,7 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
                 vs = acc ? 1 : 0;
                 ebar = E[vs];
             } else {
-                vs = mc3o_select_mcmcmc(M + 1, E, NULL, beta[ts], u53, &ebar, &margin, &wsum);
+                vs = mc3o_select_mcmcmc(M + 1, E, log_prior, beta[ts], u53, &ebar, &margin, &wsum);
             }
             if (forced && forced[(size_t)ts * cfg->chains + c] >= 0)
                 vs = forced[(size_t)ts * cfg->chains + c];
@@ -359,6 +404,6 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
             }
         }
     }
-    free(flips); free(nodes); free(E);
+    free(flips); free(nodes); free(E); free(log_prior);
     return 0;
 }

@@ -149,3 +149,57 @@ def line_graph_generation(L: int) -> np.ndarray:
         left = sum(1 for b in bits if b == 0)
         g[left] += 0.5 ** (L - 1)
     return g
+
+
+# ---------------------------------------------------------------- trees and lines
+
+def tree_parent(v: int, arity: int) -> int:
+    """Parent of node v >= 1 in the breadth-first labelling of an arity-ary tree
+    (node 0 on top; arity 1 is a line, arity M the M-ary star)."""
+    return (v - 1) // arity
+
+
+def tree_kernel(E: np.ndarray, beta: float, N: int, M: int, arity: int, kmin: int, kmax: int,
+                law: str = "uniform", prior: str = "none") -> np.ndarray:
+    """Exact transition matrix of one MCMCMC step on the tree with M+1 nodes
+    (breadth-first labelling, parent(v) = (v-1) // arity), every edge populated with an
+    independent flip set, over all root positions and all flip-set realisations.
+
+    law "uniform": the current state sits at node r ~ U{0..M} (populating process
+    with a uniform root).  law "line" (arity 1): r ~ Binomial(M, 1/2), the position of
+    the starting node after M additions at either end of a line.
+    prior: "none" (weights exp(-beta E_v)), "comb" (times C(M, v), the line process's
+    generation probability of the graph from node v), or "printed" (times C(M+1, v),
+    the printed form) -- the last two for the line law.
+    Node v's configuration is the current state with the flip sets of every edge on
+    the path from r to v flipped."""
+    S = 2 ** N
+    masks, probs = flip_sets(N, kmin, kmax)
+    nF = len(masks)
+    V = M + 1
+    P = np.zeros((S, S))
+    combos = np.array(list(itertools.product(range(nF), repeat=M)), dtype=np.int64)  # edge e = column e-1
+    cprob = np.prod(probs[combos], axis=1)
+    fm = masks[combos]                                                                # [C, M]
+    # path masks from node 0: Ppath[:, v] = xor of the flip sets on the path 0 -> v
+    Ppath = np.zeros((len(combos), V), dtype=np.int64)
+    for v in range(1, V):
+        Ppath[:, v] = Ppath[:, tree_parent(v, arity)] ^ fm[:, v - 1]
+    if law == "uniform":
+        roots = [(r, 1.0 / V) for r in range(V)]
+    else:
+        roots = [(r, math.comb(M, r) / 2 ** M) for r in range(V)]
+    if prior == "comb":
+        g = np.array([math.comb(M, v) for v in range(V)], dtype=np.float64)
+    elif prior == "printed":
+        g = np.array([math.comb(M + 1, v) for v in range(V)], dtype=np.float64)
+    else:
+        g = np.ones(V)
+    for s in range(S):
+        for r, pr in roots:
+            nodes = s ^ Ppath[:, r:r + 1] ^ Ppath
+            En = E[nodes]
+            w = np.exp(-beta * (En - En.min(axis=1, keepdims=True))) * g[None, :]
+            pn = w / w.sum(axis=1, keepdims=True)
+            np.add.at(P, (np.full(nodes.shape, s), nodes), pr * cprob[:, None] * pn)
+    return P

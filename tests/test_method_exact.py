@@ -170,3 +170,50 @@ def test_line_graph_prior_reading(L):
         assert g[k] == pytest.approx(math.comb(L - 1, k) / 2 ** (L - 1), rel=1e-14)
     printed = np.array([math.comb(L, k) / 2 ** L for k in range(L)])
     assert abs(printed.sum() - 1.0) > 1e-3
+
+
+# ---------------------------------------------------------------- trees and lines
+
+from exact_tools import tree_kernel  # noqa: E402
+
+
+def _stationary_and_reversible(P, pi, tol=1e-12):
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-13)
+    assert np.max(np.abs(pi @ P - pi)) < tol
+    F = pi[:, None] * P
+    assert np.max(np.abs(F - F.T)) < tol
+
+
+@pytest.mark.parametrize("M,arity,kmin,kmax,beta", [(3, 2, 1, 1, 1.3), (4, 2, 1, 2, 0.8), (3, 1, 1, 1, 2.0),
+                                                    (4, 3, 1, 1, 1.0)])
+def test_tree_uniform_root_is_stationary_and_reversible(M, arity, kmin, kmax, beta):
+    """Any tree populated from a uniformly drawn root with a symmetric two-body law
+    is self-thermalising (App. 'General graph populating process'): the node rule with
+    plain Boltzmann weights leaves the Boltzmann law invariant."""
+    N = 3
+    J, scale = inputs.couplings_gauss(N, 40 + M + arity)
+    E = all_energies(J, scale)
+    P = tree_kernel(E, beta, N, M, arity, kmin, kmax)
+    _stationary_and_reversible(P, boltzmann(E, beta))
+    # arity M is the star of the main path
+    if arity == M:
+        from exact_tools import star_kernel
+        assert np.allclose(P, star_kernel(E, beta, N, M, kmin, kmax), atol=1e-14)
+
+
+@pytest.mark.parametrize("M", [2, 3])
+def test_line_addition_process_needs_its_prior(M):
+    """Line-graph addition process (App. 'Line-graph addition process'): the starting
+    node sits at position k ~ Binomial(M, 1/2) of a line of L = M+1 nodes, so
+    P_gen(T|c_v) carries C(L-1, v) (reading of the garbled prefactor).  With that
+    factor in the node weights the chain is stationary; without it, or with the
+    printed C(L, v), it is not."""
+    N, beta = 3, 1.5
+    J, scale = inputs.couplings_gauss(N, 91 + M)
+    E = all_energies(J, scale)
+    pi = boltzmann(E, beta)
+    good = tree_kernel(E, beta, N, M, 1, 1, 1, law="line", prior="comb")
+    _stationary_and_reversible(good, pi)
+    for bad in ("none", "printed"):
+        P = tree_kernel(E, beta, N, M, 1, 1, 1, law="line", prior=bad)
+        assert np.max(np.abs(pi @ P - pi)) > 1e-4, bad

@@ -85,3 +85,69 @@ def test_node_energies_recorded_and_nodes_follow_star_rule():
         assert np.array_equal(nodes[r], s[c])
         for v in range(M + 1):
             assert out["node_e"][0, c, v] == oracle.energy(J, scale, nodes[v])
+
+
+# ---------------------------------------------------------------- trees and lines
+
+from exact_tools import tree_kernel  # noqa: E402
+
+
+def test_line_root_is_binomial():
+    """The line process's root (number of left additions among M) is Binomial(M, 1/2)."""
+    import math
+    M, n = 9, 20000
+    r = np.array([oracle.root(3, c % 64, c // 64, M, oracle.LAW_LINE) for c in range(n)])
+    probs = np.array([math.comb(M, k) / 2 ** M for k in range(M + 1)])
+    stat, dof = _chi2_pass(np.bincount(r, minlength=M + 1), probs, n)
+    assert stat < dof + 6 * np.sqrt(2 * dof), (stat, dof)
+
+
+def test_line_log_prior_is_log_binomial():
+    import math
+    for M in (1, 4, 127):
+        lp = oracle.log_prior_line(M)
+        exact = np.array([math.log(math.comb(M, v)) for v in range(M + 1)])
+        np.testing.assert_allclose(lp, exact, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("M,arity,law,kmin,kmax,beta,start", [
+    (3, 2, oracle.LAW_UNIFORM, 1, 1, 1.0, 5),
+    (4, 2, oracle.LAW_UNIFORM, 1, 2, 0.8, 11),
+    (3, 1, oracle.LAW_LINE, 1, 1, 1.5, 19),
+    (3, 1, oracle.LAW_UNIFORM, 1, 1, 1.2, 2),
+])
+def test_tree_one_step_frequencies_match_exact_row(M, arity, law, kmin, kmax, beta, start):
+    N, K = 5, 40000
+    J, scale = inputs.couplings_gauss(N, 23)
+    E = all_energies(J, scale)
+    P = tree_kernel(E, beta, N, M, arity, kmin, kmax, law="line" if law == oracle.LAW_LINE else "uniform",
+                    prior="comb" if law == oracle.LAW_LINE else "none")
+    s0 = spins_of(np.array([start]), N)[0].astype(np.int8)
+    spins = np.repeat(s0[None, :], K, axis=0)
+    out = oracle.run(J, scale, N, M, K, kmin, kmax, seed=78, betas=[beta], spins=spins, arity=arity, law=law)
+    counts = np.bincount(_states_of(out["spins"]), minlength=2 ** N)
+    stat, dof = _chi2_pass(counts, P[start], K)
+    assert stat < dof + 6 * np.sqrt(2 * dof), (stat, dof)
+
+
+def test_tree_nodes_follow_path_rule():
+    """Node v of the tree is the current state with the flip sets of the edges between
+    the root position and v flipped (checked edge by edge on a binary tree)."""
+    N, M, arity = 40, 9, 2
+    s = oracle.init_spins(4, N, 0)
+    for step in range(6):
+        r, nodes = oracle.propose_nodes(4, 0, step, N, M, 1, 3, s, arity=arity)
+        F = [None] + [oracle.edge_flips(4, 0, step, e, N, 1, 3)[1].astype(bool) for e in range(1, M + 1)]
+
+        def up(v):
+            out = []
+            while v:
+                out.append(v)
+                v = (v - 1) // arity
+            return out
+        for v in range(M + 1):
+            a, b = set(up(r)), set(up(v))
+            flip = np.zeros(N, dtype=bool)
+            for e in a ^ b:
+                flip ^= F[e]
+            assert np.array_equal(nodes[v], np.where(flip, -s, s)), (step, r, v)
