@@ -74,11 +74,34 @@ typedef enum {
  *          dU = -2 sum_{i in D} s_i h_i + 4 sum_{i<j in D} J_ij s_i s_j (|D| + |D|^2/2
  *          couplings per candidate instead of N^2); a move updates h with the |D|
  *          rows of J.  All steps of a chain run in one persistent workgroup.  Limits:
- *          kmax <= 16, M <= 512, N <= 4096 and the per-chain state within 64 KiB of
- *          LDS (MC3_E_UNSUPPORTED otherwise); only mc3_step_n moves the chains
+ *          kmax <= 16, M <= 512, N <= 4096, kmax times the longest path between two
+ *          nodes (in edges) <= 32 and the per-chain state within 64 KiB of LDS
+ *          (MC3_E_UNSUPPORTED otherwise); only mc3_step_n moves the chains
  *          (mc3_propose, mc3_score_candidates, mc3_select, mc3_read_candidates and
  *          mc3_step_n_per_instance return MC3_E_UNSUPPORTED).  `precision` is unused.
- *   AUTO:  DELTA where its limits hold and kmax <= 8, else GEMM. */
+ *   AUTO:  DELTA where its limits hold and kmax times the longest path is at most
+ *          16, else GEMM. */
+/* How the current state is placed in the graph (the root law of the populating
+ * process).  The graph is the tree on M+1 nodes labelled breadth first with the
+ * parent of node v >= 1 at (v-1)/arity; edge v joins node v to its parent and carries
+ * the flip set F_v; node v holds the state at node 0 with the flip sets of the edges
+ * from node 0 down to v flipped (the current state sits at the root position r).
+ *   UNIFORM: r ~ U{0..M}, the populating process with a uniform root (App. "General
+ *            graph populating process"): self-thermalising, node weights
+ *            exp(-beta E_v).  arity = M is the M-ary star; the paper's SK trees are
+ *            arities 2, 3, 16 with 127, 121, 273 nodes (Fig. fig_sk).
+ *   LINE:    the line-graph addition process (App. "Line-graph addition process";
+ *            requires arity 1): M nodes added one by one at either end with
+ *            probability 1/2, so r ~ Binomial(M, 1/2) (bit j of the root stream's
+ *            words sends addition j left) and P_gen(T|c_v) carries C(M, v) / 2^M
+ *            (the reading of the garbled prefactor); node weights
+ *            exp(-beta E_v) C(M, v), applied as the log-prior
+ *            lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1). */
+typedef enum {
+    MC3_LAW_UNIFORM = 0,
+    MC3_LAW_LINE = 1
+} mc3_graph_law;
+
 typedef enum {
     MC3_SCORER_GEMM = 0,
     MC3_SCORER_DELTA = 1,
@@ -100,6 +123,8 @@ typedef struct {
     int32_t mean_steps;      /* capacity of the per-step chain-mean trace ring (>= 0) */
     double near_tie_tol;     /* selection margin below which a step is flagged; < 0 => default */
     int32_t scorer;          /* mc3_scorer */
+    int32_t arity;           /* graph tree arity; 0 or >= M: the M-ary star */
+    int32_t law;             /* mc3_graph_law */
 } mc3_config;
 
 /* One instance of a batch: its size, graph size, chains and flip-set range, with the
@@ -124,6 +149,8 @@ typedef struct {
     double near_tie_tol;     /* < 0 => default */
     const mc3_instance_desc* instances;  /* [n_instances], copied by mc3_batch_create */
     int32_t scorer;          /* mc3_scorer */
+    int32_t arity;           /* graph tree arity of every instance; 0 or >= M: the star */
+    int32_t law;             /* mc3_graph_law */
 } mc3_batch_config;
 
 /* Per-step, per-chain record (40 bytes). */

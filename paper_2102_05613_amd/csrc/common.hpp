@@ -40,9 +40,12 @@ struct Inst {
   int32_t N, Np, W, M;
   int32_t chains, kmin, kmax, B;
   int32_t Bp, NB, P, chain0;
+  int32_t arity;    // tree arity: the parent of node v >= 1 is (v-1)/arity (arity M: the star)
+  int32_t law;      // root law: 0 uniform over the M+1 nodes, 1 line-graph addition process
   double scale;
   uint64_t J64, Jpack, flips, flip_slot, base[2], partial, spins;
   uint64_t field;   // [chains][Np] FP64 local fields (field-update path only)
+  uint64_t prior;   // [M+1] FP64 log-prior of the nodes (line law), 0 = none
 };
 
 // Flip sets of the step held in ring slot `slot` (slots of flip_slot bytes each).

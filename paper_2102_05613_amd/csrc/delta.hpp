@@ -52,10 +52,43 @@ __device__ __forceinline__ double spin_of(const uint32_t* bits, int i) {
   return ((bits[i >> 5] >> (i & 31)) & 1u) ? -1.0 : 1.0;
 }
 
-// Path flip set D_v of node v (root r) into out[]; returns |D_v|.  Sites of F_v not in
-// F_r (in F_v's order), then sites of F_r not in F_v (in F_r's order).
-__device__ __forceinline__ int path_set(const uint16_t* sites, const uint8_t* ks, int r, int v, uint16_t* out) {
+// Whether node u (>= 1) is node x or one of its ancestors (breadth-first labels:
+// ancestors have smaller labels).
+__device__ __forceinline__ bool on_path_up(int u, int x, int arity) {
+  while (x > u) x = (x - 1) / arity;
+  return x == u;
+}
+
+// Toggle site t in the list out[0..n): remove it if present, append it otherwise.
+__device__ __forceinline__ void toggle_site(uint16_t* out, int& n, uint16_t t) {
+  for (int a = 0; a < n; ++a)
+    if (out[a] == t) {
+      out[a] = out[n - 1];
+      --n;
+      return;
+    }
+  out[n++] = t;
+}
+
+// Path flip set D_v of node v (root r) into out[]; returns |D_v|.
+// Star (arity >= M): sites of F_v not in F_r (in F_v's order), then sites of F_r not in
+// F_v (in F_r's order).  Other trees: the flip sets of the edges on the path from r up
+// to the common ancestor, then from v up to it, each site toggled into the list.  The
+// host keeps |D_v| <= 2 kDeltaMaxK.
+__device__ __forceinline__ int path_set(const uint16_t* sites, const uint8_t* ks, int r, int v, uint16_t* out,
+                                        int M, int arity) {
   int n = 0;
+  if (arity < M) {
+    for (int u = r; u >= 1; u = (u - 1) / arity) {
+      if (on_path_up(u, v, arity)) continue;
+      for (int a = 0; a < ks[u - 1]; ++a) toggle_site(out, n, sites[(size_t)(u - 1) * kDeltaMaxK + a]);
+    }
+    for (int u = v; u >= 1; u = (u - 1) / arity) {
+      if (on_path_up(u, r, arity)) continue;
+      for (int a = 0; a < ks[u - 1]; ++a) toggle_site(out, n, sites[(size_t)(u - 1) * kDeltaMaxK + a]);
+    }
+    return n;
+  }
   const uint16_t* fv = v >= 1 ? sites + (size_t)(v - 1) * kDeltaMaxK : nullptr;
   const uint16_t* fr = r >= 1 ? sites + (size_t)(r - 1) * kDeltaMaxK : nullptr;
   const int kv = v >= 1 ? ks[v - 1] : 0;
@@ -126,7 +159,7 @@ __global__ __launch_bounds__(256) void k_step_delta(
     const uint32_t step = step0 + (uint32_t)it;
     const double beta = total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)step / (double)(total - 1));
     // 1. root and flip sets
-    if (tid == 0) sh_r = root_of(key, gc, step, M, metropolis);
+    if (tid == 0) sh_r = root_of(key, gc, step, M, metropolis, in.law);
     for (int e1 = tid; e1 < M; e1 += 256) {
       const uint32_t e = (uint32_t)e1 + 1u;
       uint16_t* my = sites + (size_t)e1 * kDeltaMaxK;
@@ -149,7 +182,7 @@ __global__ __launch_bounds__(256) void k_step_delta(
     for (int v = tid; v <= M; v += 256) {
       if (v == r) continue;
       uint16_t* D = dbuf + (size_t)tid * 2 * kDeltaMaxK;
-      const int nd = path_set(sites, ks, r, v, D);
+      const int nd = path_set(sites, ks, r, v, D, M, in.arity);
       double lin = 0.0, pair = 0.0;
       for (int a = 0; a < nd; ++a) {
         const int i = D[a];
@@ -169,7 +202,8 @@ __global__ __launch_bounds__(256) void k_step_delta(
     // 3. the rule
     if (wave == 0) {
       const uint4 ub = stream_block(key, kTagSelect, gc, step, 0u, 0u);
-      const RuleOut o = apply_rule(En, Qn, M, r, -(scale * U), metropolis, beta, u53_of(ub.x, ub.y), lane);
+      const RuleOut o = apply_rule(En, Qn, M, r, -(scale * U), metropolis, beta, u53_of(ub.x, ub.y), lane,
+                                   in.prior ? ws_at<const double>(ws, in.prior) : nullptr);
       if (lane == 0) {
         sh_vstar = o.vstar;
         record_outcome(o, g, r, tol, step, trace_steps, total_chains, e_cur, e_bar_out, moves, near_ties,
@@ -179,7 +213,7 @@ __global__ __launch_bounds__(256) void k_step_delta(
           vv[0] = o.e_new;
           vv[1] = o.ebar;
         }
-        if (o.vstar != r) sh_nd = path_set(sites, ks, r, o.vstar, dstar);
+        if (o.vstar != r) sh_nd = path_set(sites, ks, r, o.vstar, dstar, M, in.arity);
       }
     }
     __syncthreads();

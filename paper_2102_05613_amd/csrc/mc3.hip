@@ -34,6 +34,8 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct InstH {
   mc3_instance_desc desc;
+  int arity = 1;                                       // resolved: parent of v is (v-1)/arity
+  size_t prior = 0;                                    // log-prior table (line law), 0 = none
   int Np, W, Wn, B, Bp, NB, P, chain0, col0;
   size_t J64, Jpack, flips, base[2], partial, spins;  // byte offsets into the workspace
   size_t flip_slot;                                    // bytes of one step's flip sets
@@ -50,7 +52,7 @@ struct Plan {
   bool delta = false;   // field-update scorer (else the matrix-core pair sum)
   size_t delta_lds = 0;
   int total_chains = 0, total_cols = 0, Wmax = 0, Wn_max = 0, Mmax = 0;
-  int prop_T = 256, prop_stride = 1;
+  int prop_T = 256, prop_stride = 1, prop_rows = 1;
   int ahead = 1;    // steps proposed per launch in mc3_step_n
   int nslots = 2;   // flip-set and root ring slots (ahead + 1)
   std::vector<mc3::Unit> units_global[kClasses], units_local;
@@ -79,12 +81,17 @@ const char* validate_batch(const mc3_batch_config* c) {
   if (c->rule != MC3_RULE_MCMCMC && c->rule != MC3_RULE_METROPOLIS) return "unknown rule";
   if (c->scorer != MC3_SCORER_GEMM && c->scorer != MC3_SCORER_DELTA && c->scorer != MC3_SCORER_AUTO)
     return "unknown scorer";
+  if (c->arity < 0) return "arity must be >= 0";
+  if (c->law != MC3_LAW_UNIFORM && c->law != MC3_LAW_LINE) return "unknown graph law";
   if (c->trace_steps < 0) return "trace_steps must be >= 0";
   if (c->mean_steps < 0) return "mean_steps must be >= 0";
   if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
   long long chains = 0, cols = 0;
   for (int i = 0; i < c->n_instances; ++i) {
     if (const char* e = validate_instance(c->instances[i], c->rule)) return e;
+    const int M = c->instances[i].M;
+    const int a = (c->arity == 0 || c->arity > M) ? M : c->arity;
+    if (c->law == MC3_LAW_LINE && a != 1) return "the line law needs arity 1";
     chains += c->instances[i].chains;
     cols += (long long)c->instances[i].chains * c->instances[i].M;
   }
@@ -94,12 +101,26 @@ const char* validate_batch(const mc3_batch_config* c) {
   return nullptr;
 }
 
+int resolved_arity(const mc3_batch_config& c, int M) { return (c.arity == 0 || c.arity > M) ? M : c.arity; }
+
+// Longest path between two nodes of the tree on M+1 nodes with the given arity, in
+// edges: M for a line, otherwise twice the depth of node M (the deepest label).
+int longest_path(int M, int arity) {
+  if (arity == 1) return M;
+  int depth = 0;
+  for (int v = M; v >= 1; v = (v - 1) / arity) ++depth;
+  return 2 * depth;
+}
+
 // Whether the field-update scorer can run this batch (its limits), and its LDS bytes.
-bool delta_fits(const mc3_batch_config& c, size_t* lds, int kmax_limit) {
+// path_limit bounds kmax times the longest path (the size of a path flip set).
+bool delta_fits(const mc3_batch_config& c, size_t* lds, int path_limit) {
   int Nmax = 0, Mmax = 0, Wmax = 0;
   for (int i = 0; i < c.n_instances; ++i) {
     const mc3_instance_desc& d = c.instances[i];
-    if (d.kmax > kmax_limit || d.M > mc3::kDeltaMaxM || d.N > mc3::kDeltaMaxN) return false;
+    if (d.kmax > mc3::kDeltaMaxK || d.M > mc3::kDeltaMaxM || d.N > mc3::kDeltaMaxN) return false;
+    const int path = longest_path(d.M, resolved_arity(c, d.M));
+    if ((long long)d.kmax * path > path_limit) return false;
     Nmax = std::max(Nmax, d.N);
     Mmax = std::max(Mmax, d.M);
     Wmax = std::max(Wmax, (d.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock / 32);
@@ -112,8 +133,8 @@ bool delta_fits(const mc3_batch_config& c, size_t* lds, int kmax_limit) {
 // outside its limits.
 int resolve_delta(const mc3_batch_config& c, size_t* lds) {
   if (c.scorer == MC3_SCORER_GEMM) return 0;
-  if (c.scorer == MC3_SCORER_DELTA) return delta_fits(c, lds, mc3::kDeltaMaxK) ? 1 : -1;
-  return delta_fits(c, lds, 8) ? 1 : 0;
+  if (c.scorer == MC3_SCORER_DELTA) return delta_fits(c, lds, 2 * mc3::kDeltaMaxK) ? 1 : -1;
+  return delta_fits(c, lds, 16) ? 1 : 0;
 }
 
 // Tile class of an instance's split scoring: 512-column tiles (8 waves share each A
@@ -143,6 +164,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
     h.Bp = (h.B + kColPad - 1) / kColPad * kColPad;
     h.NB = h.Np / mc3::kRowBlock;
     h.P = (h.NB + 1) / 2;
+    h.arity = resolved_arity(cfg, d.M);
     h.chain0 = pl.total_chains;
     h.col0 = pl.total_cols;
     pl.total_chains += d.chains;
@@ -157,12 +179,16 @@ Plan make_plan(const mc3_batch_config& cfg) {
   for (const InstH& h : pl.inst) slot_bytes += (size_t)h.W * h.Bp * 4;
   pl.ahead = (int)std::max<size_t>(1, std::min<size_t>(kMaxAhead, kFlipBudget / slot_bytes));
   pl.nslots = pl.ahead + 1;
-  // proposal blocks: one LDS bitset per thread, row stride W+1 where 64 threads fit
+  // proposal blocks: one LDS bitset per thread (two when paths are longer than one
+  // edge), row stride W+1 where 64 threads fit
+  pl.prop_rows = 1;
+  for (const InstH& h : pl.inst)
+    if (h.arity < h.desc.M) pl.prop_rows = 2;
   pl.prop_stride = pl.Wmax + 1;
-  int T = (int)(65536 / ((size_t)pl.prop_stride * 4));
+  int T = (int)(65536 / ((size_t)pl.prop_rows * pl.prop_stride * 4));
   if (T < 64) {
     pl.prop_stride = pl.Wmax;
-    T = (int)(65536 / ((size_t)pl.prop_stride * 4));
+    T = (int)(65536 / ((size_t)pl.prop_rows * pl.prop_stride * 4));
   }
   T = std::min(T, 256) / 64 * 64;
   pl.prop_T = std::max(T, 64);
@@ -246,6 +272,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
     h.partial = take((size_t)h.P * h.Bp * 8);
     h.spins = take((size_t)h.desc.chains * h.W * 4);
     if (pl.delta) h.field = take((size_t)h.desc.chains * h.Np * 8);
+    if (cfg.law == MC3_LAW_LINE) h.prior = take((size_t)(h.desc.M + 1) * 8);
     candT = std::max(candT, (size_t)h.W * h.Bp * 4);
   }
   pl.candT = take(candT);
@@ -271,6 +298,8 @@ mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
   b.near_tie_tol = c->near_tie_tol;
   b.instances = one;
   b.scorer = c->scorer;
+  b.arity = c->arity;
+  b.law = c->law;
   return b;
 }
 
@@ -370,6 +399,8 @@ mc3_status upload_insts(mc3_ctx* c) {
     d.NB = h.NB;
     d.P = h.P;
     d.chain0 = h.chain0;
+    d.arity = h.arity;
+    d.law = c->cfg.law;
     d.scale = h.scale;
     d.J64 = h.J64;
     d.Jpack = h.Jpack;
@@ -380,6 +411,7 @@ mc3_status upload_insts(mc3_ctx* c) {
     d.partial = h.partial;
     d.spins = h.spins;
     d.field = h.field;
+    d.prior = h.prior;
   }
   MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<char>(pl.insts), t.data(), t.size() * sizeof(mc3::Inst),
                                    hipMemcpyHostToDevice, c->stream), "upload instance table"));
@@ -440,11 +472,11 @@ mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, 
 // (at most nslots - 1 of them); with write_base, also the base words of step0.
 mc3_status launch_propose(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base, int b0, int nb) {
   const Plan& pl = c->pl;
-  const size_t lds = (size_t)pl.prop_T * pl.prop_stride * 4;
+  const size_t lds = (size_t)pl.prop_rows * pl.prop_T * pl.prop_stride * 4;
   hipLaunchKernelGGL(mc3::k_propose, dim3(nb, nsteps), dim3(pl.prop_T), lds, c->stream, c->ws, c->insts(),
                      c->at<const mc3::PBlock>(pl.pblocks_off) + b0, c->at<int32_t>(pl.roots), pl.total_chains,
-                     (uint32_t)pl.nslots, write_base ? 1 : 0, pl.prop_stride, c->metropolis() ? 1 : 0, c->key(),
-                     c->cfg.chain_base, step0);
+                     (uint32_t)pl.nslots, write_base ? 1 : 0, pl.prop_stride, pl.prop_rows, c->metropolis() ? 1 : 0,
+                     c->key(), c->cfg.chain_base, step0);
   return check_launch(c, "propose kernel");
 }
 
@@ -646,6 +678,16 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
     e = up(P.units_global_off[k], P.units_global[k].data(), P.units_global[k].size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.units_local_off, P.units_local.data(), P.units_local.size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.pblocks_off, P.pblocks.data(), P.pblocks.size() * sizeof(mc3::PBlock));
+  // the line law's log-prior log C(M, v) = lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1)
+  std::vector<std::vector<double>> priors;
+  for (const InstH& h : P.inst) {
+    if (!h.prior || e != hipSuccess) continue;
+    const int M = h.desc.M;
+    priors.emplace_back(M + 1);
+    for (int v = 0; v <= M; ++v)
+      priors.back()[v] = std::lgamma((double)M + 1.0) - std::lgamma((double)v + 1.0) - std::lgamma((double)(M - v) + 1.0);
+    e = up(h.prior, priors.back().data(), priors.back().size() * 8);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess || upload_insts(c) != MC3_OK) {
     mc3_destroy(c);

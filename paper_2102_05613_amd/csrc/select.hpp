@@ -13,15 +13,17 @@ namespace mc3 {
 // node order, threshold t = floor(u53 W / 2^53), v* = min{v : Q_v > t}; the margin is
 // the draw's distance to the edges of its interval as a fraction of W, and the
 // node-weighted energy sum w E / sum w.  Metropolis (M = 1): accept iff dE <= 0 or
-// u53 / 2^53 < exp(-(beta dE)).  Without a log-prior the largest exponent is -0, so
-// exp(l - lmax) = exp(l) bit for bit and that shift is not formed.
+// u53 / 2^53 < exp(-(beta dE)).  With a log-prior lambda (the line process) the
+// exponents are l_v = -(beta (E_v - Emin)) + lambda_v and the weights
+// exp(l_v - max l); without one the largest exponent is -0, so exp(l - lmax) =
+// exp(l) bit for bit and that shift is not formed.
 struct RuleOut {
   int vstar;
   double e_new, ebar, margin;
 };
 
 __device__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, int r, double ecur, int metropolis,
-                              double beta, uint64_t u53, int lane) {
+                              double beta, uint64_t u53, int lane, const double* __restrict__ prior) {
   RuleOut o;
   const int nodes = M + 1;
   if (metropolis) {
@@ -45,12 +47,21 @@ __device__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, i
   double emin = __longlong_as_double(0x7FF0000000000000ll);
   for (int v = lane; v < nodes; v += 64) emin = En[v] < emin ? En[v] : emin;
   emin = wave_min(emin);
+  double lmax = 0.0;
+  if (prior) {
+    lmax = __longlong_as_double(0xFFF0000000000000ll);
+    for (int v = lane; v < nodes; v += 64) {
+      const double l = -(beta * (En[v] - emin)) + prior[v];
+      lmax = l > lmax ? l : lmax;
+    }
+    lmax = wave_max(lmax);
+  }
   // fixed-point weights, their total, and the weighted energy
   unsigned long long wq = 0ull;
   double num = 0.0, den = 0.0;
   for (int v = lane; v < nodes; v += 64) {
     const double E = En[v];
-    const double w = exp_weight(-(beta * (E - emin)));
+    const double w = prior ? exp_weight((-(beta * (E - emin)) + prior[v]) - lmax) : exp_weight(-(beta * (E - emin)));
     const unsigned long long q = (unsigned long long)(w * 0x1.0p52);
     Qn[v] = q;
     wq += q;
@@ -176,7 +187,8 @@ __global__ __launch_bounds__(256) void k_select(
   // 2. the rule (wave 0)
   if (wave == 0) {
     const uint4 ub = stream_block(key, kTagSelect, chain_base + (uint32_t)g, step, 0u, 0u);
-    const RuleOut o = apply_rule(En, Qn, M, r, ecur, metropolis, beta, u53_of(ub.x, ub.y), lane);
+    const RuleOut o = apply_rule(En, Qn, M, r, ecur, metropolis, beta, u53_of(ub.x, ub.y), lane,
+                                 in.prior ? ws_at<const double>(ws, in.prior) : nullptr);
     if (lane == 0) {
       sh_vstar = o.vstar;
       record_outcome(o, g, r, tol, step, trace_steps, total_chains, e_cur, e_bar_out, moves, near_ties, min_margin,

@@ -49,6 +49,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mc3_instance_desc), sizeof(mc3_batch_config),
          offsetof(mc3_batch_config, chain_base), offsetof(mc3_batch_config, seed),
          offsetof(mc3_batch_config, instances), offsetof(mc3_batch_config, scorer), offsetof(mc3_config, scorer));
+  printf("%zu %zu %zu %zu\n", offsetof(mc3_config, arity), offsetof(mc3_config, law),
+         offsetof(mc3_batch_config, arity), offsetof(mc3_batch_config, law));
   return 0;
 }
 '''
@@ -64,7 +66,8 @@ int main(void) {
                     ctypes.sizeof(native.InstanceDesc), ctypes.sizeof(native.BatchConfig),
                     native.BatchConfig.chain_base.offset, native.BatchConfig.seed.offset,
                     native.BatchConfig.instances.offset, native.BatchConfig.scorer.offset,
-                    native.Config.scorer.offset]
+                    native.Config.scorer.offset, native.Config.arity.offset, native.Config.law.offset,
+                    native.BatchConfig.arity.offset, native.BatchConfig.law.offset]
 
 
 def test_version(lib):
@@ -185,3 +188,23 @@ def test_unknown_scorer_rejected(lib):
     cfg.scorer = 7
     n = ctypes.c_size_t()
     assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == native.MC3_E_ARG
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(arity=2), native.MC3_OK), (dict(arity=1, law="line"), native.MC3_OK),
+    (dict(arity=2, law="line"), native.MC3_E_ARG), (dict(arity=-1), native.MC3_E_ARG),
+    (dict(arity=0, law="line"), native.MC3_E_ARG),
+    # field update: a binary tree on 127 nodes has paths of 12 edges
+    (dict(M=126, kmin=1, kmax=2, arity=2, scorer="delta"), native.MC3_OK),
+    (dict(M=126, kmin=1, kmax=3, arity=2, scorer="delta"), native.MC3_E_UNSUPPORTED),
+    (dict(M=127, kmin=1, kmax=1, arity=1, law="line", scorer="delta"), native.MC3_E_UNSUPPORTED),
+    (dict(M=127, kmin=1, kmax=1, arity=1, law="line", scorer="auto"), native.MC3_OK),
+    (dict(M=31, kmin=1, kmax=1, arity=1, law="line", scorer="delta"), native.MC3_OK)])
+def test_graph_shape_validation(lib, kw, expect):
+    base = dict(N=64, M=6, chains=2, kmin=1, kmax=1)
+    for k in ("M", "kmin", "kmax"):
+        if k in kw:
+            base[k] = kw.pop(k)
+    cfg = native.make_config(precision="fp64", **base, **kw)
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == expect

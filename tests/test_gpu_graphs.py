@@ -1,0 +1,84 @@
+"""The paper's graph shapes on the GPU: breadth-first a-ary trees populated from a
+uniform root (binary, ternary, 16-ary), and the line-graph addition process with its
+C(M, v) prior, against the oracle.
+
+Bars: candidate bitsets and roots bit-exact; +-1 couplings give the oracle's
+trajectories bit for bit on every scorer; Gaussian couplings at N=1024 give the
+oracle's selections except at flagged near ties."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import announce, compare_trajectory, gpu_spins, oracle_candidates
+from paper_2102_05613_amd import inputs, native
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (M, arity, law, kmin, kmax)
+    (14, 2, "uniform", 1, 1), (12, 3, "uniform", 1, 2), (7, 1, "line", 1, 1), (20, 16, "uniform", 1, 1),
+    (9, 2, "uniform", 2, 5)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    native.lib()
+
+
+def _ctx(N, M, chains, kmin, kmax, J, scale, arity, law, prec="fp64", scorer="gemm", steps=0, seed=0):
+    cfg = native.make_config(N, M, chains, kmin, kmax, precision=prec, trace_steps=steps, seed=seed, scorer=scorer,
+                             arity=arity, law=law)
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    return ctx
+
+
+@pytest.mark.parametrize("M,arity,law,kmin,kmax", SHAPES)
+def test_tree_candidates_bit_exact(M, arity, law, kmin, kmax):
+    N, chains = 70, 5
+    announce(f"tree propose M={M} a={arity} {law}")
+    J, scale = inputs.couplings_pm1(N, 5)
+    ctx = _ctx(N, M, chains, kmin, kmax, J, scale, arity, law, seed=31)
+    s = gpu_spins(ctx)
+    for step in (0, 9, 2 ** 31 + 3):
+        ctx.propose(step)
+        bits, roots = ctx.read_candidates()
+        cand = native.bits_to_spins(bits, N)
+        for c in range(chains):
+            r, cols = oracle_candidates(31, c, step, N, M, kmin, kmax, s[c], arity=arity, law=law)
+            assert roots[c] == r
+            assert np.array_equal(cand[c], cols)
+
+
+@pytest.mark.parametrize("M,arity,law,kmin,kmax", SHAPES)
+@pytest.mark.parametrize("prec,scorer", [("fp64", "gemm"), ("split_bf16", "gemm"), ("fp64", "delta")])
+def test_tree_pm1_trajectory_bit_exact(M, arity, law, kmin, kmax, prec, scorer):
+    N, chains, steps = 48, 3, 1500
+    announce(f"tree pm1 trajectory M={M} a={arity} {law} {prec} {scorer}")
+    J, scale = inputs.couplings_pm1(N, 0x5EED0001)
+    ctx = _ctx(N, M, chains, kmin, kmax, J, scale, arity, law, prec=prec, scorer=scorer, steps=steps, seed=6)
+    ctx.step_n(0, steps, 1.0, 1.0, 1)
+    rec = ctx.read_records(0, steps)
+    compare_trajectory(rec, J, scale, N, M, chains, kmin, kmax, 6, np.ones(steps), "mcmcmc", 0.0, exact=True,
+                       arity=arity, law=law)
+    assert ctx.measure()[2]["moves"] > 0
+
+
+@pytest.mark.parametrize("M,arity,law", [(126, 2, "uniform"), (120, 3, "uniform"), (272, 16, "uniform"),
+                                         (127, 1, "line")])
+def test_paper_shapes_gauss_guided(M, arity, law):
+    """The paper's SK graphs (binary tree of depth 7, ternary of depth 5, 16-ary of
+    depth 3, line of 2^7 nodes) at L = 1024, single-spin-flip edges, T = 1, split
+    BF16 scoring: 15 steps of 4 chains match the oracle (guided at flagged ties)."""
+    N, chains, steps = 1024, 4, 15
+    announce(f"paper shape M={M} a={arity} {law}")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0003)
+    ctx = _ctx(N, M, chains, 1, 1, J, scale, arity, law, prec="split_bf16", steps=steps, seed=8)
+    ctx.step_n(0, steps, 1.0, 1.0, 1)
+    rec = ctx.read_records(0, steps)
+    _, nforced = compare_trajectory(rec, J, scale, N, M, chains, 1, 1, 8, np.ones(steps), "mcmcmc", 1e-4,
+                                    arity=arity, law=law)
+    assert nforced <= 3
