@@ -67,10 +67,10 @@ def _traffic_from_profile():
     return rec, "measured"
 
 
-def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0, scorer="gemm"):
+def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0, scorer="gemm", arity=0, law="uniform"):
     from paper_2102_05613_amd import native
     cfg = native.make_config(w.N, M, w.chains, kmin, kmax, precision=precision, rule=rule, seed=w.seed,
-                             mean_steps=mean_steps, scorer=scorer)
+                             mean_steps=mean_steps, scorer=scorer, arity=arity, law=law)
     ctx = native.Context(cfg)
     ctx.init_couplings(J, scale)
     ctx.init_chains()
@@ -120,20 +120,23 @@ def _t_within(e, ref, window, tol=0.01):
     return t if t <= T - window else None
 
 
-def _thermalize_study(w, J, scale, T, beta, k_edge, label):
+def _thermalize_study(w, J, scale, T, beta, k_edge, label, specs=None):
     """MCMCMC (split-BF16 and FP64 pair sums, and the FP64 field-update scorer where
     the flip sets are small enough; M = w.M, flip sets of k_edge = (kmin, kmax)) and
     single-flip Metropolis (field-update scorer) on the same instance, chains and
-    initial states."""
+    initial states.  specs: (name, precision, rule, M, kmin, kmax, scorer, arity, law)
+    to run instead."""
     import torch
     runs = {}
-    specs = [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm"),
-             ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm")]
-    if k_edge[1] <= 16:
-        specs.append(("mcmcmc_fp64_field_update", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "delta"))
-    specs.append(("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta"))
-    for name, prec, rule, M, kmin, kmax, scorer in specs:
-        ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T, scorer=scorer)
+    if specs is None:
+        specs = [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm", 0, "uniform"),
+                 ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm", 0, "uniform")]
+        if k_edge[1] <= 16:
+            specs.append(("mcmcmc_fp64_field_update", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "delta", 0,
+                          "uniform"))
+        specs.append(("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform"))
+    for name, prec, rule, M, kmin, kmax, scorer, arity, law in specs:
+        ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T, scorer=scorer, arity=arity, law=law)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.step_n(0, T, beta, beta, 1)
@@ -141,7 +144,9 @@ def _thermalize_study(w, J, scale, T, beta, k_edge, label):
         wall = time.perf_counter() - t0
         means = ctx.read_means(0, T) / w.N
         ctx.close()
-        runs[name] = {"wall_s": wall, "e_bar": means[:, 1], "M": M, "scorer": scorer}
+        runs[name] = {"wall_s": wall, "e_bar": means[:, 1], "M": M, "scorer": scorer, "precision": prec,
+                      "graph": "star" if arity == 0 else (f"line, {M + 1} nodes" if law == "line"
+                                                          else f"{arity}-ary tree, {M + 1} nodes")}
     tail = {name: float(np.mean(r["e_bar"][-T // 4:])) for name, r in runs.items()}
     ref = min(tail.values())
     window = max(10, T // 100)
@@ -154,7 +159,7 @@ def _thermalize_study(w, J, scale, T, beta, k_edge, label):
                      "t_seconds": None if t is None else t * per_step_s,
                      "t_candidates": None if t is None else t * w.chains * r["M"],
                      "tail_energy_per_spin": tail[name], "ms_per_step": per_step_s * 1e3,
-                     "scorer": r["scorer"]}
+                     "scorer": r["scorer"], "precision": r["precision"], "graph": r["graph"]}
     return out
 
 
@@ -165,6 +170,16 @@ def _thermalize(w, J, scale, T):
                       "mean (last 25% of steps) among the runs of the study",
         "paper_setting": _thermalize_study(w, J, scale, T, 1.0, (1, 1),
                                            "single-spin-flip edges at T = Tc = 1 (the paper's SK experiment)"),
+        "paper_graph_shapes": _thermalize_study(
+            w, J, scale, T, 1.0, (1, 1),
+            "the paper's SK comparison (Fig. fig_sk) on this instance: L = 1024, T = 1, single-spin-flip edges; "
+            "line-graph addition process of 2^7 nodes, binary tree of depth 7, ternary of depth 5, 16-ary of "
+            "depth 3 (uniform root), against single-update Metropolis",
+            specs=[("line_2e7", "split_bf16", "mcmcmc", 127, 1, 1, "gemm", 1, "line"),
+                   ("binary_depth7", "fp64", "mcmcmc", 126, 1, 1, "delta", 2, "uniform"),
+                   ("ternary_depth5", "fp64", "mcmcmc", 120, 1, 1, "delta", 3, "uniform"),
+                   ("16ary_depth3", "fp64", "mcmcmc", 272, 1, 1, "delta", 16, "uniform"),
+                   ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform")]),
         "configured_workload": _thermalize_study(w, J, scale, T, w.beta0, (w.kmin, w.kmax),
                                                  "the benchmark workload's own flip sets and beta"),
     }
