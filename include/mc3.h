@@ -296,6 +296,21 @@ mc3_status mc3_timing_enable(mc3_ctx* ctx, int32_t on);
 /* Synchronise; total milliseconds of the timed scoring launches and their number. */
 mc3_status mc3_timing_read(mc3_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Checkpoint of the chains: spins, carried energies (field-update scorer: also the pair
+ * sums and fields), counters and steps done, as a self-describing host buffer (header,
+ * instance shapes, arrays; the record and means rings are not included).  With
+ * buf == NULL, *bytes receives the size needed; otherwise *bytes is the buffer's size
+ * on entry and the size written on return.  Synchronises.  For resuming a run after
+ * the process that made it ended. */
+mc3_status mc3_checkpoint_save(mc3_ctx* ctx, void* buf, size_t* bytes);
+
+/* Restore a checkpoint into a context of the same batch shape (instances, N, M,
+ * chains) and scorer, after mc3_init_couplings of every instance, in place of
+ * mc3_init_chains (the rings are cleared).  The steps that follow equal, bit for
+ * bit, those the saving context would have run with the same step numbers.
+ * MC3_E_ARG for a buffer of another shape or not a checkpoint. */
+mc3_status mc3_checkpoint_load(mc3_ctx* ctx, const void* buf, size_t bytes);
+
 /* Wait for the stream; report any device error. */
 mc3_status mc3_sync(mc3_ctx* ctx);
 

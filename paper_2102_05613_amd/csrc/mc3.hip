@@ -729,6 +729,46 @@ mc3_status init_couplings_impl(mc3_ctx* c, int32_t instance, const double* J, in
   return upload_insts(c);
 }
 
+// Clear what a fresh chain state needs cleared: flip-set padding columns and the zero
+// base row (must read as zero), counters, margins, the record and means rings.
+mc3_status reset_buffers(mc3_ctx* c) {
+  const Plan& pl = c->pl;
+  const size_t C = (size_t)pl.total_chains;
+  for (const InstH& h : pl.inst) {
+    MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.flips), 0, (size_t)pl.nslots * h.flip_slot, c->stream), "clear"));
+    for (int q = 0; q < 2; ++q)
+      MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.base[q]), 0, (size_t)(h.desc.chains + 1) * h.W * 4, c->stream),
+                     "clear"));
+  }
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.moves), 0, C * 8, c->stream), "clear"));
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.near), 0, C * 8, c->stream), "clear"));
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift), 0, C * 8, c->stream), "clear"));
+  {
+    std::vector<double> big(C, HUGE_VAL);
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.minm), big.data(), big.size() * 8, hipMemcpyHostToDevice,
+                                     c->stream), "init margins"));
+    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
+  }
+  if (c->cfg.trace_steps > 0) {
+    std::vector<mc3::Record> ring((size_t)c->cfg.trace_steps * C);
+    for (auto& r : ring) {
+      std::memset(&r, 0, sizeof r);
+      r.step = 0xFFFFFFFFu;
+    }
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<mc3::Record>(pl.ring), ring.data(), ring.size() * sizeof(mc3::Record),
+                                     hipMemcpyHostToDevice, c->stream), "clear ring"));
+    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
+  }
+  if (c->cfg.mean_steps > 0) {
+    std::vector<double> tr((size_t)c->cfg.mean_steps * 3, -1.0);
+    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.means), tr.data(), tr.size() * 8, hipMemcpyHostToDevice,
+                                     c->stream), "clear means"));
+    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
+  }
+  return MC3_OK;
+}
+
+
 mc3_status step_args(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "step_n before init_chains");
@@ -815,38 +855,7 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
     MC3_TRY(check_launch(c, "init spins kernel"));
   }
   MC3_TRY(launch_energy(c, c->at<double>(pl.e_cur)));
-  // flip-set padding columns and the zero base row must read as zero
-  for (const InstH& h : pl.inst) {
-    MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.flips), 0, (size_t)pl.nslots * h.flip_slot, c->stream), "clear"));
-    for (int q = 0; q < 2; ++q)
-      MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(h.base[q]), 0, (size_t)(h.desc.chains + 1) * h.W * 4, c->stream),
-                     "clear"));
-  }
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.moves), 0, C * 8, c->stream), "clear"));
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.near), 0, C * 8, c->stream), "clear"));
-  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift), 0, C * 8, c->stream), "clear"));
-  {
-    std::vector<double> big(C, HUGE_VAL);
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.minm), big.data(), big.size() * 8, hipMemcpyHostToDevice,
-                                     c->stream), "init margins"));
-    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
-  }
-  if (c->cfg.trace_steps > 0) {
-    std::vector<mc3::Record> ring((size_t)c->cfg.trace_steps * C);
-    for (auto& r : ring) {
-      std::memset(&r, 0, sizeof r);
-      r.step = 0xFFFFFFFFu;
-    }
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<mc3::Record>(pl.ring), ring.data(), ring.size() * sizeof(mc3::Record),
-                                     hipMemcpyHostToDevice, c->stream), "clear ring"));
-    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
-  }
-  if (c->cfg.mean_steps > 0) {
-    std::vector<double> tr((size_t)c->cfg.mean_steps * 3, -1.0);
-    MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.means), tr.data(), tr.size() * 8, hipMemcpyHostToDevice,
-                                     c->stream), "clear means"));
-    MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "init_chains sync"));
-  }
+  MC3_TRY(reset_buffers(c));
   c->have_chains = true;
   c->have_proposal = c->have_scores = false;
   c->steps_done = 0;
@@ -1050,6 +1059,119 @@ mc3_status mc3_read_means(mc3_ctx* c, uint32_t first, int32_t n, double* out) {
     out[2 * (size_t)i] = buf[3 * slot + 1];
     out[2 * (size_t)i + 1] = buf[3 * slot + 2];
   }
+  return MC3_OK;
+}
+
+// Checkpoint layout: header, one shape record per instance, then the arrays in a
+// fixed order (see checkpoint_items).
+struct CkHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t n_instances, total_chains, delta;
+  int64_t steps_done;
+  uint64_t payload;
+};
+struct CkShape {
+  int32_t N, M, chains, W;
+};
+
+}  // extern "C"
+
+namespace {
+
+// (device pointer, bytes) of every array a checkpoint carries, in order.
+std::vector<std::pair<char*, size_t>> checkpoint_items(mc3_ctx* c) {
+  const Plan& pl = c->pl;
+  const size_t C = (size_t)pl.total_chains;
+  std::vector<std::pair<char*, size_t>> it;
+  it.emplace_back(c->at<char>(pl.e_cur), C * 8);
+  if (pl.delta) it.emplace_back(c->at<char>(pl.u_cur), C * 8);
+  it.emplace_back(c->at<char>(pl.moves), C * 8);
+  it.emplace_back(c->at<char>(pl.near), C * 8);
+  it.emplace_back(c->at<char>(pl.minm), C * 8);
+  it.emplace_back(c->at<char>(pl.drift), C * 8);
+  for (const InstH& h : pl.inst) {
+    it.emplace_back(c->at<char>(h.spins), (size_t)h.desc.chains * h.W * 4);
+    if (pl.delta) it.emplace_back(c->at<char>(h.field), (size_t)h.desc.chains * h.Np * 8);
+  }
+  return it;
+}
+
+size_t checkpoint_bytes(mc3_ctx* c) {
+  size_t n = sizeof(CkHeader) + c->pl.inst.size() * sizeof(CkShape);
+  for (const auto& x : checkpoint_items(c)) n += x.second;
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+mc3_status mc3_checkpoint_save(mc3_ctx* c, void* buf, size_t* bytes) {
+  MC3_TRY(usable(c));
+  if (!bytes) return fail(c, MC3_E_ARG, "bytes is NULL");
+  const size_t need = checkpoint_bytes(c);
+  if (!buf) {
+    *bytes = need;
+    return MC3_OK;
+  }
+  if (*bytes < need) return fail(c, MC3_E_ARG, "checkpoint needs %zu bytes", need);
+  if (!c->have_chains) return fail(c, MC3_E_STATE, "checkpoint_save before init_chains");
+  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "checkpoint sync"));
+  char* p = (char*)buf;
+  CkHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  std::memcpy(hd.magic, "MC3CKPT1", 8);
+  hd.version = 1;
+  hd.n_instances = (int32_t)c->pl.inst.size();
+  hd.total_chains = c->pl.total_chains;
+  hd.delta = c->pl.delta ? 1 : 0;
+  hd.steps_done = c->steps_done;
+  hd.payload = need - sizeof hd;
+  std::memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  for (const InstH& h : c->pl.inst) {
+    const CkShape sh{h.desc.N, h.desc.M, h.desc.chains, h.W};
+    std::memcpy(p, &sh, sizeof sh);
+    p += sizeof sh;
+  }
+  for (const auto& x : checkpoint_items(c)) {
+    MC3_TRY(hip_ok(c, hipMemcpy(p, x.first, x.second, hipMemcpyDeviceToHost), "checkpoint read"));
+    p += x.second;
+  }
+  *bytes = need;
+  return MC3_OK;
+}
+
+mc3_status mc3_checkpoint_load(mc3_ctx* c, const void* buf, size_t bytes) {
+  MC3_TRY(usable(c));
+  if (!buf) return fail(c, MC3_E_ARG, "buf is NULL");
+  if (!c->all_J()) return fail(c, MC3_E_STATE, "checkpoint_load before init_couplings of every instance");
+  const size_t need = checkpoint_bytes(c);
+  if (bytes < need) return fail(c, MC3_E_ARG, "checkpoint is %zu bytes, this context needs %zu", bytes, need);
+  const char* p = (const char*)buf;
+  CkHeader hd;
+  std::memcpy(&hd, p, sizeof hd);
+  p += sizeof hd;
+  if (std::memcmp(hd.magic, "MC3CKPT1", 8) != 0 || hd.version != 1) return fail(c, MC3_E_ARG, "not a checkpoint");
+  if (hd.n_instances != (int32_t)c->pl.inst.size() || hd.total_chains != c->pl.total_chains ||
+      hd.delta != (c->pl.delta ? 1 : 0) || hd.payload != need - sizeof hd)
+    return fail(c, MC3_E_ARG, "checkpoint of a different batch shape or scorer");
+  for (const InstH& h : c->pl.inst) {
+    CkShape sh;
+    std::memcpy(&sh, p, sizeof sh);
+    p += sizeof sh;
+    if (sh.N != h.desc.N || sh.M != h.desc.M || sh.chains != h.desc.chains || sh.W != h.W)
+      return fail(c, MC3_E_ARG, "checkpoint of a different instance shape");
+  }
+  MC3_TRY(reset_buffers(c));
+  for (const auto& x : checkpoint_items(c)) {
+    MC3_TRY(hip_ok(c, hipMemcpy(x.first, p, x.second, hipMemcpyHostToDevice), "checkpoint write"));
+    p += x.second;
+  }
+  c->have_chains = true;
+  c->have_proposal = c->have_scores = false;
+  c->steps_done = hd.steps_done;
   return MC3_OK;
 }
 

@@ -34,7 +34,8 @@ EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_coupling
            "mc3_propose", "mc3_score_candidates", "mc3_select", "mc3_step_n", "mc3_recompute", "mc3_measure",
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
            "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
-           "mc3_init_couplings_instance", "mc3_step_n_per_instance"]
+           "mc3_init_couplings_instance", "mc3_step_n_per_instance", "mc3_checkpoint_save",
+           "mc3_checkpoint_load"]
 
 
 class Config(ctypes.Structure):
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.mc3_batch_create.argtypes = [P(BatchConfig), vp, c.c_size_t, vp, P(vp)]
     L.mc3_init_couplings_instance.argtypes = [vp, c.c_int32, P(c.c_double), c.c_int64, c.c_double]
     L.mc3_step_n_per_instance.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
+    L.mc3_checkpoint_save.argtypes = [vp, vp, P(c.c_size_t)]
+    L.mc3_checkpoint_load.argtypes = [vp, vp, c.c_size_t]
     L.mc3_last_error.argtypes = [vp]
     L.mc3_last_error.restype = c.c_char_p
     L.mc3_version.restype = c.c_char_p
@@ -226,6 +229,17 @@ class Context:
     def step_n_per_instance(self, step0: int, n: int, beta0: float, beta1: float, total: int):
         self._check(lib().mc3_step_n_per_instance(self.h, step0, n, float(beta0), float(beta1), total),
                     "mc3_step_n_per_instance")
+
+    def checkpoint_save(self) -> bytes:
+        n = ctypes.c_size_t()
+        self._check(lib().mc3_checkpoint_save(self.h, None, ctypes.byref(n)), "mc3_checkpoint_save")
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(lib().mc3_checkpoint_save(self.h, buf, ctypes.byref(n)), "mc3_checkpoint_save")
+        return buf.raw[:n.value]
+
+    def checkpoint_load(self, data: bytes):
+        buf = ctypes.create_string_buffer(data, len(data))
+        self._check(lib().mc3_checkpoint_load(self.h, buf, len(data)), "mc3_checkpoint_load")
 
     def recompute(self):
         self._check(lib().mc3_recompute(self.h), "mc3_recompute")
