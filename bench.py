@@ -267,7 +267,9 @@ def _batched_workload(args):
             "N_range": [int(Ns.min()), int(Ns.max())], "M_range": [int(Ms.min()), int(Ms.max())],
             "candidates_per_step": cand, "steps": args.batch_steps,
             "batched": {"ms_per_step": ms_step, "candidates_per_s": cand / (ms_step / 1e3),
-                        "score_kernel_ms": score_s * 1e3, "launches_per_step": 3},
+                        "score_kernel_ms": score_s * 1e3,
+                        "launches_per_step": "one scoring launch per tile width present, one selection, one "
+                                             "proposal per 16 steps"},
             "per_instance_launches": {"ms_per_step": per_ms, "candidates_per_s": cand / (per_ms / 1e3),
                                       "steps": n_per, "launches_per_step": 3 * len(descs)},
             "speedup_batched": per_ms / ms_step,
@@ -303,6 +305,65 @@ def _large_workload(args):
     return out
 
 
+def _precision_report(w, J, scale, step=3):
+    """Relative error of the split-BF16 energies of every candidate of one step against
+    the FP64 scorer's energies of the same candidates (same seed and step; the FP64
+    path itself is pinned to the oracle by the parity tests)."""
+    import torch
+    from paper_2102_05613_amd import native
+    E = {}
+    for prec in ("split_bf16", "fp64"):
+        cfg = native.make_config(w.N, w.M, w.chains, w.kmin, w.kmax, precision=prec, seed=w.seed)
+        ctx = native.Context(cfg)
+        ctx.init_couplings(J, scale)
+        ctx.init_chains()
+        ctx.propose(step)
+        out = torch.zeros(w.chains * w.M, dtype=torch.float64, device="cuda")
+        ctx.score_candidates(out)
+        E[prec] = out.cpu().numpy()
+        ctx.close()
+    rel = np.abs(E["split_bf16"] - E["fp64"]) / np.maximum(np.abs(E["fp64"]), 1e-300)
+    d = np.abs(E["split_bf16"] - E["fp64"])
+    return {"candidates": int(rel.size), "rel_max": float(rel.max()), "rel_p9999": float(np.quantile(rel, 0.9999)),
+            "rel_mean": float(rel.mean()), "abs_max": float(d.max()), "abs_p9999": float(np.quantile(d, 0.9999)),
+            "abs_mean": float(d.mean()), "energy_abs_mean": float(np.abs(E["fp64"]).mean()),
+            "reference": "FP64 matrix-core scoring of the same candidates",
+            "note": "relative errors peak at candidates with energies near zero; the absolute error is the "
+                    "FP32 accumulation's"}
+
+
+def _anneal_thermalize(T):
+    """Steps to thermalize under the anneal workload (N = 256, 64 chains, M = 16, flip
+    sets 1..4, beta 0.1 -> 3 over T steps, FP64 field-update scorer) against
+    single-flip Metropolis under the same schedule."""
+    import torch
+    from paper_2102_05613_amd import inputs
+    w = inputs.workload("sk_n256_anneal_m16")
+    J, scale = w.couplings_matrix()
+    runs = {}
+    for name, rule, M, kmin, kmax in (("mcmcmc_m16", "mcmcmc", w.M, w.kmin, w.kmax),
+                                      ("metropolis_m1_single_flip", "metropolis", 1, 1, 1)):
+        ctx = _context(w, "fp64", rule, M, kmin, kmax, J, scale, mean_steps=T, scorer="delta")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step_n(0, T, w.beta0, w.beta1, T)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs[name] = {"wall_s": wall, "e_bar": ctx.read_means(0, T)[:, 1] / w.N, "M": M}
+        ctx.close()
+    tail = {k: float(np.mean(r["e_bar"][-T // 100:])) for k, r in runs.items()}
+    ref = min(tail.values())
+    window = max(10, T // 100)
+    out = {"workload": w.name, "beta": [w.beta0, w.beta1], "T": T, "window": window,
+           "reference_energy_per_spin": ref,
+           "note": "reference = lowest mean over the last 1% of steps (the coldest part of the anneal)"}
+    for k, r in runs.items():
+        t = _t_within(r["e_bar"], ref, window)
+        out[k] = {"t_steps": t if t is not None else f"> {T}", "final_energy_per_spin": tail[k],
+                  "t_seconds": None if t is None else t * r["wall_s"] / T, "ms_per_step": r["wall_s"] / T * 1e3}
+    return out
+
+
 def _cpu_baseline(w, J, scale, sample_chains):
     import oracle
     t0 = time.perf_counter()
@@ -322,6 +383,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--thermalize-steps", type=int, default=20000)
     ap.add_argument("--cpu-chains", type=int, default=160)
+    ap.add_argument("--anneal-steps", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--small-steps", type=int, default=10000,
                     help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
@@ -394,8 +456,10 @@ def main():
         "split_vs_fp64": fp64_ms_step / ms_step,
         "selection": {"moves": split["moves"], "near_ties": split["near_ties"]},
     }
+    out["precision_split_vs_fp64"] = {"headline": _precision_report(w, J, scale)}
     if args.thermalize_steps > 0:
         out["steps_to_thermalize"] = _thermalize(w, J, scale, args.thermalize_steps)
+        out["steps_to_thermalize"]["anneal_workload"] = _anneal_thermalize(args.anneal_steps)
         _log("thermalization study done")
     other = {}
     if args.small_steps > 0:
@@ -407,6 +471,10 @@ def main():
         _log("batched workload done")
     if args.large_steps > 0:
         other["sk_n8192_m1024_split"] = _large_workload(args)
+        wl = inputs.workload("sk_n8192_m1024_split")
+        Jl, sl = wl.couplings_matrix()
+        out["precision_split_vs_fp64"]["sk_n8192_m1024"] = _precision_report(wl, Jl, sl)
+        _log("large workload precision done")
     if other:
         out["other_workloads"] = other
     if not args.no_cpu:
