@@ -8,7 +8,11 @@
 //           fragment order: fragment (R, S, t) = rows 32R..32R+31, k = 16S..16S+15,
 //           term t, stored as 64 lanes x 8 bf16 (lane l holds row 32R + l%32,
 //           k = 16S + 8(l/32) + e for e = 0..7); 1 KiB per fragment.
-//   spins   [chains][W] uint32 bitsets (set bit = spin -1).
+//   spins   [chains][W] uint32 bitsets (set bit = spin -1); within a word, site k of
+//           its 32 sites sits at bit site_bit(k): even sites in the low half, odd
+//           sites in the high half, so that two sites 16 bits apart become the two
+//           bfloat16 signs of one register with a single shift (every bitset below
+//           uses this order).
 //   flipsT  ring of slots, one step each, slot = step % slots; a slot is [W][Bp]
 //           uint32: word w of the flip set F_{m+1} of edge m+1 of chain c at column
 //           c*M + m (columns contiguous, so a matrix-core B fragment's 32 columns are
@@ -32,6 +36,22 @@
 namespace mc3 {
 
 constexpr int kRowBlock = 128;  // rows of J per scoring work unit (4 fragments of 32)
+
+// Bit position of site k (0..31) within its word: site 2q at bit q, site 2q+1 at bit
+// 16+q.
+__host__ __device__ constexpr uint32_t site_bit(uint32_t k) { return ((k & 1u) << 4) | (k >> 1); }
+
+// A word in site order (bit k = site k) rearranged into the stored order, and back.
+__host__ __device__ inline uint32_t stored_word(uint32_t natural) {
+  uint32_t r = 0u;
+  for (uint32_t k = 0; k < 32u; ++k) r |= ((natural >> k) & 1u) << site_bit(k);
+  return r;
+}
+__host__ __device__ inline uint32_t natural_word(uint32_t stored) {
+  uint32_t r = 0u;
+  for (uint32_t k = 0; k < 32u; ++k) r |= ((stored >> site_bit(k)) & 1u) << k;
+  return r;
+}
 
 // One SK instance of a batch, as the kernels see it.  Byte offsets are into the
 // workspace; the per-chain arrays (energies, roots, counters, records) are global over

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_field_init(char* __restrict__ ws, const
     const double* row = J64 + (size_t)i * Np;
     double acc = 0.0;
     for (int j = 0; j < N; ++j) {
-      const double sj = ((s[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
+      const double sj = ((s[j >> 5] >> site_bit(j & 31)) & 1u) ? -1.0 : 1.0;
       acc += row[j] * sj;
     }
     h[i] = acc;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_field_init(char* __restrict__ ws, const
 }
 
 __device__ __forceinline__ double spin_of(const uint32_t* bits, int i) {
-  return ((bits[i >> 5] >> (i & 31)) & 1u) ? -1.0 : 1.0;
+  return ((bits[i >> 5] >> site_bit(i & 31)) & 1u) ? -1.0 : 1.0;
 }
 
 // Whether node u (>= 1) is node x or one of its ancestors (breadth-first labels:
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_step_delta(
       }
       __syncthreads();
       if (tid == 0) {
-        for (int a = 0; a < nd; ++a) sbits[dstar[a] >> 5] ^= 1u << (dstar[a] & 31);
+        for (int a = 0; a < nd; ++a) sbits[dstar[a] >> 5] ^= 1u << site_bit(dstar[a] & 31);
       }
       U += dU[vstar];
       __syncthreads();

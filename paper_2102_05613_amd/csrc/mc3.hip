@@ -842,7 +842,7 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
         for (int i = 0; i < h.desc.N; ++i) {
           const int8_t v = spins[off + (size_t)ch * h.desc.N + i];
           if (v != 1 && v != -1) return fail(c, MC3_E_ARG, "spin [%d][%d] is not +-1", h.chain0 + ch, i);
-          if (v == -1) bits[(size_t)ch * h.W + i / 32] |= 1u << (i % 32);
+          if (v == -1) bits[(size_t)ch * h.W + i / 32] |= 1u << mc3::site_bit(i % 32);
         }
       off += (size_t)h.desc.chains * h.desc.N;
       MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<uint32_t>(h.spins), bits.data(), bits.size() * 4,
@@ -944,7 +944,8 @@ mc3_status mc3_measure(mc3_ctx* c, double* e_cur, uint32_t* spin_bits, mc3_summa
       MC3_TRY(hip_ok(c, hipMemcpy(b.data(), c->at<uint32_t>(h.spins), b.size() * 4, hipMemcpyDeviceToHost),
                      "read spins"));
       for (int ch = 0; ch < h.desc.chains; ++ch)
-        std::memcpy(spin_bits + (size_t)(h.chain0 + ch) * pl.Wn_max, b.data() + (size_t)ch * h.W, (size_t)h.Wn * 4);
+        for (int w = 0; w < h.Wn; ++w)
+          spin_bits[(size_t)(h.chain0 + ch) * pl.Wn_max + w] = mc3::natural_word(b[(size_t)ch * h.W + w]);
     }
   }
   if (summary) {
@@ -1006,7 +1007,7 @@ mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
     MC3_TRY(hip_ok(c, hipMemcpy(t.data(), c->at<uint32_t>(c->pl.candT), t.size() * 4, hipMemcpyDeviceToHost),
                    "read"));
     for (int col = 0; col < h.B; ++col)
-      for (int w = 0; w < h.Wn; ++w) bits[(size_t)col * h.Wn + w] = t[(size_t)w * h.Bp + col];
+      for (int w = 0; w < h.Wn; ++w) bits[(size_t)col * h.Wn + w] = mc3::natural_word(t[(size_t)w * h.Bp + col]);
   }
   if (roots)
     MC3_TRY(hip_ok(c, hipMemcpy(roots, c->roots(st) + h.chain0, (size_t)h.desc.chains * 4, hipMemcpyDeviceToHost),

@@ -6,9 +6,9 @@ namespace mc3 {
 
 // ------------------------------------------------------------------- init spins
 
-// Spins of every chain from the init stream: word w of the chain's bitset is word w
-// of stream (init, chain_base + global chain, step 0, edge 0); bits at and beyond N
-// are cleared.  Grid: x over words (up to the largest W), y over global chains.
+// Spins of every chain from the init stream: site 32w + k is bit k of word w of
+// stream (init, chain_base + global chain, step 0, edge 0), stored at bit site_bit(k);
+// sites at and beyond N are cleared.  Grid: x over words (up to the largest W), y over global chains.
 __global__ void k_init_spins(char* __restrict__ ws, const Inst* __restrict__ insts,
                              const int32_t* __restrict__ chain_inst, int total_chains, Key key, uint32_t chain_base) {
   const int g = blockIdx.y;
@@ -23,6 +23,7 @@ __global__ void k_init_spins(char* __restrict__ ws, const Inst* __restrict__ ins
     v = pick(b, (uint32_t)w % 4u);
     int rem = in.N - w * 32;
     if (rem < 32) v &= (1u << rem) - 1u;
+    v = stored_word(v);
   }
   ws_at<uint32_t>(ws, in.spins)[(size_t)c * in.W + w] = v;
 }
@@ -63,9 +64,9 @@ __device__ __forceinline__ void draw_flip_set(uint32_t* set, Key key, uint32_t g
     if ((n & 3u) == 0u) blk = stream_block(key, kTagEdge, gc, step, e, n >> 2);
     const uint32_t j = (uint32_t)(N - k + idx);
     const uint32_t t = randint(pick(blk, n & 3u), j + 1u);
-    const uint32_t bt = set[t >> 5] >> (t & 31u) & 1u;
+    const uint32_t bt = set[t >> 5] >> site_bit(t & 31u) & 1u;
     const uint32_t pos = bt ? j : t;
-    set[pos >> 5] |= 1u << (pos & 31u);
+    set[pos >> 5] |= 1u << site_bit(pos & 31u);
   }
 }
 

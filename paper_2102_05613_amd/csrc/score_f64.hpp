@@ -64,7 +64,7 @@ __device__ __forceinline__ void f64_mfma(f64x4 (&acc)[4][4], const F64Stage& st,
     double b[4];
 #pragma unroll
     for (int cf = 0; cf < 4; ++cf) {
-      const uint32_t bit = (w[cf] >> (4 * s + (lane >> 4))) & 1u;
+      const uint32_t bit = (w[cf] >> site_bit(4 * s + (lane >> 4))) & 1u;
       b[cf] = __longlong_as_double(__double_as_longlong(one) | ((long long)bit << 63));
     }
 #pragma unroll
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_score_f64(char* __restrict__ ws, con
         double sum = 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int bit = (row0 & 31) + 4 * e + (lane >> 4);
+          const uint32_t bit = site_bit((row0 & 31) + 4 * e + (lane >> 4));
           const double h = acc[rf][cf][e];
           sum += ((rb >> bit) & 1u) ? -h : h;
         }

@@ -63,13 +63,14 @@ __global__ void k_pack_split(uint4* __restrict__ Apack, const double* __restrict
 
 // ------------------------------------------------------------------- split scoring
 
-// Expand 8 spin bits (set = -1) into 8 bfloat16 values +-1 (0x3F80 | bit << 15):
-// register p holds elements 2p (low half) and 2p+1 (high half).
-__device__ __forceinline__ bf16x8 spins_to_bf16(uint32_t byte) {
+// The 8 bfloat16 values +-1 (0x3F80 | bit << 15) of sites k0 .. k0+7 (k0 even) of a
+// stored word, q0 = k0 / 2: register p holds sites k0+2p (low half, stored at bit
+// q0+p) and k0+2p+1 (high half, bit 16+q0+p), so one shift brings both signs into
+// place.
+__device__ __forceinline__ bf16x8 spins_to_bf16(uint32_t word, int q0) {
   union { uint32_t u[4]; bf16x8 v; } r;
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
-    r.u[p] = ((byte << (30 - 2 * p)) & 0x80000000u) | ((byte << (15 - 2 * p)) & 0x00008000u) | 0x3F803F80u;
+  for (int p = 0; p < 4; ++p) r.u[p] = ((word << (15 - q0 - p)) & 0x80008000u) | 0x3F803F80u;
   return r.v;
 }
 
@@ -142,7 +143,7 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStag
   for (int s = 0; s < 2; ++s) {
     bf16x8 b[2];
 #pragma unroll
-    for (int cf = 0; cf < 2; ++cf) b[cf] = spins_to_bf16((w[cf] >> (16 * s + 8 * (lane >> 5))) & 0xFFu);
+    for (int cf = 0; cf < 2; ++cf) b[cf] = spins_to_bf16(w[cf], 8 * s + 4 * (lane >> 5));
     bf16x8 a[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
         double sum = 0.0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int bit = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+          const uint32_t bit = site_bit(8 * (e >> 2) + 4 * (lane >> 5) + (e & 3));
           const float h = __uint_as_float(__float_as_uint(acc[rf][cf][e]) ^ (((rb >> bit) & 1u) << 31));
           sum += (double)h;
         }

@@ -271,12 +271,12 @@ __global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, do
   const uint32_t* s = ws_at<const uint32_t>(ws, in.spins) + (size_t)c * W;
   double acc = 0.0;
   for (int i = 0; i < N; ++i) {
-    const double si = ((s[i >> 5] >> (i & 31)) & 1u) ? -1.0 : 1.0;
+    const double si = ((s[i >> 5] >> site_bit(i & 31)) & 1u) ? -1.0 : 1.0;
     const double* row = J64 + (size_t)i * Np;
     double rs = 0.0;
     for (int j = (int)threadIdx.x; j < N; j += 256) {
       if (j > i) {
-        const double sj = ((s[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
+        const double sj = ((s[j >> 5] >> site_bit(j & 31)) & 1u) ? -1.0 : 1.0;
         rs += row[j] * sj;
       }
     }
