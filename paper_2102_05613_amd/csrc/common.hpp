@@ -85,6 +85,20 @@ struct PBlock {
   int32_t inst, edge0;
 };
 
+// Asynchronous copy of 16 bytes per lane from global memory straight into LDS:
+// lane l's bytes land at lds_base + 16 l (lds_base must be wave-uniform).
+__device__ __forceinline__ void lds_dma16(const uint4* gsrc, uint4* lds_base) {
+  __builtin_amdgcn_global_load_lds((const void*)gsrc,
+                                   (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
+}
+
+// Asynchronous copy of 4 bytes per lane from global memory straight into LDS:
+// lane l's word lands at lds_base + 4 l.
+__device__ __forceinline__ void lds_dma4(const uint32_t* gsrc, uint32_t* lds_base) {
+  __builtin_amdgcn_global_load_lds((const void*)gsrc,
+                                   (__attribute__((address_space(3))) void*)lds_base, 4, 0, 0);
+}
+
 template <class T>
 __device__ __forceinline__ T* ws_at(char* ws, uint64_t off) {
   return reinterpret_cast<T*>(ws + off);

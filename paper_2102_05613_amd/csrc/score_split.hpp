@@ -74,28 +74,11 @@ __device__ __forceinline__ bf16x8 spins_to_bf16(uint32_t word, int q0) {
   return r.v;
 }
 
-// Asynchronous copy of 16 bytes per lane from global memory straight into LDS:
-// lane l's bytes land at lds_base + 16 l (lds_base must be wave-uniform).
-__device__ __forceinline__ void lds_dma16(const uint4* gsrc, uint4* lds_base) {
-  __builtin_amdgcn_global_load_lds((const void*)gsrc,
-                                   (__attribute__((address_space(3))) void*)lds_base, 16, 0, 0);
-}
-
-// Asynchronous copy of 4 bytes per lane from global memory straight into LDS:
-// lane l's word lands at lds_base + 4 l.
-__device__ __forceinline__ void lds_dma4(const uint32_t* gsrc, uint32_t* lds_base) {
-  __builtin_amdgcn_global_load_lds((const void*)gsrc,
-                                   (__attribute__((address_space(3))) void*)lds_base, 4, 0, 0);
-}
-
 // LDS stage of the split scoring loop: the four A fragment rows of the block (six
-// fragments each: two 16-k steps x three terms) and, per column of the tile, the
-// flip-set word and the chain's base word.
+// fragments each: two 16-k steps x three terms).
 template <int WAVES>
 struct SplitStage {
   uint4 a[4][6][64];
-  uint32_t flip[WAVES * 64];
-  uint32_t base[WAVES * 64];
 };
 
 // This wave's share of the 24 A fragments of a chunk (4 fragment rows x 6): PER =
@@ -115,30 +98,28 @@ __device__ __forceinline__ void copy_a(SplitStage<WAVES>& st, const uint4* src, 
   }
 }
 
-// One 32-k chunk of the split scoring loop: DMA of the next chunk into `nxt` (the 24
-// A fragments split evenly over the waves, each wave's own 64 columns' words), then
-// 2 k-steps x 12 A fragments x 2 columns fragments of MFMAs from `cur`.  Two distinct
-// LDS stages alternate, so the compiler can see that reading one never waits for the
-// copy into the other; nothing loaded from global memory is carried in registers
-// across chunks.  RF_LAST: row fragments rf > RF_LAST of this chunk lie entirely below
-// the diagonal (every k <= i), so their fragments are zero and are neither read nor
-// multiplied.  rootmask bit cf: this lane's column of fragment cf is its chain's root
-// column (bits = base only).
+// One 32-k chunk: DMA of the next chunk's A fragments into `nxt`; this chunk's flip
+// and base words (loaded into registers two chunks ago) combined; the loads of the
+// words two chunks ahead issued into the same registers; then 2 k-steps x 12 A
+// fragments x 2 column fragments of MFMAs from `cur`.  The closing wait lets the
+// four word loads stay in flight (they were issued after the copies; loads complete
+// in order), so global latency of the words is hidden behind two chunks.
 template <int WAVES, int RF_LAST = 3>
 __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStage<WAVES>& cur,
                                             SplitStage<WAVES>& nxt, const uint4* next_a, size_t row_stride,
-                                            const uint32_t* next_flip, const uint32_t* next_base, uint32_t rootmask,
-                                            int lane, int wave) {
+                                            uint32_t (&rawf)[2], uint32_t (&rawb)[2], const uint32_t* pf0,
+                                            const uint32_t* pf1, const uint32_t* pb0, const uint32_t* pb1,
+                                            uint32_t rootmask, int lane, int wave) {
   copy_a<WAVES>(nxt, next_a, row_stride, wave);
-  lds_dma4(next_flip, &nxt.flip[64 * wave]);
-  lds_dma4(next_base, &nxt.base[64 * wave]);
   __builtin_amdgcn_sched_barrier(0);
   uint32_t w[2];
 #pragma unroll
-  for (int cf = 0; cf < 2; ++cf) {
-    const int j = wave * 64 + cf * 32 + (lane & 31);
-    w[cf] = cur.base[j] ^ (((rootmask >> cf) & 1u) ? 0u : cur.flip[j]);
-  }
+  for (int cf = 0; cf < 2; ++cf) w[cf] = rawb[cf] ^ (((rootmask >> cf) & 1u) ? 0u : rawf[cf]);
+  rawf[0] = *pf0;
+  rawf[1] = *pf1;
+  rawb[0] = *pb0;
+  rawb[1] = *pb1;
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     bf16x8 b[2];
@@ -152,7 +133,6 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStag
       x.q = cur.a[i % 4][s * 3 + i / 4][lane];
       a[i] = x.v;
     }
-    // consecutive instructions update different accumulators
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
       if (i % 4 > RF_LAST) continue;
@@ -161,8 +141,9 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStag
         acc[i % 4][cf] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[cf], acc[i % 4][cf], 0, 0, 0);
     }
   }
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  // vmcnt(4), no wait on the other counters
+  __builtin_amdgcn_s_waitcnt(4 | (7 << 4) | (15 << 8));
+  __builtin_amdgcn_s_barrier();
 }
 
 // Energies of candidate columns on the BF16 matrix cores.
@@ -171,14 +152,15 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStag
 // J = hi + mid + lo.  A work unit is (row-block pair p, column tile of 64 WAVES
 // columns; 2, 4 or 8 waves, chosen per instance so that small instances waste few
 // padding columns): row blocks p and NB-1-p (128 rows each; their K ranges start at the
-// block's first row, so the pair costs NB+1 blocks of K whatever p is).  The waves
-// share the A fragments through LDS, filled by direct global->LDS copies one 32-k
-// chunk ahead (two stages, the copy running on from one row block into the next);
-// each wave owns 64 columns whose flip-set and base words come through LDS the same
-// way and are combined and expanded to +-1 in registers.  The epilogue multiplies h
-// by the column's spins and sums over rows in FP64; the unit writes one FP64 value
-// per column.  Each block takes its unit from a table built by the host (the order of
-// the table decides which XCD runs which unit).
+// block's first row, so the pair costs NB+1 blocks of K whatever p is), taken in an
+// order that alternates between units.  The waves share the A fragments through LDS,
+// filled by direct global->LDS copies one 32-k chunk ahead (two stages, the copy
+// running on from one row block into the next); each wave owns 64 columns, whose
+// flip-set and base words each lane loads into registers two chunks ahead, combines
+// and expands to +-1 BF16.  The epilogue multiplies h by the column's spins and sums
+// over rows in FP64; the unit writes one FP64 value per column.  Each block takes its
+// unit from a table built by the host (the order of the table decides which XCD runs
+// which unit).
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
     char* __restrict__ ws, const Inst* __restrict__ insts, const Unit* __restrict__ units,
@@ -204,11 +186,13 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
   const int KS = Np / 16;
   const int W = Np / 32;
   const int B = chains * M;
-  const int rf_w = (wave * PER) / 6, f_w = (wave * PER) % 6;   // this wave's first A copy slot
-  const size_t row_stride = (size_t)KS * 3 * 64;                 // uint4 between fragment rows
+  const int rf_w = (wave * PER) / 6, f_w = (wave * PER) % 6;
+  const size_t row_stride = (size_t)KS * 3 * 64;
 
-  // per-lane column data: base row of the copied column, root-column mask
-  const uint32_t* brow = base + (size_t)(col_w + lane < B ? (col_w + lane) / M : chains) * W;
+  // this lane's two columns: flip-word columns, base rows, root-column mask
+  const int col0 = col_w + (lane & 31), col1 = col0 + 32;
+  const uint32_t* brow0 = base + (size_t)(col0 < B ? col0 / M : chains) * W;
+  const uint32_t* brow1 = base + (size_t)(col1 < B ? col1 / M : chains) * W;
   uint32_t rootmask = 0u;
 #pragma unroll
   for (int cf = 0; cf < 2; ++cf) {
@@ -218,29 +202,40 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
       if (r >= 1 && col - c * M == r - 1) rootmask |= 1u << cf;
     }
   }
-
   double part[2] = {0.0, 0.0};
 
-  // the unit's row blocks p and NB-1-p, in an order that alternates between units
   const int nblk = (p == NB - 1 - p) ? 1 : 2;
   const int first = ((p + ct) & 1) ? NB - 1 - p : p;
   const int second = NB - 1 - first;
-  // this wave's first A fragment of chunk 0 of row block I
+  const int nA = (Np - first * kRowBlock) / 32;
+  const int nTot = nA + (nblk == 2 ? (Np - second * kRowBlock) / 32 : 0);
+  // word row (k / 32) of the unit's chunk g (0 .. nTot-1), clamped to the last chunk
+  auto kw_of = [&](int g) {
+    g = g < nTot ? g : nTot - 1;
+    return g < nA ? 4 * first + g : 4 * second + (g - nA);
+  };
   auto a_src = [&](int I) {
     return Apack + (((size_t)(4 * I + rf_w) * KS + 8 * I) * 3 + f_w) * 64 + lane;
   };
+  uint32_t rfE[2], rbE[2], rfO[2], rbO[2];   // raw words of even and odd chunks
   {
-    const int kw = 4 * first;
+    const int k0w = kw_of(0), k1w = kw_of(1);
+    rfE[0] = flipsT[(size_t)k0w * Bp + col0];
+    rfE[1] = flipsT[(size_t)k0w * Bp + col1];
+    rbE[0] = brow0[k0w];
+    rbE[1] = brow1[k0w];
+    rfO[0] = flipsT[(size_t)k1w * Bp + col0];
+    rfO[1] = flipsT[(size_t)k1w * Bp + col1];
+    rbO[0] = brow0[k1w];
+    rbO[1] = brow1[k1w];
     copy_a<WAVES>(st0, a_src(first), row_stride, wave);
-    lds_dma4(flipsT + (size_t)kw * Bp + col_w + lane, &st0.flip[64 * wave]);
-    lds_dma4(brow + kw, &st0.base[64 * wave]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
+  int g = 0;   // the unit's chunk index
   for (int bi = 0; bi < nblk; ++bi) {
     const int I = bi == 0 ? first : second;
-    const int kw0 = 4 * I;
     const int nchunk = (Np - I * kRowBlock) / 32;   // a multiple of 4
     f32x16 acc[4][2];
 #pragma unroll
@@ -249,41 +244,24 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
       for (int cf = 0; cf < 2; ++cf)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[rf][cf][e] = 0.0f;
-
     const uint4* src = a_src(I);
-    const uint32_t* fsrc = flipsT + (size_t)kw0 * Bp + col_w + lane;
-    // the chunk after this block's last: the next block's first chunk, or (none) this
-    // block's last chunk again (in bounds; not read before the next refill)
     const bool more = bi + 1 < nblk;
-    const int kwn = more ? 4 * second : kw0 + nchunk - 1;
     const uint4* src_n = more ? a_src(second) : src + (size_t)(nchunk - 1) * 6 * 64;
-    const uint32_t* fsrc_n = flipsT + (size_t)kwn * Bp + col_w + lane;
-    // chunk c of this row block: A at src + 6*64 c, flip words at fsrc + Bp c, base
-    // words at brow + kw0 + c; the first four chunks cover the diagonal block: chunk c
-    // needs row fragments 0..c (nchunk is a multiple of 4)
-#define MC3_NEXT(cn)                                                                       \
-  const bool e##cn = (cn) >= nchunk;                                                       \
-  const uint4* na##cn = e##cn ? src_n : src + (size_t)(cn) * 6 * 64;                       \
-  const uint32_t* nf##cn = e##cn ? fsrc_n : fsrc + (size_t)(cn) * Bp;                      \
-  const uint32_t* nb##cn = brow + (e##cn ? kwn : kw0 + (cn));
-    {
-      MC3_NEXT(1)
-      split_chunk<WAVES, 0>(acc, st0, st1, na1, row_stride, nf1, nb1, rootmask, lane, wave);
-      MC3_NEXT(2)
-      split_chunk<WAVES, 1>(acc, st1, st0, na2, row_stride, nf2, nb2, rootmask, lane, wave);
-      MC3_NEXT(3)
-      split_chunk<WAVES, 2>(acc, st0, st1, na3, row_stride, nf3, nb3, rootmask, lane, wave);
-      MC3_NEXT(4)
-      split_chunk<WAVES, 3>(acc, st1, st0, na4, row_stride, nf4, nb4, rootmask, lane, wave);
-    }
+    // A of the chunk after local chunk c (the next block's first after the last)
+#define MC3_A(cn) (((cn) >= nchunk) ? src_n : src + (size_t)(cn) * 6 * 64)
+#define MC3_W(gg) flipsT + (size_t)kw_of(gg) * Bp + col0, flipsT + (size_t)kw_of(gg) * Bp + col1, \
+                  brow0 + kw_of(gg), brow1 + kw_of(gg)
+    split_chunk<WAVES, 0>(acc, st0, st1, MC3_A(1), row_stride, rfE, rbE, MC3_W(g + 2), rootmask, lane, wave);
+    split_chunk<WAVES, 1>(acc, st1, st0, MC3_A(2), row_stride, rfO, rbO, MC3_W(g + 3), rootmask, lane, wave);
+    split_chunk<WAVES, 2>(acc, st0, st1, MC3_A(3), row_stride, rfE, rbE, MC3_W(g + 4), rootmask, lane, wave);
+    split_chunk<WAVES, 3>(acc, st1, st0, MC3_A(4), row_stride, rfO, rbO, MC3_W(g + 5), rootmask, lane, wave);
     for (int c = 4; c < nchunk; c += 2) {
-      const int ca = c + 1, cb = c + 2;
-      MC3_NEXT(ca)
-      split_chunk<WAVES>(acc, st0, st1, naca, row_stride, nfca, nbca, rootmask, lane, wave);
-      MC3_NEXT(cb)
-      split_chunk<WAVES>(acc, st1, st0, nacb, row_stride, nfcb, nbcb, rootmask, lane, wave);
+      split_chunk<WAVES>(acc, st0, st1, MC3_A(c + 1), row_stride, rfE, rbE, MC3_W(g + c + 2), rootmask, lane, wave);
+      split_chunk<WAVES>(acc, st1, st0, MC3_A(c + 2), row_stride, rfO, rbO, MC3_W(g + c + 3), rootmask, lane, wave);
     }
-#undef MC3_NEXT
+#undef MC3_A
+#undef MC3_W
+    g += nchunk;
     // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf + lane%32
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf) {
