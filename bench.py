@@ -364,6 +364,41 @@ def _anneal_thermalize(T):
     return out
 
 
+def _large_thermalize(T):
+    """Steps to thermalize under the large workload's anneal (N = 8192, 32 chains,
+    M = 1024, 256-spin flip sets, beta 0.2 -> 2.5 over T steps, split BF16) against
+    single-flip Metropolis under the same schedule (pair-sum FP64 scorer: the
+    field-update scorer stops at N = 4096)."""
+    import torch
+    from paper_2102_05613_amd import inputs
+    w = inputs.workload("sk_n8192_m1024_split")
+    J, scale = w.couplings_matrix()
+    runs = {}
+    for name, prec, rule, M, kmin, kmax in (("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax),
+                                            ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1)):
+        ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s0 in range(0, T, 1000):
+            ctx.step_n(s0, min(1000, T - s0), w.beta0, w.beta1, T)
+            ctx.sync()
+            _log(f"large thermalize {name}: {s0 + min(1000, T - s0)} / {T}")
+        wall = time.perf_counter() - t0
+        runs[name] = {"wall_s": wall, "e_bar": ctx.read_means(0, T)[:, 1] / w.N, "M": M}
+        ctx.close()
+    tail = {k: float(np.mean(r["e_bar"][-max(1, T // 100):])) for k, r in runs.items()}
+    ref = min(tail.values())
+    window = max(10, T // 100)
+    out = {"workload": w.name, "beta": [w.beta0, w.beta1], "T": T, "window": window,
+           "reference_energy_per_spin": ref,
+           "note": "reference = lowest mean over the last 1% of steps (the coldest part of the anneal)"}
+    for k, r in runs.items():
+        t = _t_within(r["e_bar"], ref, window)
+        out[k] = {"t_steps": t if t is not None else f"> {T}", "final_energy_per_spin": tail[k],
+                  "t_seconds": None if t is None else t * r["wall_s"] / T, "ms_per_step": r["wall_s"] / T * 1e3}
+    return out
+
+
 def _cpu_baseline(w, J, scale, sample_chains):
     import oracle
     t0 = time.perf_counter()
@@ -384,6 +419,8 @@ def main():
     ap.add_argument("--thermalize-steps", type=int, default=20000)
     ap.add_argument("--cpu-chains", type=int, default=160)
     ap.add_argument("--anneal-steps", type=int, default=100000)
+    ap.add_argument("--large-thermalize-steps", type=int, default=0,
+                    help="steps of the N=8192 anneal study (0 skips it; 20000 is the workload's schedule)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--small-steps", type=int, default=10000,
                     help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
@@ -475,6 +512,8 @@ def main():
         Jl, sl = wl.couplings_matrix()
         out["precision_split_vs_fp64"]["sk_n8192_m1024"] = _precision_report(wl, Jl, sl)
         _log("large workload precision done")
+    if args.large_thermalize_steps > 0:
+        out.setdefault("steps_to_thermalize", {})["large_workload"] = _large_thermalize(args.large_thermalize_steps)
     if other:
         out["other_workloads"] = other
     if not args.no_cpu:
