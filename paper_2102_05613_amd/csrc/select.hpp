@@ -139,9 +139,10 @@ __device__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint3
 //      p) into the node-energy array En (LDS) at their node (column m is node m+1,
 //      or the hub for column r-1), the root's entry = carried energy;
 //   2. wave 0: the rule (apply_rule) and the bookkeeping;
-//   3. all threads: the new state's bitset, base ^ F_{v*} (base alone for the hub),
-//      or unchanged;
-//   4. next_base: base of step t+1 = new state ^ F_{r'} of that step's root r'.
+//   3. thread w (one word each, W <= 256): the new state's word, base ^ P(v*) (base
+//      alone for node 0), or unchanged; its spins, base and next-root words are loaded
+//      before step 1, so only the chosen node's column waits for the rule;
+//   4. next_base: base of step t+1 = new state ^ P(r') of that step's root r'.
 // Dynamic LDS: 16 (M+1) + 4 W bytes.
 __global__ __launch_bounds__(256) void k_select(
     char* __restrict__ ws, const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
@@ -170,9 +171,21 @@ __global__ __launch_bounds__(256) void k_select(
   const int nodes = M + 1;
   double* En = sel_lds;                                                              // [nodes]
   unsigned long long* Qn = reinterpret_cast<unsigned long long*>(sel_lds + nodes);   // [nodes]
-  uint32_t* snew = reinterpret_cast<uint32_t*>(sel_lds + 2 * (size_t)nodes);        // [W]
   const int r = metropolis ? 0 : roots[c];
   const double ecur = e_cur[g];
+
+  // words of this thread (W <= 256): current spins, base, and the next step's root
+  // column, loaded now so that only the chosen node's column waits for the rule
+  const int w = tid;
+  uint32_t s_old = 0u, b_cur = 0u, f_next = 0u;
+  if (w < W) {
+    s_old = spins[(size_t)c * W + w];
+    b_cur = base[(size_t)c * W + w];
+    if (next_base) {
+      const int r1 = roots_next[c];
+      if (r1 >= 1) f_next = flipsT_next[(size_t)w * Bp + (size_t)c * M + (r1 - 1)];
+    }
+  }
 
   // 1. node energies
   for (int m = tid; m < M; m += 256) {
@@ -197,29 +210,17 @@ __global__ __launch_bounds__(256) void k_select(
   }
   __syncthreads();
 
-  // 3. the new state
+  // 3. the new state, and 4. the base of the next step
   const int vstar = sh_vstar;
   const bool moved = vstar != r;
-  for (int w = tid; w < W; w += 256) {
-    uint32_t x;
+  if (w < W) {
+    uint32_t x = s_old;
     if (moved) {
-      x = base[(size_t)c * W + w];
+      x = b_cur;
       if (vstar >= 1) x ^= flipsT[(size_t)w * Bp + (size_t)c * M + (vstar - 1)];
       spins[(size_t)c * W + w] = x;
-    } else {
-      x = spins[(size_t)c * W + w];
     }
-    snew[w] = x;
-  }
-  if (!next_base) return;
-  __syncthreads();
-
-  // 4. base of the next step
-  const int r1 = roots_next[c];
-  for (int w = tid; w < W; w += 256) {
-    uint32_t x = snew[w];
-    if (r1 >= 1) x ^= flipsT_next[(size_t)w * Bp + (size_t)c * M + (r1 - 1)];
-    base_next[(size_t)c * W + w] = x;
+    if (next_base) base_next[(size_t)c * W + w] = x ^ f_next;
   }
 }
 
