@@ -22,7 +22,7 @@ struct RuleOut {
   double e_new, ebar, margin;
 };
 
-__device__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, int r, double ecur, int metropolis,
+__device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, int r, double ecur, int metropolis,
                               double beta, uint64_t u53, int lane, const double* __restrict__ prior) {
   RuleOut o;
   const int nodes = M + 1;
@@ -110,7 +110,7 @@ __device__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, i
 
 // Per-chain bookkeeping of a selected step (one lane): carried energy, node-weighted
 // energy, counters and, with a ring, the step's record.
-__device__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint32_t step, int trace_steps,
+__device__ __forceinline__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint32_t step, int trace_steps,
                                int total_chains, double* e_cur, double* e_bar_out, unsigned long long* moves,
                                unsigned long long* near_ties, double* min_margin, Record* ring) {
   const bool moved = o.vstar != r;
@@ -133,17 +133,76 @@ __device__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint3
   }
 }
 
+// Node energies of chain c into En (LDS), by the threads t = 0 .. nt-1 of a group: the
+// column energies -(scale * sum_p partial[p][col]) (fixed order over p) at their node
+// (column m is node m+1, or the hub for column r-1), and the root's entry the carried
+// energy.
+__device__ __forceinline__ void node_energies(double* En, const double* __restrict__ partial, int P, size_t Bp,
+                                              size_t col0, int M, int r, double scale, double ecur, int t, int nt) {
+  for (int m = t; m < M; m += nt) {
+    const size_t col = col0 + m;
+    double acc = 0.0;
+    for (int q = 0; q < P; ++q) acc += partial[(size_t)q * Bp + col];
+    En[(r >= 1 && m == r - 1) ? 0 : m + 1] = -(scale * acc);
+  }
+  if (t == 0) En[r] = ecur;
+}
+
+// The words of one chain's state that a group of NT threads handles (thread t owns
+// words t, t + NT, ...; W <= 256): current spins, this step's base and the next step's
+// root column, loaded before the rule so that only the chosen node's column waits for
+// it.
+template <int NT>
+struct ChainWords {
+  static constexpr int K = 256 / NT;
+  uint32_t s_old[K], b_cur[K], f_next[K];
+
+  // col_next: the next step's root column c*M + r'-1, or < 0 when r' = 0 or there is
+  // no next step
+  __device__ __forceinline__ void load(const uint32_t* __restrict__ spins_c, const uint32_t* __restrict__ base_c,
+                                       const uint32_t* __restrict__ flipsT_next, size_t Bp, long long col_next,
+                                       int W, int t) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int w = t + k * NT;
+      s_old[k] = b_cur[k] = f_next[k] = 0u;
+      if (w < W) {
+        s_old[k] = spins_c[w];
+        b_cur[k] = base_c[w];
+        if (col_next >= 0) f_next[k] = flipsT_next[(size_t)w * Bp + (size_t)col_next];
+      }
+    }
+  }
+
+  // The move to node vstar (base ^ P(v*), the base alone for node 0; unchanged when
+  // v* = r) and, with next_base, the next step's base = new state ^ P(r').
+  __device__ __forceinline__ void store(uint32_t* __restrict__ spins_c, uint32_t* __restrict__ base_next_c,
+                                        const uint32_t* __restrict__ flipsT, size_t Bp, size_t col0, int vstar,
+                                        int r, bool next_base, int W, int t) const {
+    const bool moved = vstar != r;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int w = t + k * NT;
+      if (w < W) {
+        uint32_t x = s_old[k];
+        if (moved) {
+          x = b_cur[k];
+          if (vstar >= 1) x ^= flipsT[(size_t)w * Bp + col0 + (size_t)(vstar - 1)];
+          spins_c[w] = x;
+        }
+        if (next_base) base_next_c[w] = x ^ f_next[k];
+      }
+    }
+  }
+};
+
 // One block of 256 threads per chain: node rule (MCMCMC) or Metropolis rate, move,
 // record, and (next_base) the base words of step t+1.
-//   1. all threads: column energies -(scale * sum_p partial[p][col]) (fixed order over
-//      p) into the node-energy array En (LDS) at their node (column m is node m+1,
-//      or the hub for column r-1), the root's entry = carried energy;
+//   1. all threads: the node energies (node_energies);
 //   2. wave 0: the rule (apply_rule) and the bookkeeping;
-//   3. thread w (one word each, W <= 256): the new state's word, base ^ P(v*) (base
-//      alone for node 0), or unchanged; its spins, base and next-root words are loaded
-//      before step 1, so only the chosen node's column waits for the rule;
-//   4. next_base: base of step t+1 = new state ^ P(r') of that step's root r'.
-// Dynamic LDS: 16 (M+1) + 4 W bytes.
+//   3. thread w: the new state's word and the next step's base word (ChainWords),
+//      loaded before step 1.
+// Dynamic LDS: 16 (M+1) bytes.
 __global__ __launch_bounds__(256) void k_select(
     char* __restrict__ ws, const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
     int total_chains, double* __restrict__ e_cur, const int32_t* __restrict__ roots_all,
@@ -158,46 +217,28 @@ __global__ __launch_bounds__(256) void k_select(
   if (g >= total_chains) return;
   const Inst& in = insts[chain_inst[g]];
   const int c = g - in.chain0;            // chain within the instance
-  const int M = in.M, W = in.W, Bp = in.Bp, P = in.P;
-  const double scale = in.scale;
-  uint32_t* __restrict__ spins = ws_at<uint32_t>(ws, in.spins);
+  const int M = in.M, W = in.W;
+  const size_t Bp = (size_t)in.Bp, col0 = (size_t)c * M;
+  uint32_t* __restrict__ spins = ws_at<uint32_t>(ws, in.spins) + (size_t)c * W;
   const uint32_t* __restrict__ flipsT = flips_at(ws, in, slot);
-  const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[step & 1u]);
+  const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[step & 1u]) + (size_t)c * W;
   const uint32_t* __restrict__ flipsT_next = flips_at(ws, in, slot_next);
-  uint32_t* __restrict__ base_next = ws_at<uint32_t>(ws, in.base[(step + 1u) & 1u]);
-  const double* __restrict__ partial = ws_at<const double>(ws, in.partial);
-  const int32_t* __restrict__ roots = roots_all + in.chain0;
-  const int32_t* __restrict__ roots_next = roots_next_all + in.chain0;
+  uint32_t* __restrict__ base_next = ws_at<uint32_t>(ws, in.base[(step + 1u) & 1u]) + (size_t)c * W;
   const int nodes = M + 1;
   double* En = sel_lds;                                                              // [nodes]
   unsigned long long* Qn = reinterpret_cast<unsigned long long*>(sel_lds + nodes);   // [nodes]
-  const int r = metropolis ? 0 : roots[c];
+  const int r = metropolis ? 0 : roots_all[in.chain0 + c];
   const double ecur = e_cur[g];
-
-  // words of this thread (W <= 256): current spins, base, and the next step's root
-  // column, loaded now so that only the chosen node's column waits for the rule
-  const int w = tid;
-  uint32_t s_old = 0u, b_cur = 0u, f_next = 0u;
-  if (w < W) {
-    s_old = spins[(size_t)c * W + w];
-    b_cur = base[(size_t)c * W + w];
-    if (next_base) {
-      const int r1 = roots_next[c];
-      if (r1 >= 1) f_next = flipsT_next[(size_t)w * Bp + (size_t)c * M + (r1 - 1)];
-    }
+  long long col_next = -1;
+  if (next_base) {
+    const int r1 = roots_next_all[in.chain0 + c];
+    if (r1 >= 1) col_next = (long long)col0 + (r1 - 1);
   }
+  ChainWords<256> cw;
+  cw.load(spins, base, flipsT_next, Bp, col_next, W, tid);
 
-  // 1. node energies
-  for (int m = tid; m < M; m += 256) {
-    const size_t col = (size_t)c * M + m;
-    double acc = 0.0;
-    for (int q = 0; q < P; ++q) acc += partial[(size_t)q * Bp + col];
-    En[(r >= 1 && m == r - 1) ? 0 : m + 1] = -(scale * acc);
-  }
-  if (tid == 0) En[r] = ecur;
+  node_energies(En, ws_at<const double>(ws, in.partial), in.P, Bp, col0, M, r, in.scale, ecur, tid, 256);
   __syncthreads();
-
-  // 2. the rule (wave 0)
   if (wave == 0) {
     const uint4 ub = stream_block(key, kTagSelect, chain_base + (uint32_t)g, step, 0u, 0u);
     const RuleOut o = apply_rule(En, Qn, M, r, ecur, metropolis, beta, u53_of(ub.x, ub.y), lane,
@@ -209,19 +250,7 @@ __global__ __launch_bounds__(256) void k_select(
     }
   }
   __syncthreads();
-
-  // 3. the new state, and 4. the base of the next step
-  const int vstar = sh_vstar;
-  const bool moved = vstar != r;
-  if (w < W) {
-    uint32_t x = s_old;
-    if (moved) {
-      x = b_cur;
-      if (vstar >= 1) x ^= flipsT[(size_t)w * Bp + (size_t)c * M + (vstar - 1)];
-      spins[(size_t)c * W + w] = x;
-    }
-    if (next_base) base_next[(size_t)c * W + w] = x ^ f_next;
-  }
+  cw.store(spins, base_next, flipsT, Bp, col0, sh_vstar, r, next_base != 0, W, tid);
 }
 
 // ------------------------------------------------------------------- means trace

@@ -63,5 +63,8 @@ def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas,
         assert np.array_equal(gpu_rec["e_cur"], orec["e_cur"])
     else:
         np.testing.assert_allclose(gpu_rec["e_cur"], orec["e_cur"], rtol=energy_rtol, atol=energy_rtol)
-    np.testing.assert_allclose(gpu_rec["e_bar"], orec["e_bar"], rtol=max(energy_rtol, 1e-12), atol=1e-12)
+    # e_bar is a weighted mean of node energies that each carry the path's absolute
+    # error, so it takes the same absolute tolerance as e_cur
+    np.testing.assert_allclose(gpu_rec["e_bar"], orec["e_bar"], rtol=max(energy_rtol, 1e-12),
+                               atol=max(energy_rtol, 1e-12))
     return ro, int((forced >= 0).sum())

@@ -1,0 +1,110 @@
+"""mc3_step_n (flip sets drawn ahead, and the selection of step t-1 taken inside the
+scoring launch of step t where the shape allows) against the single-step calls
+(mc3_propose / mc3_score_candidates / mc3_select) and the oracle.
+
+Both paths read the same partial sums in the same order and apply the same rule, so
+their records, states and counters agree bit for bit.  The shapes put one chain in a
+tile, many chains in one tile, chains straddling tile edges, chains spanning several
+tiles, a node count whose weights leave room for only two selecting waves, a tree, the
+line law, and a shape with too many chains per tile, which keeps the selection
+launch.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import announce, compare_trajectory, gpu_spins
+from paper_2102_05613_amd import inputs, native
+
+pytestmark = pytest.mark.gpu
+
+# (N, M, chains, kmax, rule, arity, law, oracle): arity 0 = the star
+CASES = [
+    (40, 1, 20, 2, "metropolis", 0, "uniform", True),    # 20 chains in one 128-column tile
+    (64, 1, 32, 3, "mcmcmc", 0, "uniform", True),        # the per-tile cap exactly
+    (300, 120, 9, 16, "mcmcmc", 0, "uniform", True),     # 256-column tiles, chains straddle edges
+    (256, 600, 3, 8, "mcmcmc", 0, "uniform", False),     # each chain spans 3-4 tiles
+    (160, 1500, 2, 4, "mcmcmc", 0, "uniform", False),    # 512-column tiles, two selecting waves
+    (200, 62, 10, 4, "mcmcmc", 2, "uniform", True),      # binary tree
+    (128, 40, 8, 3, "mcmcmc", 1, "line", True),          # line graph, binomial root, log-prior
+    (96, 1, 200, 2, "metropolis", 0, "uniform", False),  # 200 chains per tile: separate launch
+]
+
+
+def _ctx(N, M, chains, kmax, rule, arity, law, J, scale, steps, seed):
+    cfg = native.make_config(N, M, chains, 1, kmax, precision="split_bf16", rule=rule, trace_steps=steps,
+                             seed=seed, mean_steps=steps, arity=arity, law=law)
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    return ctx
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    native.lib()
+
+
+@pytest.mark.parametrize("N,M,chains,kmax,rule,arity,law,with_oracle", CASES)
+def test_select_in_scoring_matches_separate_launch(N, M, chains, kmax, rule, arity, law, with_oracle):
+    steps, seed = 24, 41
+    beta = 1.3
+    announce(f"select in scoring N={N} M={M} chains={chains} {rule} arity={arity} {law}")
+    J, scale = inputs.couplings_gauss(N, 900 + N + M)
+    # one step_n call per half, so that the counters must be back at zero between calls
+    a = _ctx(N, M, chains, kmax, rule, arity, law, J, scale, steps, seed)
+    a.step_n(0, steps // 2, beta, beta, 1)
+    a.step_n(steps // 2, steps - steps // 2, beta, beta, 1)
+    b = _ctx(N, M, chains, kmax, rule, arity, law, J, scale, steps, seed)
+    for t in range(steps):
+        b.propose(t)
+        b.score_candidates()
+        b.select(t, beta)
+    ra, rb = a.read_records(0, steps), b.read_records(0, steps)
+    for f in ("r", "vstar", "e_cur", "e_bar", "margin", "flags", "step"):
+        assert np.array_equal(ra[f], rb[f]), f
+    assert np.array_equal(a.read_means(0, steps), b.read_means(0, steps))
+    ea, bits_a, sa = a.measure()
+    eb, bits_b, sb = b.measure()
+    assert np.array_equal(ea, eb)
+    assert np.array_equal(bits_a, bits_b)
+    for k in ("moves", "near_ties", "min_margin", "steps_done"):
+        assert sa[k] == sb[k], k
+    assert sa["moves"] > 0
+    if with_oracle:
+        compare_trajectory(ra, J, scale, N, M, chains, 1, kmax, seed, np.full(steps, beta), rule, 1e-4,
+                           arity=arity if arity else None, law=law)
+    a.close()
+    b.close()
+
+
+def test_select_in_scoring_headline_shape_repeatable():
+    """Headline shape (N=1024, 256 chains x M=128): two runs of 20 steps through the
+    one-launch step agree bit for bit, and agree with the separate launches."""
+    N, M, chains, steps = 1024, 128, 256, 20
+    announce("select in scoring headline shape")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0003)
+    runs = []
+    for rep in range(2):
+        cfg = native.make_config(N, M, chains, 1, 128, precision="split_bf16", trace_steps=steps, seed=3)
+        ctx = native.Context(cfg)
+        ctx.init_couplings(J, scale)
+        ctx.init_chains()
+        ctx.step_n(0, steps, 2.0, 2.0, 1)
+        runs.append((ctx.read_records(0, steps), gpu_spins(ctx)))
+        ctx.close()
+    cfg = native.make_config(N, M, chains, 1, 128, precision="split_bf16", trace_steps=steps, seed=3)
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    for t in range(steps):
+        ctx.propose(t)
+        ctx.score_candidates()
+        ctx.select(t, 2.0)
+    runs.append((ctx.read_records(0, steps), gpu_spins(ctx)))
+    for rec, s in runs[1:]:
+        for f in ("r", "vstar", "e_cur", "e_bar", "margin", "flags"):
+            assert np.array_equal(rec[f], runs[0][0][f]), f
+        assert np.array_equal(s, runs[0][1])
