@@ -288,9 +288,12 @@ mc3_status mc3_read_candidates(mc3_ctx* ctx, uint32_t* bits, int32_t* roots);
  * (Eq. eq_monte_carlo_graph)}.  Both means are fixed-order device reductions. */
 mc3_status mc3_read_means(mc3_ctx* ctx, uint32_t first, int32_t n, double* out);
 
-/* Measurement aid: while enabled, every scoring-kernel launch (mc3_score_candidates,
- * mc3_step_n) is bracketed by HIP events recorded on the stream it runs on.
- * Enabling resets the totals. */
+/* Measurement aid.  on = 0 disables; on = k >= 1 brackets every k-th scoring-kernel
+ * launch (mc3_score_candidates, mc3_step_n; the first one after enabling, then every
+ * k-th) with timestamp-only HIP events (no system-scope cache flush) recorded on the
+ * stream it runs on: k = 1 times every launch, a larger k keeps the events' own cost
+ * (a few microseconds per record) out of a long run.  Enabling resets the totals.
+ * MC3_E_ARG for on < 0. */
 mc3_status mc3_timing_enable(mc3_ctx* ctx, int32_t on);
 
 /* Synchronise; total milliseconds of the timed scoring launches and their number. */

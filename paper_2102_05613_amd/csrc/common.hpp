@@ -104,35 +104,67 @@ __device__ __forceinline__ T* ws_at(char* ws, uint64_t off) {
   return reinterpret_cast<T*>(ws + off);
 }
 
-// Wave-wide reductions (64 lanes, fixed butterfly order: every lane ends with the
-// same value).
+// Wave-wide operations (64 lanes, all active) on DPP lane permutations and lane reads,
+// with no LDS round trips.  A reduction swaps neighbours, then pairs, then half-rows,
+// then the halves of each row of 16 lanes (every lane of a row then holds the row's
+// result: the operations are commutative) and combines the four rows read from lanes
+// 0, 16, 32 and 48 as (r0 . r1) . (r2 . r3); sums are taken in this fixed order.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const uint32_t lo = dpp_u32<CTRL>((uint32_t)b), hi = dpp_u32<CTRL>((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+template <class Op>
+__device__ __forceinline__ double wave_reduce_f64(double x, Op op) {
+  x = op(x, dpp_f64<0xB1>(x));    // quad_perm [1,0,3,2]
+  x = op(x, dpp_f64<0x4E>(x));    // quad_perm [2,3,0,1]
+  x = op(x, dpp_f64<0x141>(x));   // row_half_mirror
+  x = op(x, dpp_f64<0x140>(x));   // row_mirror
+  const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16), r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x = x + __shfl_xor(x, o);
-  return x;
+  return wave_reduce_f64(x, [](double a, double b) { return a + b; });
 }
 __device__ __forceinline__ double wave_min(double x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) { double y = __shfl_xor(x, o); x = y < x ? y : x; }
-  return x;
+  return wave_reduce_f64(x, [](double a, double b) { return b < a ? b : a; });
 }
 __device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) { double y = __shfl_xor(x, o); x = y > x ? y : x; }
-  return x;
+  return wave_reduce_f64(x, [](double a, double b) { return b > a ? b : a; });
 }
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
-  return x;
+// row_shr by N: a lane whose source lies before the start of its row reads 0
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_shr_u64(unsigned long long x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
 }
+// Inclusive prefix sum over the lanes (exact integer arithmetic): Hillis-Steele within
+// each row (shifts 1, 2, 4, 8), then the totals of the rows before.
 __device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long x, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    unsigned long long y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  return x;
+  x += dpp_shr_u64<0x111>(x);
+  x += dpp_shr_u64<0x112>(x);
+  x += dpp_shr_u64<0x114>(x);
+  x += dpp_shr_u64<0x118>(x);
+  const unsigned long long r0 = readlane_u64(x, 15), r1 = readlane_u64(x, 31), r2 = readlane_u64(x, 47);
+  const int row = lane >> 4;
+  return x + (row >= 1 ? r0 : 0ull) + (row >= 2 ? r1 : 0ull) + (row >= 3 ? r2 : 0ull);
 }
 
 struct Record {

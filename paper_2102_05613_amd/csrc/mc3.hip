@@ -318,6 +318,8 @@ struct mc3_ctx {
   int64_t steps_done = 0;
   // optional HIP-event timing of the scoring launches
   bool timing = false;
+  int32_t t_every = 1;      // bracket every t_every-th scoring launch
+  int64_t t_seen = 0;       // scoring launches since timing was enabled
   std::vector<hipEvent_t> t_start, t_stop;
   std::vector<char> t_pending;
   size_t t_next = 0;
@@ -525,7 +527,8 @@ struct ScoreLaunch {
 
 mc3_status score_timed(mc3_ctx* c, const ScoreLaunch* tables, int n) {
   size_t i = 0;
-  if (c->timing) {
+  const bool timed = c->timing && (c->t_seen++ % c->t_every) == 0;
+  if (timed) {
     i = c->t_next;
     c->t_next = (c->t_next + 1) % c->t_start.size();
     MC3_TRY(timing_collect(c, i));
@@ -533,7 +536,7 @@ mc3_status score_timed(mc3_ctx* c, const ScoreLaunch* tables, int n) {
   }
   for (int k = 0; k < n; ++k)
     if (tables[k].grid > 0) MC3_TRY(launch_score_units(c, tables[k].off, tables[k].grid, tables[k].cls));
-  if (c->timing) {
+  if (timed) {
     MC3_TRY(hip_ok(c, hipEventRecord(c->t_stop[i], c->stream), "timing event"));
     c->t_pending[i] = 1;
   }
@@ -1017,20 +1020,24 @@ mc3_status mc3_read_candidates(mc3_ctx* c, uint32_t* bits, int32_t* roots) {
 
 mc3_status mc3_timing_enable(mc3_ctx* c, int32_t on) {
   MC3_TRY(usable(c));
+  if (on < 0) return fail(c, MC3_E_ARG, "timing period must be >= 0");
   if (on && c->t_start.empty()) {
     const size_t n = 256;
     c->t_start.assign(n, nullptr);
     c->t_stop.assign(n, nullptr);
     c->t_pending.assign(n, 0);
     for (size_t i = 0; i < n; ++i) {
-      MC3_TRY(hip_ok(c, hipEventCreate(&c->t_start[i]), "timing events"));
-      MC3_TRY(hip_ok(c, hipEventCreate(&c->t_stop[i]), "timing events"));
+      // timestamps only: no system-scope cache writeback and invalidation at each record
+      MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->t_start[i], hipEventDisableSystemFence), "timing events"));
+      MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->t_stop[i], hipEventDisableSystemFence), "timing events"));
     }
   }
   if (on) {
     for (size_t i = 0; i < c->t_pending.size(); ++i) c->t_pending[i] = 0;
     c->t_total_ms = 0.0;
     c->t_count = 0;
+    c->t_every = on;
+    c->t_seen = 0;
   }
   c->timing = on != 0;
   return MC3_OK;

@@ -44,13 +44,16 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
     o.ebar = o.e_new;
     return o;
   }
+  // lane l holds nodes [l K, l K + K): node order is lane order
+  const int K = (nodes + 63) >> 6;
+  const int v0 = lane * K, v1 = min(v0 + K, nodes);
   double emin = __longlong_as_double(0x7FF0000000000000ll);
-  for (int v = lane; v < nodes; v += 64) emin = En[v] < emin ? En[v] : emin;
+  for (int v = v0; v < v1; ++v) emin = En[v] < emin ? En[v] : emin;
   emin = wave_min(emin);
   double lmax = 0.0;
   if (prior) {
     lmax = __longlong_as_double(0xFFF0000000000000ll);
-    for (int v = lane; v < nodes; v += 64) {
+    for (int v = v0; v < v1; ++v) {
       const double l = -(beta * (En[v] - emin)) + prior[v];
       lmax = l > lmax ? l : lmax;
     }
@@ -59,7 +62,7 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
   // fixed-point weights, their total, and the weighted energy
   unsigned long long wq = 0ull;
   double num = 0.0, den = 0.0;
-  for (int v = lane; v < nodes; v += 64) {
+  for (int v = v0; v < v1; ++v) {
     const double E = En[v];
     const double w = prior ? exp_weight((-(beta * (E - emin)) + prior[v]) - lmax) : exp_weight(-(beta * (E - emin)));
     const unsigned long long q = (unsigned long long)(w * 0x1.0p52);
@@ -68,7 +71,8 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
     num += w * E;
     den += w;
   }
-  const unsigned long long Wq = wave_sum_u64(wq);
+  const unsigned long long S = wave_scan_u64(wq, lane);   // Q at the lane's last node
+  const unsigned long long Wq = readlane_u64(S, 63);
   num = wave_sum(num);
   den = wave_sum(den);
   o.ebar = num / den;
@@ -76,30 +80,31 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
   const unsigned long long lo = (unsigned long long)u53 * Wq;
   const unsigned long long hi = __umul64hi((unsigned long long)u53, Wq);
   const unsigned long long t = (hi << 11) | (lo >> 53);
-  // inclusive prefix sums in node order; first node with Q_v > t
-  unsigned long long carry = 0ull;
-  int vstar = -1;
-  unsigned long long qv = 0ull, Qv = 0ull;
-  for (int base = 0; base < nodes; base += 64) {
-    const int v = base + lane;
-    const unsigned long long q = (v < nodes) ? Qn[v] : 0ull;
-    const unsigned long long Q = carry + wave_scan_u64(q, lane);
-    const unsigned long long hit = __ballot(v < nodes && Q > t);
-    if (hit) {
-      const int first = __ffsll((long long)hit) - 1;
-      vstar = base + first;
-      qv = __shfl(q, first);
-      Qv = __shfl(Q, first);
-      break;
+  // inclusive prefix sums Q_v in node order; the first node with Q_v > t lies in the
+  // first lane that finds one among its own nodes
+  unsigned long long Q = S - wq;
+  int vhit = -1;
+  unsigned long long qh = 0ull, Qh = 0ull;
+  for (int v = v0; v < v1; ++v) {
+    const unsigned long long q = Qn[v];
+    Q += q;
+    if (vhit < 0 && Q > t) {
+      vhit = v;
+      qh = q;
+      Qh = Q;
     }
-    carry = __shfl(Q, 63);
   }
-  if (vstar < 0) {
+  const unsigned long long hit = __ballot(vhit >= 0);
+  int vstar;
+  if (hit == 0ull) {
     // unreachable for finite energies (the minimum-energy node has q = 2^52 > 0);
     // stay put and report a zero margin rather than index outside the graph
     vstar = r;
     o.margin = 0.0;
   } else {
+    const int first = __ffsll((long long)hit) - 1;
+    vstar = __builtin_amdgcn_readlane(vhit, first);
+    const unsigned long long qv = readlane_u64(qh, first), Qv = readlane_u64(Qh, first);
     const unsigned long long d1 = t - (Qv - qv), d2 = Qv - t;
     o.margin = (double)(d1 < d2 ? d1 : d2) / (double)Wq;
   }

@@ -268,8 +268,9 @@ class Context:
         self._check(lib().mc3_read_means(self.h, first, n, out.ctypes.data), "mc3_read_means")
         return out
 
-    def timing_enable(self, on: bool = True):
-        self._check(lib().mc3_timing_enable(self.h, 1 if on else 0), "mc3_timing_enable")
+    def timing_enable(self, on: bool = True, every: int = 1):
+        """Time every `every`-th scoring launch while on (mc3_timing_enable)."""
+        self._check(lib().mc3_timing_enable(self.h, int(every) if on else 0), "mc3_timing_enable")
 
     def timing_read(self):
         ms, n = ctypes.c_double(), ctypes.c_int64()

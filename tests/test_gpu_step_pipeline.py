@@ -1,13 +1,12 @@
-"""mc3_step_n (flip sets drawn ahead, and the selection of step t-1 taken inside the
-scoring launch of step t where the shape allows) against the single-step calls
-(mc3_propose / mc3_score_candidates / mc3_select) and the oracle.
+"""mc3_step_n (flip sets drawn up to 16 steps ahead into a ring, one scoring and one
+selection launch per step, the selection forming the next step's base words) against
+the single-step calls (mc3_propose / mc3_score_candidates / mc3_select) and the oracle.
 
 Both paths read the same partial sums in the same order and apply the same rule, so
-their records, states and counters agree bit for bit.  The shapes put one chain in a
-tile, many chains in one tile, chains straddling tile edges, chains spanning several
-tiles, a node count whose weights leave room for only two selecting waves, a tree, the
-line law, and a shape with too many chains per tile, which keeps the selection
-launch.
+their records, states, means and counters agree bit for bit.  The shapes cover one
+chain in a scoring tile, many chains in one tile, chains straddling tile edges, chains
+spanning several tiles of each width, a tree, the line law and Metropolis; each run is
+split over two mc3_step_n calls.
 """
 import numpy as np
 import pytest
@@ -20,13 +19,13 @@ pytestmark = pytest.mark.gpu
 # (N, M, chains, kmax, rule, arity, law, oracle): arity 0 = the star
 CASES = [
     (40, 1, 20, 2, "metropolis", 0, "uniform", True),    # 20 chains in one 128-column tile
-    (64, 1, 32, 3, "mcmcmc", 0, "uniform", True),        # the per-tile cap exactly
+    (64, 1, 32, 3, "mcmcmc", 0, "uniform", True),        # 32 chains of two nodes
     (300, 120, 9, 16, "mcmcmc", 0, "uniform", True),     # 256-column tiles, chains straddle edges
     (256, 600, 3, 8, "mcmcmc", 0, "uniform", False),     # each chain spans 3-4 tiles
-    (160, 1500, 2, 4, "mcmcmc", 0, "uniform", False),    # 512-column tiles, two selecting waves
+    (160, 1500, 2, 4, "mcmcmc", 0, "uniform", False),    # 512-column tiles, 1501 nodes
     (200, 62, 10, 4, "mcmcmc", 2, "uniform", True),      # binary tree
     (128, 40, 8, 3, "mcmcmc", 1, "line", True),          # line graph, binomial root, log-prior
-    (96, 1, 200, 2, "metropolis", 0, "uniform", False),  # 200 chains per tile: separate launch
+    (96, 1, 200, 2, "metropolis", 0, "uniform", False),  # 200 chains per tile
 ]
 
 
@@ -48,12 +47,12 @@ def _need_gpu():
 
 
 @pytest.mark.parametrize("N,M,chains,kmax,rule,arity,law,with_oracle", CASES)
-def test_select_in_scoring_matches_separate_launch(N, M, chains, kmax, rule, arity, law, with_oracle):
+def test_step_n_matches_single_step_calls(N, M, chains, kmax, rule, arity, law, with_oracle):
     steps, seed = 24, 41
     beta = 1.3
-    announce(f"select in scoring N={N} M={M} chains={chains} {rule} arity={arity} {law}")
+    announce(f"step_n vs single steps N={N} M={M} chains={chains} {rule} arity={arity} {law}")
     J, scale = inputs.couplings_gauss(N, 900 + N + M)
-    # one step_n call per half, so that the counters must be back at zero between calls
+    # one step_n call per half: the second starts from the first's carried state
     a = _ctx(N, M, chains, kmax, rule, arity, law, J, scale, steps, seed)
     a.step_n(0, steps // 2, beta, beta, 1)
     a.step_n(steps // 2, steps - steps // 2, beta, beta, 1)
@@ -80,11 +79,11 @@ def test_select_in_scoring_matches_separate_launch(N, M, chains, kmax, rule, ari
     b.close()
 
 
-def test_select_in_scoring_headline_shape_repeatable():
-    """Headline shape (N=1024, 256 chains x M=128): two runs of 20 steps through the
-    one-launch step agree bit for bit, and agree with the separate launches."""
+def test_step_n_headline_shape_repeatable():
+    """Headline shape (N=1024, 256 chains x M=128): two runs of 20 steps of mc3_step_n
+    agree bit for bit, and agree with the single-step calls."""
     N, M, chains, steps = 1024, 128, 256, 20
-    announce("select in scoring headline shape")
+    announce("step_n headline shape")
     J, scale = inputs.couplings_gauss(N, 0x5EED0003)
     runs = []
     for rep in range(2):
@@ -108,3 +107,23 @@ def test_select_in_scoring_headline_shape_repeatable():
         for f in ("r", "vstar", "e_cur", "e_bar", "margin", "flags"):
             assert np.array_equal(rec[f], runs[0][0][f]), f
         assert np.array_equal(s, runs[0][1])
+
+
+def test_timing_every_kth_launch():
+    """mc3_timing_enable(k): events around the first and then every k-th scoring
+    launch; k < 0 is an argument error."""
+    N, M, chains = 256, 16, 8
+    J, scale = inputs.couplings_gauss(N, 77)
+    cfg = native.make_config(N, M, chains, 1, 4, precision="split_bf16", seed=1)
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    for every, steps, expect in ((1, 5, 5), (4, 10, 3), (16, 16, 1), (16, 17, 2)):
+        ctx.timing_enable(True, every=every)
+        ctx.step_n(0, steps, 1.0, 1.0, 1)
+        ms, launches = ctx.timing_read()
+        assert launches == expect, (every, steps)
+        assert ms > 0.0
+    ctx.timing_enable(False)
+    assert native.lib().mc3_timing_enable(ctx.h, -1) == native.MC3_E_ARG
+    ctx.close()
