@@ -52,76 +52,140 @@ __device__ __forceinline__ int root_of(Key key, uint32_t gc, uint32_t step, int 
   return k;
 }
 
+// One insertion of Floyd's k-of-N: t = randint(word, j+1), then t if it is not in the
+// set yet, else j (never in the set before this insertion).  The words of t and j are
+// read together, and the chosen one is written back with its bit set.
+__device__ __forceinline__ void floyd_insert(uint32_t* set, uint32_t word, uint32_t j) {
+  const uint32_t t = randint(word, j + 1u);
+  const uint32_t wt = set[t >> 5], wj = set[j >> 5];
+  const bool taken = ((wt >> site_bit(t & 31u)) & 1u) != 0u;
+  const uint32_t pos = taken ? j : t;
+  set[pos >> 5] = (taken ? wj : wt) | (1u << site_bit(pos & 31u));
+}
+
 // Floyd's k-of-N draw of the flip set of edge e into the bitset `set` (all zero on
 // entry): k_e = kmin + randint(word 0, kmax-kmin+1), then for idx = 0..k-1 a
-// uniform t in [0, N-k+idx], taking N-k+idx instead when t is already in the set.
+// uniform t in [0, N-k+idx] from word idx+1, taking N-k+idx instead when t is already
+// in the set.  Words 1..3 are the rest of block 0; block b >= 1 holds words 4b..4b+3.
 __device__ __forceinline__ void draw_flip_set(uint32_t* set, Key key, uint32_t gc, uint32_t step, uint32_t e, int N,
                                               int kmin, int kmax) {
   uint4 blk = stream_block(key, kTagEdge, gc, step, e, 0u);
   const int k = kmin + (int)randint(blk.x, (uint32_t)(kmax - kmin + 1));
-  for (int idx = 0; idx < k; ++idx) {
-    const uint32_t n = 1u + (uint32_t)idx;
-    if ((n & 3u) == 0u) blk = stream_block(key, kTagEdge, gc, step, e, n >> 2);
-    const uint32_t j = (uint32_t)(N - k + idx);
-    const uint32_t t = randint(pick(blk, n & 3u), j + 1u);
-    const uint32_t bt = set[t >> 5] >> site_bit(t & 31u) & 1u;
-    const uint32_t pos = bt ? j : t;
-    set[pos >> 5] |= 1u << site_bit(pos & 31u);
+  const uint32_t j0 = (uint32_t)(N - k);
+  floyd_insert(set, blk.y, j0);   // k >= 1
+  if (k > 1) floyd_insert(set, blk.z, j0 + 1u);
+  if (k > 2) floyd_insert(set, blk.w, j0 + 2u);
+  for (int idx = 3; idx < k; idx += 4) {
+    blk = stream_block(key, kTagEdge, gc, step, e, (uint32_t)(idx + 1) >> 2);
+    floyd_insert(set, blk.x, j0 + (uint32_t)idx);
+    if (idx + 1 < k) floyd_insert(set, blk.y, j0 + (uint32_t)idx + 1u);
+    if (idx + 2 < k) floyd_insert(set, blk.z, j0 + (uint32_t)idx + 2u);
+    if (idx + 3 < k) floyd_insert(set, blk.w, j0 + (uint32_t)idx + 3u);
   }
+}
+
+// The flip-set size k_e of edge e (word 0 of its stream).
+__device__ __forceinline__ int flip_count(Key key, uint32_t gc, uint32_t step, uint32_t e, int kmin, int kmax) {
+  const uint4 blk = stream_block(key, kTagEdge, gc, step, e, 0u);
+  return kmin + (int)randint(blk.x, (uint32_t)(kmax - kmin + 1));
 }
 
 // Flip sets and roots do not depend on the chains' states, so several steps are
 // drawn in one launch: grid (proposal blocks, steps), step = step0 + blockIdx.y, its
-// results in ring slot step % nslots.  One thread per (chain, node v = 1..M) of one
-// instance (block table) forms the path set P(v): the XOR of the flip sets of the
-// edges from node 0 down to v (edge u joins node u to its parent), each drawn by
-// Floyd into the thread's LDS scratch row and folded into its accumulator row (for
-// the star the path is the one edge and the two rows are one).  Rows have stride
-// `stride` >= W words (W+1 where it fits, so the final copy does not collide on
-// banks); every word goes to flipsT[w][chain*M + v-1] (consecutive threads,
-// consecutive addresses).  Thread (chain, node 1) stores the chain's root in
-// roots_ring[slot][global chain].  With write_base, for the first step only, the
-// thread of node r (node 1 if r = 0) also writes base = s ^ P(r) from the chain's
-// current spins.  Dynamic LDS: rows * blockDim.x * stride words.
+// results in ring slot step % nslots.  Each (chain, node v = 1..M) of one instance
+// (block table) gets the path set P(v): the XOR of the flip sets of the edges from
+// node 0 down to v (edge u joins node u to its parent), each drawn by Floyd into an
+// LDS scratch row and folded into an accumulator row (for the star the path is the
+// one edge and the two rows are one).  A wave runs as long as its longest draw, so the
+// block first orders its paths by their number of insertions (the sum of k_u along
+// the path, in 16 buckets of 1/16 of the largest possible sum, kmax times the depth of
+// node M; ties in any order): thread i draws the path of rank i into row i.  Then thread i writes the path of its own column, (chain, v) =
+// edge0 + i, from the row that holds it: every word to flipsT[w][chain*M + v-1]
+// (consecutive threads, consecutive addresses).  Rows have stride `stride` >= W
+// words (W+1 where it fits, against bank collisions).  The thread of node 1 stores the
+// chain's root in roots_ring[slot][global chain].  With write_base, for the first step
+// only, the thread of node r (node 1 if r = 0) also writes base = s ^ P(r) from the
+// chain's current spins.  Dynamic LDS: rows * blockDim.x * stride words.
 __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts, const PBlock* __restrict__ blocks,
                           int32_t* __restrict__ roots_ring, int total_chains, uint32_t nslots, int write_base,
                           int stride, int rows, int metropolis, Key key, uint32_t chain_base, uint32_t step0) {
   extern __shared__ uint32_t lds_bits[];
-  const int T = blockDim.x;
+  __shared__ int bucket_n[16], bucket_at[16];
+  __shared__ int order[256];
+  const int T = blockDim.x, tid = threadIdx.x;
   const uint32_t step = step0 + blockIdx.y;
   const uint32_t slot = step % nslots;
   const PBlock blk0 = blocks[blockIdx.x];
   const Inst& in = insts[blk0.inst];
   const int N = in.N, M = in.M, W = in.W, Bp = in.Bp;
   const long long total = (long long)in.chains * M;
-  for (int i = threadIdx.x; i < rows * T * stride; i += T) lds_bits[i] = 0u;
+  const bool star = in.arity >= M;
+  for (int i = tid; i < rows * T * stride; i += T) lds_bits[i] = 0u;
+  if (tid < 16) bucket_n[tid] = 0;
   __syncthreads();
-  const long long g = (long long)blk0.edge0 + threadIdx.x;
-  if (g >= total) return;
-  const int c = (int)(g / M);
-  const uint32_t e = (uint32_t)(g % M) + 1u;
+  // 1. rank of this thread's own path by its number of insertions
+  const long long g = (long long)blk0.edge0 + tid;
+  const bool real = g < total;
+  const int c = real ? (int)(g / M) : 0;
+  const uint32_t e = real ? (uint32_t)(g % M) + 1u : 0u;
   const uint32_t gc = chain_base + (uint32_t)(in.chain0 + c);
-  uint32_t* mine = lds_bits + (size_t)threadIdx.x * stride;
-  if (in.arity >= M) {
-    draw_flip_set(mine, key, gc, step, e, N, in.kmin, in.kmax);
-  } else {
-    uint32_t* tmp = lds_bits + (size_t)(T + threadIdx.x) * stride;
-    for (uint32_t u = e; u >= 1u; u = (u - 1u) / (uint32_t)in.arity) {
-      draw_flip_set(tmp, key, gc, step, u, N, in.kmin, in.kmax);
-      for (int w = 0; w < W; ++w) {
-        mine[w] ^= tmp[w];
-        tmp[w] = 0u;
+  int work = 0;
+  if (real)
+    for (uint32_t u = e; u >= 1u; u = star ? 0u : (u - 1u) / (uint32_t)in.arity)
+      work += flip_count(key, gc, step, u, in.kmin, in.kmax);
+  int depth = 1;   // edges on the longest path from node 0 (that of node M)
+  if (!star) {
+    depth = 0;
+    for (uint32_t u = (uint32_t)M; u >= 1u; u = (u - 1u) / (uint32_t)in.arity) ++depth;
+  }
+  const int bucket = min(15, (int)(((long long)work * 16) / ((long long)in.kmax * depth + 1)));
+  const int within = atomicAdd(&bucket_n[bucket], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b < 16; ++b) {
+      bucket_at[b] = acc;
+      acc += bucket_n[b];
+    }
+  }
+  __syncthreads();
+  const int rank = bucket_at[bucket] + within;
+  order[rank] = tid;
+  __syncthreads();
+  // 2. draw the path of rank tid into row tid
+  {
+    const long long gd = (long long)blk0.edge0 + order[tid];
+    if (gd < total) {
+      const int cd = (int)(gd / M);
+      const uint32_t ed = (uint32_t)(gd % M) + 1u;
+      const uint32_t gcd = chain_base + (uint32_t)(in.chain0 + cd);
+      uint32_t* mine = lds_bits + (size_t)tid * stride;
+      if (star) {
+        draw_flip_set(mine, key, gcd, step, ed, N, in.kmin, in.kmax);
+      } else {
+        uint32_t* tmp = lds_bits + (size_t)(T + tid) * stride;
+        for (uint32_t u = ed; u >= 1u; u = (u - 1u) / (uint32_t)in.arity) {
+          draw_flip_set(tmp, key, gcd, step, u, N, in.kmin, in.kmax);
+          for (int w = 0; w < W; ++w) {
+            mine[w] ^= tmp[w];
+            tmp[w] = 0u;
+          }
+        }
       }
     }
   }
+  __syncthreads();
+  // 3. this thread's own column, from row `rank`
+  if (!real) return;
+  const uint32_t* path = lds_bits + (size_t)rank * stride;
   const int r = root_of(key, gc, step, M, metropolis, in.law);
   if (e == 1u) roots_ring[(size_t)slot * total_chains + in.chain0 + c] = (int32_t)r;
   uint32_t* flipsT = flips_at(ws, in, slot);
-  for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = mine[w];
+  for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = path[w];
   if (write_base && blockIdx.y == 0 && (int)e == (r == 0 ? 1 : r)) {
     uint32_t* base = ws_at<uint32_t>(ws, in.base[step & 1u]);
     const uint32_t* spins = ws_at<const uint32_t>(ws, in.spins);
-    for (int w = 0; w < W; ++w) base[(size_t)c * W + w] = spins[(size_t)c * W + w] ^ (r ? mine[w] : 0u);
+    for (int w = 0; w < W; ++w) base[(size_t)c * W + w] = spins[(size_t)c * W + w] ^ (r ? path[w] : 0u);
   }
 }
 
