@@ -415,8 +415,8 @@ def _cpu_baseline(w, J, scale, sample_chains):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="sk_n1024_m128_split")
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--thermalize-steps", type=int, default=20000)
