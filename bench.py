@@ -327,12 +327,17 @@ def _precision_report(w, J, scale, step=3):
         ctx.close()
     rel = np.abs(E["split_bf16"] - E["fp64"]) / np.maximum(np.abs(E["fp64"]), 1e-300)
     d = np.abs(E["split_bf16"] - E["fp64"])
+    # differences between nodes of one chain (what the weights see): E_v - E of the chain's first column
+    ds, d64 = (E[p].reshape(w.chains, w.M) for p in ("split_bf16", "fp64"))
+    dd = np.abs((ds - ds[:, :1]) - (d64 - d64[:, :1]))[:, 1:]
     return {"candidates": int(rel.size), "rel_max": float(rel.max()), "rel_p9999": float(np.quantile(rel, 0.9999)),
             "rel_mean": float(rel.mean()), "abs_max": float(d.max()), "abs_p9999": float(np.quantile(d, 0.9999)),
             "abs_mean": float(d.mean()), "energy_abs_mean": float(np.abs(E["fp64"]).mean()),
+            "node_difference_abs_max": float(dd.max()), "node_difference_abs_p9999": float(np.quantile(dd, 0.9999)),
+            "node_difference_abs_mean": float(dd.mean()),
             "reference": "FP64 matrix-core scoring of the same candidates",
             "note": "relative errors peak at candidates with energies near zero; the absolute error is the "
-                    "FP32 accumulation's"}
+                    "FP32 accumulation's; node differences are E_v - E_0 within each chain"}
 
 
 def _anneal_thermalize(T):
@@ -402,14 +407,38 @@ def _large_thermalize(T):
     return out
 
 
-def _cpu_baseline(w, J, scale, sample_chains):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(w, J, scale, sample_chains, threads):
+    """The oracle as it stands on the host's cores: one step of `sample_chains` chains
+    of the workload, split over `threads` threads (each a disjoint chain range with its
+    own chain_base, so the chains are the ones the GPU runs; the oracle's C code
+    releases the interpreter lock while it runs)."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(threads, sample_chains))
+    bounds = [(sample_chains * i) // threads for i in range(threads + 1)]
+
+    def part(i):
+        lo, hi = bounds[i], bounds[i + 1]
+        oracle.run(J, scale, w.N, w.M, hi - lo, w.kmin, w.kmax, w.seed, [w.beta0], chain_base=lo)
+
     t0 = time.perf_counter()
-    oracle.run(J, scale, w.N, w.M, sample_chains, w.kmin, w.kmax, w.seed, [w.beta0])
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        list(pool.map(part, range(threads)))
     dt = time.perf_counter() - t0
-    return {"value": sample_chains * w.M / dt, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+    return {"value": sample_chains * w.M / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
             "sample": f"1 step of {sample_chains} chains (x{w.M} candidates; plain pair-sum energies of all "
-                      f"{w.M + 1} nodes) of the same workload, {dt:.1f} s on 1 core"}
+                      f"{w.M + 1} nodes) of the same workload, {dt:.1f} s wall on {threads} threads",
+            "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -420,7 +449,9 @@ def main():
     ap.add_argument("--workload", default="sk_n1024_m128_split")
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--thermalize-steps", type=int, default=20000)
-    ap.add_argument("--cpu-chains", type=int, default=160)
+    ap.add_argument("--cpu-chains", type=int, default=320)
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="oracle threads for the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--anneal-steps", type=int, default=100000)
     ap.add_argument("--large-thermalize-steps", type=int, default=0,
                     help="steps of the N=8192 anneal study (0 skips it; 20000 is the workload's schedule)")
@@ -496,7 +527,8 @@ def main():
                       "achieved_tflops": achieved64, "peak_tflops": PEAK_FP64_TFLOPS,
                       "frac": achieved64 / PEAK_FP64_TFLOPS},
         "split_vs_fp64": fp64_ms_step / ms_step,
-        "selection": {"moves": split["moves"], "near_ties": split["near_ties"]},
+        "selection": {"moves": split["moves"], "near_ties": split["near_ties"],
+                      "near_ties_per_1e4_chain_steps": split["near_ties"] * 1e4 / ((args.warmup + args.steps) * w.chains)},
     }
     out["precision_split_vs_fp64"] = {"headline": _precision_report(w, J, scale)}
     if args.thermalize_steps > 0:
@@ -522,7 +554,8 @@ def main():
     if other:
         out["other_workloads"] = other
     if not args.no_cpu:
-        out["cpu_baseline"] = _cpu_baseline(w, J, scale, args.cpu_chains)
+        out["cpu_baseline"] = _cpu_baseline(w, J, scale, args.cpu_chains,
+                                            min(args.cpu_threads, os.cpu_count() or 1))
         _log("cpu baseline done")
     print(json.dumps(out))
 
