@@ -96,10 +96,24 @@ typedef enum {
  *            words sends addition j left) and P_gen(T|c_v) carries C(M, v) / 2^M
  *            (the reading of the garbled prefactor); node weights
  *            exp(-beta E_v) C(M, v), applied as the log-prior
- *            lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1). */
+ *            lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1).
+ *   TABLE:   a root law given by the caller (App. "General graph populating
+ *            process": the root distribution p_r of a tree is free), any arity: weights
+ *            g_0..g_M >= 0 per instance (law_table), taken in fixed point as
+ *            q_v = floor(g_v / S * 2^52), S = sum of g in node order; the root is
+ *            r = min { v : q_0 + .. + q_v > t }, t = floor(u53 W / 2^53) with u53 from
+ *            root-stream words 0 and 1 and W = sum q.  With flip sets that do not
+ *            depend on the state P_gen(T|c_v) is p_v times a factor common to the
+ *            nodes, so node weights are exp(-beta E_v) q_v (log-prior log q_v; q_v = 0:
+ *            never the root, never chosen).  The three-configuration process with a
+ *            general p (Sec. "Generalization to three configurations per Monte Carlo
+ *            step") is arity 1, M = 2, weights (q/2, p, q/2), q = 1 - p; the line-graph
+ *            addition process with probability p of adding at node 0's end is arity 1
+ *            with weights C(M, v) p^v q^(M-v). */
 typedef enum {
     MC3_LAW_UNIFORM = 0,
-    MC3_LAW_LINE = 1
+    MC3_LAW_LINE = 1,
+    MC3_LAW_TABLE = 2
 } mc3_graph_law;
 
 typedef enum {
@@ -125,6 +139,8 @@ typedef struct {
     int32_t scorer;          /* mc3_scorer */
     int32_t arity;           /* graph tree arity; 0 or >= M: the M-ary star */
     int32_t law;             /* mc3_graph_law */
+    const double* law_table; /* law TABLE: host [M+1] root weights, copied by mc3_create;
+                                otherwise ignored */
 } mc3_config;
 
 /* One instance of a batch: its size, graph size, chains and flip-set range, with the
@@ -151,6 +167,9 @@ typedef struct {
     int32_t scorer;          /* mc3_scorer */
     int32_t arity;           /* graph tree arity of every instance; 0 or >= M: the star */
     int32_t law;             /* mc3_graph_law */
+    const double* law_table; /* law TABLE: host root weights of every instance, instance i's
+                                M_i+1 values after those of instances 0..i-1; copied by
+                                mc3_batch_create; otherwise ignored */
 } mc3_batch_config;
 
 /* Per-step, per-chain record (40 bytes). */

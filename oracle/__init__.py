@@ -9,7 +9,8 @@ the product.  The arithmetic lives in ``mc3_oracle.c`` (plain FP64 C, compiled w
 Every function cites the passage of the paper it follows (see ``mc3_oracle.c``):
 SK energy (Sec. "The Sherrington-Kirkpatrick model"), node rule of the graph chain
 (App. "Markov chain of graphs of configurations", Eq. eq_det_balance_graph_solution),
-uniform-root populating process (App. "General graph populating process"), Metropolis
+populating process with a uniform root or a root law given as a table, and the
+line-graph addition process (App. "Generating graphs of configurations"), Metropolis
 rate (Sec. "Problem statement").
 
 Parity pins (tests/test_oracle_*.py): Philox known-answer vectors and an independent
@@ -33,7 +34,7 @@ _LIB = os.path.join(_HERE, "libmc3_oracle.so")
 
 TAG_INIT, TAG_ROOT, TAG_EDGE, TAG_SELECT = 1, 2, 3, 4
 RULE_MCMCMC, RULE_METROPOLIS = 0, 1
-LAW_UNIFORM, LAW_LINE = 0, 1
+LAW_UNIFORM, LAW_LINE, LAW_TABLE = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -56,7 +57,7 @@ class Cfg(ctypes.Structure):
                 ("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("chain_base", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("scale", ctypes.c_double), ("arity", ctypes.c_int32),
-                ("law", ctypes.c_int32)]
+                ("law", ctypes.c_int32), ("pad2", ctypes.c_int32), ("table", ctypes.POINTER(ctypes.c_double))]
 
 
 REC_DTYPE = np.dtype([("r", np.int32), ("vstar", np.int32), ("e_cur", np.float64),
@@ -91,6 +92,11 @@ def lib():
         L.mc3o_root_line.argtypes = [u64, u32, u32, i32]
         L.mc3o_root_line.restype = i32
         L.mc3o_log_prior_line.argtypes = [i32, P(dbl)]
+        L.mc3o_root_table_prepare.argtypes = [i32, P(dbl), P(u64)]
+        L.mc3o_root_table_prepare.restype = i32
+        L.mc3o_root_table.argtypes = [u64, u32, u32, i32, P(u64)]
+        L.mc3o_root_table.restype = i32
+        L.mc3o_log_prior_table.argtypes = [i32, P(u64), P(dbl)]
         L.mc3o_build_nodes.argtypes = [i32, i32, i32, i32, P(ctypes.c_int8), P(ctypes.c_uint8), P(ctypes.c_int8)]
         L.mc3o_select_mcmcmc.argtypes = [i32, P(dbl), P(dbl), dbl, u64, P(dbl), P(dbl), P(u64)]
         L.mc3o_select_mcmcmc.restype = i32
@@ -156,10 +162,32 @@ def edge_flips(seed, chain, step, edge, N, kmin, kmax):
     return int(k), m
 
 
-def root(seed, chain, step, M, law: int = LAW_UNIFORM) -> int:
-    """Root position: uniform over the M+1 nodes, or the line process's left count."""
+def root_table_cdf(table) -> np.ndarray:
+    """Fixed-point cumulative root weights Q_0..Q_M of a table law (mc3o_root_table_prepare)."""
+    g = np.ascontiguousarray(table, dtype=np.float64)
+    Q = np.zeros(len(g), dtype=np.uint64)
+    if lib().mc3o_root_table_prepare(len(g) - 1, _ptr(g, ctypes.c_double), _ptr(Q, ctypes.c_uint64)) != 0:
+        raise ValueError("root table needs nonnegative finite weights with a positive fixed-point total")
+    return Q
+
+
+def log_prior_table(table) -> np.ndarray:
+    """log q_v of a table law: the node rule's log-prior."""
+    Q = root_table_cdf(table)
+    out = np.zeros(len(Q), dtype=np.float64)
+    lib().mc3o_log_prior_table(len(Q) - 1, _ptr(Q, ctypes.c_uint64), _ptr(out, ctypes.c_double))
+    return out
+
+
+def root(seed, chain, step, M, law: int = LAW_UNIFORM, table=None) -> int:
+    """Root position: uniform over the M+1 nodes, the line process's left count, or a
+    draw from a table law."""
     if law == LAW_LINE:
         return int(lib().mc3o_root_line(seed, chain, step, M))
+    if law == LAW_TABLE:
+        Q = root_table_cdf(table)
+        assert len(Q) == M + 1
+        return int(lib().mc3o_root_table(seed, chain, step, M, _ptr(Q, ctypes.c_uint64)))
     return int(lib().mc3o_root(seed, chain, step, M))
 
 
@@ -171,11 +199,11 @@ def log_prior_line(M: int) -> np.ndarray:
 
 
 def propose_nodes(seed, chain, step, N, M, kmin, kmax, s, rule=RULE_MCMCMC, arity: Optional[int] = None,
-                  law: int = LAW_UNIFORM):
+                  law: int = LAW_UNIFORM, table=None):
     """Root and node configurations [(M+1), N] of the tree (arity a, default the star
     a = M) generated from s."""
     arity = M if arity is None else arity
-    r = 0 if rule == RULE_METROPOLIS else root(seed, chain, step, M, law)
+    r = 0 if rule == RULE_METROPOLIS else root(seed, chain, step, M, law, table)
     flips = np.zeros((M + 1, N), dtype=np.uint8)
     for e in range(1, M + 1):
         flips[e] = edge_flips(seed, chain, step, e, N, kmin, kmax)[1]
@@ -206,7 +234,7 @@ def accept_metropolis(e_cur: float, e_new: float, beta: float, u53_value: int):
 def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kmax: int, seed: int,
         betas, spins: Optional[np.ndarray] = None, step0: int = 0, rule: int = RULE_MCMCMC,
         chain_base: int = 0, want_node_e: bool = False, forced: Optional[np.ndarray] = None,
-        arity: Optional[int] = None, law: int = LAW_UNIFORM):
+        arity: Optional[int] = None, law: int = LAW_UNIFORM, table=None):
     """Run len(betas) steps.  Returns dict(spins, e_cur, rec[, node_e]).
 
     Initial spins default to the INIT stream of each chain; energies are recomputed
@@ -224,7 +252,12 @@ def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kma
     if forced is not None:
         f = np.ascontiguousarray(forced, dtype=np.int32)
         assert f.shape == (nsteps, chains)
-    cfg = Cfg(N, M, chains, kmin, kmax, rule, chain_base, 0, seed, scale, M if arity is None else arity, law)
+    tab = None
+    if law == LAW_TABLE:
+        tab = np.ascontiguousarray(table, dtype=np.float64)
+        assert tab.shape == (M + 1,)
+    cfg = Cfg(N, M, chains, kmin, kmax, rule, chain_base, 0, seed, scale, M if arity is None else arity, law, 0,
+              None if tab is None else _ptr(tab, ctypes.c_double))
     rc = lib().mc3o_run(ctypes.byref(cfg), _ptr(J, ctypes.c_double), _ptr(spins, ctypes.c_int8),
                         _ptr(e_cur, ctypes.c_double), step0, nsteps, _ptr(betas, ctypes.c_double),
                         rec.ctypes.data, None if node_e is None else node_e.ctypes.data,

@@ -33,6 +33,14 @@
  *    P_gen(T|c_v) carries the factor C(M, v) / 2^M (the printed prefactor is
  *    garbled; C(L-1, k) / 2^(L-1) with L = M+1 nodes is the reading taken), which
  *    enters the node rule as the log-prior log C(M, v).
+ *  - A general root law, App. "General graph populating process" (the root
+ *    distribution p_r is free; with a symmetric two-body law P_gen(T|c_v) is then
+ *    p_v times a product common to all nodes): the caller gives weights g_v, the root
+ *    is drawn from them in fixed point and the node rule carries log p_v.  The
+ *    three-configuration process of Sec. "Generalization to three configurations per
+ *    Monte Carlo step" with a general p is the line of three nodes with root weights
+ *    (q/2, p, q/2), q = 1 - p, and the line-graph addition process with a bias p
+ *    toward node 0 is the line with weights C(M, v) p^v q^(M-v).
  *  - Standard MCMC with the Metropolis rate min(1, ratio), Sec. "Problem statement",
  *    for the single-update baseline (rule METROPOLIS, M = 1).
  *  - Observables as node-weighted averages over the graph, Eq. eq_monte_carlo_graph.
@@ -230,6 +238,50 @@ int mc3o_root_line(uint64_t seed, uint32_t chain, uint32_t step, int M)
     return k;
 }
 
+/* A root law given by weights g_v >= 0 (v = 0..M), in fixed point: S = sum of g in
+ * node order, q_v = floor(g_v / S * 2^52), and Q_v = q_0 + ... + q_v (written to
+ * Qcum), so node v is the root with probability q_v / Q_M.  Returns -1 when a weight
+ * is negative or not finite, or when every q_v is 0. */
+int mc3o_root_table_prepare(int M, const double* g, uint64_t* Qcum)
+{
+    double S = 0.0;
+    for (int v = 0; v <= M; ++v) {
+        if (!(g[v] >= 0.0) || g[v] == INFINITY) return -1;
+        S += g[v];
+    }
+    if (!(S > 0.0) || S == INFINITY) return -1;
+    uint64_t acc = 0;
+    for (int v = 0; v <= M; ++v) {
+        acc += (uint64_t)floor(g[v] / S * 0x1.0p52);
+        Qcum[v] = acc;
+    }
+    return acc > 0 ? 0 : -1;
+}
+
+/* Root position under a table law: u53 from ROOT words 0 and 1, threshold
+ * t = floor(u53 W / 2^53) with W = Q_M, root = min { v : Q_v > t }. */
+int mc3o_root_table(uint64_t seed, uint32_t chain, uint32_t step, int M, const uint64_t* Qcum)
+{
+    uint32_t w0 = mc3o_word(seed, TAG_ROOT, chain, step, 0u, 0u);
+    uint32_t w1 = mc3o_word(seed, TAG_ROOT, chain, step, 0u, 1u);
+    uint64_t u53 = mc3o_u53(w0, w1);
+    unsigned __int128 prod = (unsigned __int128)u53 * (unsigned __int128)Qcum[M];
+    uint64_t t = (uint64_t)(prod >> 53);
+    int r = 0;
+    while (Qcum[r] <= t) ++r;
+    return r;
+}
+
+/* The table law's log-prior: log of the fixed-point root probability's numerator,
+ * log((double) q_v) (q_v = 0 gives -infinity: the node is never chosen). */
+void mc3o_log_prior_table(int M, const uint64_t* Qcum, double* out)
+{
+    for (int v = 0; v <= M; ++v) {
+        uint64_t q = Qcum[v] - (v ? Qcum[v - 1] : 0u);
+        out[v] = q ? log((double)q) : -INFINITY;
+    }
+}
+
 /* log C(M, v) for v = 0..M: the line process's log-prior, lgamma(M+1) - lgamma(v+1)
  * - lgamma(M-v+1) evaluated left to right. */
 void mc3o_log_prior_line(int M, double* out)
@@ -337,7 +389,9 @@ typedef struct {
     uint64_t seed;
     double scale;          /* energy scale: E = -scale * sum_{i<j} J_ij s_i s_j */
     int32_t arity;         /* tree arity (parent of v is (v-1)/arity); 0 = M (the star) */
-    int32_t law;           /* 0 = uniform root, 1 = line-graph addition process (arity 1) */
+    int32_t law;           /* 0 = uniform root, 1 = line-graph addition process (arity 1), 2 = table */
+    int32_t pad2;
+    const double* table;   /* law 2: root weights g_0..g_M */
 } mc3o_cfg;
 
 /* Run nsteps steps starting at global step step0 for every chain.
@@ -358,11 +412,22 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
     if (N < 2 || M < 1 || cfg->chains < 1 || cfg->kmin < 1 || cfg->kmax < cfg->kmin || cfg->kmax > N) return -1;
     if (cfg->rule == 1 && M != 1) return -1;
     const int arity = cfg->arity > 0 ? cfg->arity : M;
-    if (arity > M || cfg->law < 0 || cfg->law > 1 || (cfg->law == 1 && arity != 1)) return -1;
+    if (arity > M || cfg->law < 0 || cfg->law > 2 || (cfg->law == 1 && arity != 1)) return -1;
+    if (cfg->law == 2 && !cfg->table) return -1;
     double* log_prior = NULL;
+    uint64_t* Qcum = NULL;
     if (cfg->law == 1) {
         log_prior = (double*)malloc(sizeof(double) * (size_t)(M + 1));
         mc3o_log_prior_line(M, log_prior);
+    } else if (cfg->law == 2) {
+        log_prior = (double*)malloc(sizeof(double) * (size_t)(M + 1));
+        Qcum = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(M + 1));
+        if (mc3o_root_table_prepare(M, cfg->table, Qcum) != 0) {
+            free(log_prior);
+            free(Qcum);
+            return -1;
+        }
+        mc3o_log_prior_table(M, Qcum, log_prior);
     }
     uint8_t* flips = (uint8_t*)malloc((size_t)(M + 1) * N);
     int8_t* nodes = (int8_t*)malloc((size_t)(M + 1) * N);
@@ -372,8 +437,15 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
         for (int c = 0; c < cfg->chains; ++c) {
             uint32_t gc = cfg->chain_base + (uint32_t)c;
             int8_t* s = spins + (size_t)c * N;
-            int r = (cfg->rule == 1) ? 0
-                    : (cfg->law == 1 ? mc3o_root_line(cfg->seed, gc, step, M) : mc3o_root(cfg->seed, gc, step, M));
+            int r = 0;
+            if (cfg->rule != 1) {
+                if (cfg->law == 1)
+                    r = mc3o_root_line(cfg->seed, gc, step, M);
+                else if (cfg->law == 2)
+                    r = mc3o_root_table(cfg->seed, gc, step, M, Qcum);
+                else
+                    r = mc3o_root(cfg->seed, gc, step, M);
+            }
             memset(flips, 0, (size_t)N);
             for (int e = 1; e <= M; ++e)
                 mc3o_edge_flips(cfg->seed, gc, step, (uint32_t)e, N, cfg->kmin, cfg->kmax, flips + (size_t)e * N);
@@ -404,6 +476,6 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
             }
         }
     }
-    free(flips); free(nodes); free(E); free(log_prior);
+    free(flips); free(nodes); free(E); free(log_prior); free(Qcum);
     return 0;
 }

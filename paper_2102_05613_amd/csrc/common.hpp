@@ -65,7 +65,8 @@ struct Inst {
   double scale;
   uint64_t J64, Jpack, flips, flip_slot, base[2], partial, spins;
   uint64_t field;   // [chains][Np] FP64 local fields (field-update path only)
-  uint64_t prior;   // [M+1] FP64 log-prior of the nodes (line law), 0 = none
+  uint64_t prior;   // [M+1] FP64 log-prior of the nodes (line and table laws), 0 = none
+  uint64_t root_q;  // [M+1] uint64 cumulative fixed-point root weights (table law), 0 = none
 };
 
 // Flip sets of the step held in ring slot `slot` (slots of flip_slot bytes each).

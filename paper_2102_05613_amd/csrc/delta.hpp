@@ -159,7 +159,8 @@ __global__ __launch_bounds__(256) void k_step_delta(
     const uint32_t step = step0 + (uint32_t)it;
     const double beta = total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)step / (double)(total - 1));
     // 1. root and flip sets
-    if (tid == 0) sh_r = root_of(key, gc, step, M, metropolis, in.law);
+    if (tid == 0)
+      sh_r = root_of(key, gc, step, M, metropolis, in.law, in.root_q ? ws_at<const uint64_t>(ws, in.root_q) : nullptr);
     for (int e1 = tid; e1 < M; e1 += 256) {
       const uint32_t e = (uint32_t)e1 + 1u;
       uint16_t* my = sites + (size_t)e1 * kDeltaMaxK;

@@ -35,7 +35,8 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct InstH {
   mc3_instance_desc desc;
   int arity = 1;                                       // resolved: parent of v is (v-1)/arity
-  size_t prior = 0;                                    // log-prior table (line law), 0 = none
+  size_t prior = 0;                                    // log-prior table (line and table laws), 0 = none
+  size_t root_q = 0;                                   // cumulative fixed-point root weights (table law)
   int Np, W, Wn, B, Bp, NB, P, chain0, col0;
   size_t J64, Jpack, flips, base[2], partial, spins;  // byte offsets into the workspace
   size_t flip_slot;                                    // bytes of one step's flip sets
@@ -73,6 +74,24 @@ const char* validate_instance(const mc3_instance_desc& d, int rule) {
   return nullptr;
 }
 
+// The table law in fixed point: S = sum of g in node order, q_v = floor(g_v / S * 2^52),
+// Qcum[v] = q_0 + .. + q_v.  False for a negative or non-finite weight or a zero total.
+bool root_table(const double* g, int M, std::vector<uint64_t>* Qcum) {
+  double S = 0.0;
+  for (int v = 0; v <= M; ++v) {
+    if (!(g[v] >= 0.0) || g[v] == HUGE_VAL) return false;
+    S += g[v];
+  }
+  if (!(S > 0.0) || S == HUGE_VAL) return false;
+  uint64_t acc = 0;
+  if (Qcum) Qcum->resize(M + 1);
+  for (int v = 0; v <= M; ++v) {
+    acc += (uint64_t)std::floor(g[v] / S * 0x1.0p52);
+    if (Qcum) (*Qcum)[v] = acc;
+  }
+  return acc > 0;
+}
+
 const char* validate_batch(const mc3_batch_config* c) {
   if (!c) return "config is NULL";
   if (c->n_instances < 1 || c->n_instances > (1 << 20)) return "n_instances must be in [1, 2^20]";
@@ -82,16 +101,21 @@ const char* validate_batch(const mc3_batch_config* c) {
   if (c->scorer != MC3_SCORER_GEMM && c->scorer != MC3_SCORER_DELTA && c->scorer != MC3_SCORER_AUTO)
     return "unknown scorer";
   if (c->arity < 0) return "arity must be >= 0";
-  if (c->law != MC3_LAW_UNIFORM && c->law != MC3_LAW_LINE) return "unknown graph law";
+  if (c->law != MC3_LAW_UNIFORM && c->law != MC3_LAW_LINE && c->law != MC3_LAW_TABLE) return "unknown graph law";
+  if (c->law == MC3_LAW_TABLE && !c->law_table) return "law TABLE needs law_table";
   if (c->trace_steps < 0) return "trace_steps must be >= 0";
   if (c->mean_steps < 0) return "mean_steps must be >= 0";
   if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
   long long chains = 0, cols = 0;
+  size_t table_at = 0;
   for (int i = 0; i < c->n_instances; ++i) {
     if (const char* e = validate_instance(c->instances[i], c->rule)) return e;
     const int M = c->instances[i].M;
     const int a = (c->arity == 0 || c->arity > M) ? M : c->arity;
     if (c->law == MC3_LAW_LINE && a != 1) return "the line law needs arity 1";
+    if (c->law == MC3_LAW_TABLE && !root_table(c->law_table + table_at, M, nullptr))
+      return "law_table: weights must be finite and >= 0 with a positive fixed-point total per instance";
+    table_at += M + 1;
     chains += c->instances[i].chains;
     cols += (long long)c->instances[i].chains * c->instances[i].M;
   }
@@ -272,7 +296,8 @@ Plan make_plan(const mc3_batch_config& cfg) {
     h.partial = take((size_t)h.P * h.Bp * 8);
     h.spins = take((size_t)h.desc.chains * h.W * 4);
     if (pl.delta) h.field = take((size_t)h.desc.chains * h.Np * 8);
-    if (cfg.law == MC3_LAW_LINE) h.prior = take((size_t)(h.desc.M + 1) * 8);
+    if (cfg.law == MC3_LAW_LINE || cfg.law == MC3_LAW_TABLE) h.prior = take((size_t)(h.desc.M + 1) * 8);
+    if (cfg.law == MC3_LAW_TABLE) h.root_q = take((size_t)(h.desc.M + 1) * 8);
     candT = std::max(candT, (size_t)h.W * h.Bp * 4);
   }
   pl.candT = take(candT);
@@ -300,6 +325,7 @@ mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
   b.scorer = c->scorer;
   b.arity = c->arity;
   b.law = c->law;
+  b.law_table = c->law_table;
   return b;
 }
 
@@ -414,6 +440,7 @@ mc3_status upload_insts(mc3_ctx* c) {
     d.spins = h.spins;
     d.field = h.field;
     d.prior = h.prior;
+    d.root_q = h.root_q;
   }
   MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<char>(pl.insts), t.data(), t.size() * sizeof(mc3::Inst),
                                    hipMemcpyHostToDevice, c->stream), "upload instance table"));
@@ -681,16 +708,32 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
     e = up(P.units_global_off[k], P.units_global[k].data(), P.units_global[k].size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.units_local_off, P.units_local.data(), P.units_local.size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.pblocks_off, P.pblocks.data(), P.pblocks.size() * sizeof(mc3::PBlock));
-  // the line law's log-prior log C(M, v) = lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1)
+  // log-priors: the line law's log C(M, v) = lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1);
+  // the table law's log q_v (q_v = 0: -infinity) and its cumulative weights
   std::vector<std::vector<double>> priors;
+  std::vector<std::vector<uint64_t>> cdfs;
+  size_t table_at = 0;
   for (const InstH& h : P.inst) {
-    if (!h.prior || e != hipSuccess) continue;
     const int M = h.desc.M;
+    if (!h.prior || e != hipSuccess) continue;
     priors.emplace_back(M + 1);
-    for (int v = 0; v <= M; ++v)
-      priors.back()[v] = std::lgamma((double)M + 1.0) - std::lgamma((double)v + 1.0) - std::lgamma((double)(M - v) + 1.0);
-    e = up(h.prior, priors.back().data(), priors.back().size() * 8);
+    if (cfg->law == MC3_LAW_TABLE) {
+      cdfs.emplace_back();
+      root_table(cfg->law_table + table_at, M, &cdfs.back());
+      table_at += M + 1;
+      for (int v = 0; v <= M; ++v) {
+        const uint64_t q = cdfs.back()[v] - (v ? cdfs.back()[v - 1] : 0u);
+        priors.back()[v] = q ? std::log((double)q) : -HUGE_VAL;
+      }
+      e = up(h.root_q, cdfs.back().data(), cdfs.back().size() * 8);
+    } else {
+      for (int v = 0; v <= M; ++v)
+        priors.back()[v] =
+            std::lgamma((double)M + 1.0) - std::lgamma((double)v + 1.0) - std::lgamma((double)(M - v) + 1.0);
+    }
+    if (e == hipSuccess) e = up(h.prior, priors.back().data(), priors.back().size() * 8);
   }
+  c->cfg.law_table = nullptr;   // the caller's table is not kept
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess || upload_insts(c) != MC3_OK) {
     mc3_destroy(c);

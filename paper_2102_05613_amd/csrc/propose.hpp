@@ -33,12 +33,30 @@ __global__ void k_init_spins(char* __restrict__ ws, const Inst* __restrict__ ins
 // Root position r of chain gc at `step` (the node the current state sits at).
 // Uniform law: randint(ROOT word 0, M+1).  Line law: the number of the M additions
 // that went to the left end, addition j going left iff bit j%32 of ROOT word j/32 is
-// set.  0 for Metropolis.
-__device__ __forceinline__ int root_of(Key key, uint32_t gc, uint32_t step, int M, int metropolis, int law) {
+// set.  Table law: t = floor(u53 W / 2^53) (u53 from ROOT words 0 and 1, W = Q_M),
+// r = min { v : Q_v > t } over the cumulative fixed-point weights Qcum.  0 for
+// Metropolis.
+__device__ __forceinline__ int root_of(Key key, uint32_t gc, uint32_t step, int M, int metropolis, int law,
+                                       const uint64_t* __restrict__ Qcum) {
   if (metropolis) return 0;
   if (law == 0) {
     const uint4 rb = stream_block(key, kTagRoot, gc, step, 0u, 0u);
     return (int)randint(rb.x, (uint32_t)(M + 1));
+  }
+  if (law == 2) {
+    const uint4 rb = stream_block(key, kTagRoot, gc, step, 0u, 0u);
+    const unsigned long long u53 = u53_of(rb.x, rb.y), W = Qcum[M];
+    const unsigned long long lo = u53 * W, hi = __umul64hi(u53, W);
+    const unsigned long long t = (hi << 11) | (lo >> 53);
+    int a = 0, b = M;   // the first v with Qcum[v] > t lies in [a, b]
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (Qcum[mid] > t)
+        b = mid;
+      else
+        a = mid + 1;
+    }
+    return a;
   }
   int k = 0;
   for (int j0 = 0; j0 < M; j0 += 128) {
@@ -178,7 +196,8 @@ __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts,
   // 3. this thread's own column, from row `rank`
   if (!real) return;
   const uint32_t* path = lds_bits + (size_t)rank * stride;
-  const int r = root_of(key, gc, step, M, metropolis, in.law);
+  const int r = root_of(key, gc, step, M, metropolis, in.law,
+                        in.root_q ? ws_at<const uint64_t>(ws, in.root_q) : nullptr);
   if (e == 1u) roots_ring[(size_t)slot * total_chains + in.chain0 + c] = (int32_t)r;
   uint32_t* flipsT = flips_at(ws, in, slot);
   for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = path[w];

@@ -19,12 +19,12 @@ MC3_E_UNSUPPORTED, MC3_E_NUMERIC, MC3_E_WORKSPACE = -5, -6, -7
 MC3_FP64, MC3_SPLIT_BF16 = 0, 1
 MC3_RULE_MCMCMC, MC3_RULE_METROPOLIS = 0, 1
 MC3_SCORER_GEMM, MC3_SCORER_DELTA, MC3_SCORER_AUTO = 0, 1, 2
-MC3_LAW_UNIFORM, MC3_LAW_LINE = 0, 1
+MC3_LAW_UNIFORM, MC3_LAW_LINE, MC3_LAW_TABLE = 0, 1, 2
 
 PRECISIONS = {"fp64": MC3_FP64, "split_bf16": MC3_SPLIT_BF16}
 RULES = {"mcmcmc": MC3_RULE_MCMCMC, "metropolis": MC3_RULE_METROPOLIS}
 SCORERS = {"gemm": MC3_SCORER_GEMM, "delta": MC3_SCORER_DELTA, "auto": MC3_SCORER_AUTO}
-LAWS = {"uniform": MC3_LAW_UNIFORM, "line": MC3_LAW_LINE}
+LAWS = {"uniform": MC3_LAW_UNIFORM, "line": MC3_LAW_LINE, "table": MC3_LAW_TABLE}
 
 STATUS_NAMES = {0: "MC3_OK", -1: "MC3_E_ARG", -3: "MC3_E_DEVICE", -4: "MC3_E_STATE",
                 -5: "MC3_E_UNSUPPORTED", -6: "MC3_E_NUMERIC", -7: "MC3_E_WORKSPACE"}
@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
                 ("rule", ctypes.c_int32), ("trace_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("chain_base", ctypes.c_uint32), ("mean_steps", ctypes.c_int32),
                 ("near_tie_tol", ctypes.c_double), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
-                ("law", ctypes.c_int32)]
+                ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double))]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -57,7 +57,7 @@ class BatchConfig(ctypes.Structure):
                 ("trace_steps", ctypes.c_int32), ("mean_steps", ctypes.c_int32), ("chain_base", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("near_tie_tol", ctypes.c_double),
                 ("instances", ctypes.POINTER(InstanceDesc)), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
-                ("law", ctypes.c_int32)]
+                ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double))]
 
 
 class Summary(ctypes.Structure):
@@ -125,20 +125,36 @@ def lib() -> ctypes.CDLL:
 def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: str = "split_bf16",
                 rule: str = "mcmcmc", trace_steps: int = 0, seed: int = 0, chain_base: int = 0,
                 near_tie_tol: float = -1.0, mean_steps: int = 0, scorer: str = "gemm", arity: int = 0,
-                law: str = "uniform") -> Config:
-    """arity 0: the M-ary star; law "line" (arity 1): the line-graph addition process."""
-    return Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base,
-                  mean_steps, near_tie_tol, SCORERS[scorer], arity, LAWS[law])
+                law: str = "uniform", law_table=None) -> Config:
+    """arity 0: the M-ary star; law "line" (arity 1): the line-graph addition process;
+    law "table": root weights law_table[0..M]."""
+    tab = _table(law_table)
+    cfg = Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base,
+                 mean_steps, near_tie_tol, SCORERS[scorer], arity, LAWS[law],
+                 None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    cfg._keep_table = tab   # the table lives as long as the config
+    return cfg
+
+
+def _table(law_table):
+    if law_table is None:
+        return None
+    return np.ascontiguousarray(law_table, dtype=np.float64).ravel().copy()
 
 
 def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcmcmc", trace_steps: int = 0,
                       seed: int = 0, chain_base: int = 0, near_tie_tol: float = -1.0,
-                      mean_steps: int = 0, scorer: str = "gemm", arity: int = 0, law: str = "uniform") -> BatchConfig:
-    """instances: sequence of (N, M, chains, kmin, kmax)."""
+                      mean_steps: int = 0, scorer: str = "gemm", arity: int = 0, law: str = "uniform",
+                      law_table=None) -> BatchConfig:
+    """instances: sequence of (N, M, chains, kmin, kmax); law "table": law_table holds
+    the root weights of every instance, M_i+1 values each, in instance order."""
     arr = (InstanceDesc * len(instances))(*[InstanceDesc(*map(int, d)) for d in instances])
+    tab = _table(law_table)
     cfg = BatchConfig(len(instances), PRECISIONS[precision], RULES[rule], trace_steps, mean_steps, chain_base, seed,
-                      near_tie_tol, ctypes.cast(arr, ctypes.POINTER(InstanceDesc)), SCORERS[scorer], arity, LAWS[law])
+                      near_tie_tol, ctypes.cast(arr, ctypes.POINTER(InstanceDesc)), SCORERS[scorer], arity, LAWS[law],
+                      None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     cfg._keep = arr   # the descriptor array lives as long as the config
+    cfg._keep_table = tab
     return cfg
 
 

@@ -160,17 +160,20 @@ def tree_parent(v: int, arity: int) -> int:
 
 
 def tree_kernel(E: np.ndarray, beta: float, N: int, M: int, arity: int, kmin: int, kmax: int,
-                law: str = "uniform", prior: str = "none") -> np.ndarray:
+                law: str = "uniform", prior: str = "none", table=None) -> np.ndarray:
     """Exact transition matrix of one MCMCMC step on the tree with M+1 nodes
     (breadth-first labelling, parent(v) = (v-1) // arity), every edge populated with an
     independent flip set, over all root positions and all flip-set realisations.
 
     law "uniform": the current state sits at node r ~ U{0..M} (populating process
     with a uniform root).  law "line" (arity 1): r ~ Binomial(M, 1/2), the position of
-    the starting node after M additions at either end of a line.
+    the starting node after M additions at either end of a line.  law "table":
+    P(r = v) = table[v] / sum(table), any arity (the populating process with a free
+    root law).
     prior: "none" (weights exp(-beta E_v)), "comb" (times C(M, v), the line process's
     generation probability of the graph from node v), or "printed" (times C(M+1, v),
-    the printed form) -- the last two for the line law.
+    the printed form) -- the last two for the line law -- or "table" (times table[v],
+    the table law's generation probability of the graph from node v).
     Node v's configuration is the current state with the flip sets of every edge on
     the path from r to v flipped."""
     S = 2 ** N
@@ -187,12 +190,17 @@ def tree_kernel(E: np.ndarray, beta: float, N: int, M: int, arity: int, kmin: in
         Ppath[:, v] = Ppath[:, tree_parent(v, arity)] ^ fm[:, v - 1]
     if law == "uniform":
         roots = [(r, 1.0 / V) for r in range(V)]
+    elif law == "table":
+        tab = np.asarray(table, dtype=np.float64)
+        roots = [(r, tab[r] / tab.sum()) for r in range(V) if tab[r] > 0]
     else:
         roots = [(r, math.comb(M, r) / 2 ** M) for r in range(V)]
     if prior == "comb":
         g = np.array([math.comb(M, v) for v in range(V)], dtype=np.float64)
     elif prior == "printed":
         g = np.array([math.comb(M + 1, v) for v in range(V)], dtype=np.float64)
+    elif prior == "table":
+        g = np.asarray(table, dtype=np.float64)
     else:
         g = np.ones(V)
     for s in range(S):

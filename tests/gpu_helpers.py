@@ -35,16 +35,20 @@ def column_nodes(M, r):
     return [0 if (r >= 1 and m == r - 1) else m + 1 for m in range(M)]
 
 
-def oracle_candidates(seed, chain, step, N, M, kmin, kmax, s, rule="mcmcmc", arity=None, law="uniform"):
+LAW_CODES = {"uniform": oracle.LAW_UNIFORM, "line": oracle.LAW_LINE, "table": oracle.LAW_TABLE}
+
+
+def oracle_candidates(seed, chain, step, N, M, kmin, kmax, s, rule="mcmcmc", arity=None, law="uniform",
+                      table=None):
     """Root and the M non-current node configurations in column order."""
     r, nodes = oracle.propose_nodes(seed, chain, step, N, M, kmin, kmax, s,
                                     rule=oracle.RULE_METROPOLIS if rule == "metropolis" else oracle.RULE_MCMCMC,
-                                    arity=arity, law=oracle.LAW_LINE if law == "line" else oracle.LAW_UNIFORM)
+                                    arity=arity, law=LAW_CODES[law], table=table)
     return r, nodes[column_nodes(M, r)]
 
 
 def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas, rule, energy_rtol,
-                       exact=False, chain_base=0, arity=None, law="uniform"):
+                       exact=False, chain_base=0, arity=None, law="uniform", table=None):
     """Run the oracle over the same steps, taking the GPU's pick at the steps the GPU
     flagged as near ties (guided replay), and compare every record."""
     steps = len(betas)
@@ -53,8 +57,7 @@ def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas,
         forced[:] = -1
     ro = oracle.run(J, scale, N, M, chains, kmin, kmax, seed, betas,
                     rule=oracle.RULE_METROPOLIS if rule == "metropolis" else oracle.RULE_MCMCMC,
-                    forced=forced, chain_base=chain_base, arity=arity,
-                    law=oracle.LAW_LINE if law == "line" else oracle.LAW_UNIFORM)
+                    forced=forced, chain_base=chain_base, arity=arity, law=LAW_CODES[law], table=table)
     orec = ro["rec"]
     assert np.array_equal(gpu_rec["r"], orec["r"]), "roots differ"
     bad = np.argwhere(gpu_rec["vstar"] != orec["vstar"])

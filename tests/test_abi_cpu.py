@@ -51,6 +51,7 @@ int main(void) {
          offsetof(mc3_batch_config, instances), offsetof(mc3_batch_config, scorer), offsetof(mc3_config, scorer));
   printf("%zu %zu %zu %zu\n", offsetof(mc3_config, arity), offsetof(mc3_config, law),
          offsetof(mc3_batch_config, arity), offsetof(mc3_batch_config, law));
+  printf("%zu %zu\n", offsetof(mc3_config, law_table), offsetof(mc3_batch_config, law_table));
   return 0;
 }
 '''
@@ -67,7 +68,8 @@ int main(void) {
                     native.BatchConfig.chain_base.offset, native.BatchConfig.seed.offset,
                     native.BatchConfig.instances.offset, native.BatchConfig.scorer.offset,
                     native.Config.scorer.offset, native.Config.arity.offset, native.Config.law.offset,
-                    native.BatchConfig.arity.offset, native.BatchConfig.law.offset]
+                    native.BatchConfig.arity.offset, native.BatchConfig.law.offset,
+                    native.Config.law_table.offset, native.BatchConfig.law_table.offset]
 
 
 def test_version(lib):
@@ -208,3 +210,31 @@ def test_graph_shape_validation(lib, kw, expect):
     cfg = native.make_config(precision="fp64", **base, **kw)
     n = ctypes.c_size_t()
     assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == expect
+
+
+@pytest.mark.parametrize("table,arity,expect", [
+    ([0.2, 0.3, 0.1, 0.1, 0.1, 0.1, 0.1], 0, native.MC3_OK),
+    ([0.2, 0.0, 0.1, 0.1, 0.1, 0.1, 0.1], 2, native.MC3_OK),
+    ([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0], 1, native.MC3_OK),
+    (None, 0, native.MC3_E_ARG),
+    ([0.0] * 7, 0, native.MC3_E_ARG),
+    ([0.2, -0.1, 0.1, 0.1, 0.1, 0.1, 0.1], 0, native.MC3_E_ARG),
+    ([0.2, float("nan"), 0.1, 0.1, 0.1, 0.1, 0.1], 0, native.MC3_E_ARG),
+    ([0.2, float("inf"), 0.1, 0.1, 0.1, 0.1, 0.1], 0, native.MC3_E_ARG)])
+def test_table_law_validation(lib, table, arity, expect):
+    cfg = native.make_config(64, 6, 2, 1, 1, precision="fp64", arity=arity, law="table", law_table=table)
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == expect
+
+
+def test_table_law_batch_validation(lib):
+    """A batch's table holds every instance's M_i+1 weights in instance order; one bad
+    instance rejects the batch."""
+    descs = [(64, 3, 2, 1, 1), (128, 2, 1, 1, 2)]
+    n = ctypes.c_size_t()
+    good = native.make_batch_config(descs, precision="fp64", law="table",
+                                    law_table=[1.0, 2.0, 3.0, 4.0, 0.5, 0.0, 0.5])
+    assert lib.mc3_batch_workspace_size(ctypes.byref(good), ctypes.byref(n)) == native.MC3_OK
+    bad = native.make_batch_config(descs, precision="fp64", law="table",
+                                   law_table=[1.0, 2.0, 3.0, 4.0, 0.0, 0.0, 0.0])
+    assert lib.mc3_batch_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == native.MC3_E_ARG

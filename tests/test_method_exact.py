@@ -217,3 +217,51 @@ def test_line_addition_process_needs_its_prior(M):
     for bad in ("none", "printed"):
         P = tree_kernel(E, beta, N, M, 1, 1, 1, law="line", prior=bad)
         assert np.max(np.abs(pi @ P - pi)) > 1e-4, bad
+
+
+@pytest.mark.parametrize("M,arity,table", [
+    (3, 3, [0.1, 0.5, 0.3, 0.1]),            # star, hub favoured
+    (3, 2, [0.4, 0.0, 0.35, 0.25]),          # binary tree, one node never the root
+    (3, 1, [0.05, 0.15, 0.3, 0.5]),          # line, skewed toward the far end
+    (4, 2, [1.0, 2.0, 0.5, 3.0, 1.5])])      # unnormalised weights
+def test_table_root_law_needs_its_prior(M, arity, table):
+    """A populating process with a free root law p_r (App. 'General graph populating
+    process'): with symmetric flip sets P_gen(T|c_v) = p_v times a product common to
+    the nodes, so node weights exp(-beta E_v) p_v make the chain stationary and
+    reversible; plain Boltzmann node weights do not."""
+    N, beta = 3, 1.2
+    J, scale = inputs.couplings_gauss(N, 300 + M + arity)
+    E = all_energies(J, scale)
+    pi = boltzmann(E, beta)
+    good = tree_kernel(E, beta, N, M, arity, 1, 1, law="table", prior="table", table=table)
+    _stationary_and_reversible(good, pi)
+    bad = tree_kernel(E, beta, N, M, arity, 1, 1, law="table", prior="none", table=table)
+    assert np.max(np.abs(pi @ bad - pi)) > 1e-6   # six orders above the stationary kernel's 1e-12
+
+
+@pytest.mark.parametrize("p", [0.2, 0.5, 0.8])
+def test_three_configuration_process_is_a_table_law(p):
+    """The three-configuration process of Sec. 'Generalization to three configurations
+    per Monte Carlo step' with symmetric proposals: the printed P_gen(T|c) of the end,
+    middle and end nodes are in the ratio q : 2p : q, which is the line of three
+    nodes with root weights (q/2, p, q/2); that table law is stationary for every p,
+    and p = 1/2 is the line-graph addition process of two additions."""
+    gold = _load_three()["P_gen_T_given"]
+    n = 4
+    rng = np.random.Generator(np.random.PCG64(8))
+    A = rng.random((n, n))
+    Pprp = A + A.T
+    np.fill_diagonal(Pprp, 0.0)
+    Pprp /= Pprp.sum()                      # symmetric two-body law
+    lab = {"c0": 0, "c1": 1, "c2": 2}       # c1 is the middle node of c0 - c1 - c2
+    g = np.array([_eval_factor(gold[c], Pprp, p, lab) for c in ("c0", "c1", "c2")])
+    q = 1.0 - p
+    table = np.array([q / 2, p, q / 2])
+    assert np.allclose(g / g.sum(), table / table.sum(), rtol=1e-12)
+    N, beta = 3, 0.9
+    J, scale = inputs.couplings_gauss(N, 77)
+    E = all_energies(J, scale)
+    P = tree_kernel(E, beta, N, 2, 1, 1, 2, law="table", prior="table", table=table)
+    _stationary_and_reversible(P, boltzmann(E, beta))
+    if p == 0.5:
+        assert np.allclose(P, tree_kernel(E, beta, N, 2, 1, 1, 2, law="line", prior="comb"), atol=1e-14)

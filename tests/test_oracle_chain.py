@@ -173,3 +173,66 @@ def test_high_temperature_expansion_at_n64():
     assert abs(m - e_pred) < 5 * se + 0.01, (m, e_pred, se)
     # the leading term alone is resolved: a dropped factor or sign fails
     assert abs(m - 2 * e_pred) > 10 * se and abs(m + e_pred) > 10 * se
+
+
+# ---------------------------------------------------------------- table root law
+
+@pytest.mark.parametrize("table", [[0.1, 0.5, 0.3, 0.1], [2.0, 0.0, 1.0, 5.0, 0.0, 2.0], [1.0] * 7])
+def test_table_root_follows_its_weights(table):
+    """Roots drawn under a table law have frequencies table[v] / sum (chi-square over
+    20000 chain-steps); weight 0 is never drawn."""
+    M, n = len(table) - 1, 20000
+    r = np.array([oracle.root(5, c % 64, c // 64, M, oracle.LAW_TABLE, table) for c in range(n)])
+    counts = np.bincount(r, minlength=M + 1)
+    g = np.asarray(table, dtype=np.float64)
+    assert np.all(counts[g == 0] == 0)
+    stat, dof = _chi2_pass(counts, g / g.sum(), n)
+    assert stat < dof + 6 * np.sqrt(2 * dof), (stat, dof)
+
+
+def test_table_root_special_cases():
+    """One nonzero weight: that node is always the root.  Weights that differ by a
+    common factor give the same roots.  Invalid tables are rejected."""
+    M = 5
+    for v in range(M + 1):
+        tab = np.zeros(M + 1)
+        tab[v] = 3.0
+        assert all(oracle.root(1, c, 7, M, oracle.LAW_TABLE, tab) == v for c in range(50))
+    t1 = [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    t2 = [x * 4.0 for x in t1]        # a power of two: the same fixed-point weights
+    assert [oracle.root(2, c, 3, M, oracle.LAW_TABLE, t1) for c in range(200)] == \
+           [oracle.root(2, c, 3, M, oracle.LAW_TABLE, t2) for c in range(200)]
+    for bad in ([0.0] * 6, [1.0, -1.0, 1.0, 1.0, 1.0, 1.0], [1.0, float("nan"), 1, 1, 1, 1],
+                [1.0, float("inf"), 1, 1, 1, 1]):
+        with pytest.raises(ValueError):
+            oracle.root_table_cdf(bad)
+
+
+def test_table_log_prior_is_log_weight():
+    """exp of the table law's log-prior is proportional to the weights (to the 2^-52
+    resolution of the fixed point); a zero weight gives -infinity."""
+    tab = np.array([0.3, 0.0, 1.7, 1e-3, 5.0])
+    lp = oracle.log_prior_table(tab)
+    assert lp[1] == -np.inf
+    ok = tab > 0
+    ratio = np.exp(lp[ok] - lp[ok].max())
+    np.testing.assert_allclose(ratio, tab[ok] / tab[ok].max(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("M,arity,table,beta,start", [
+    (3, 3, [0.1, 0.5, 0.3, 0.1], 1.0, 6),
+    (3, 1, [0.05, 0.15, 0.3, 0.5], 1.4, 13),
+    (2, 1, [0.4, 0.2, 0.4], 0.8, 27),          # three-configuration process, p = 0.2
+])
+def test_table_one_step_frequencies_match_exact_row(M, arity, table, beta, start):
+    N, K = 5, 40000
+    J, scale = inputs.couplings_gauss(N, 29)
+    E = all_energies(J, scale)
+    P = tree_kernel(E, beta, N, M, arity, 1, 1, law="table", prior="table", table=table)
+    s0 = spins_of(np.array([start]), N)[0].astype(np.int8)
+    spins = np.repeat(s0[None, :], K, axis=0)
+    out = oracle.run(J, scale, N, M, K, 1, 1, seed=79, betas=[beta], spins=spins, arity=arity,
+                     law=oracle.LAW_TABLE, table=table)
+    counts = np.bincount(_states_of(out["spins"]), minlength=2 ** N)
+    stat, dof = _chi2_pass(counts, P[start], K)
+    assert stat < dof + 6 * np.sqrt(2 * dof), (stat, dof)
