@@ -407,6 +407,69 @@ def _large_thermalize(T):
     return out
 
 
+def _table_law_workload(steps=200):
+    """The line of 2^7 nodes grown with probability 0.3 of adding at node 0's end
+    (root-law table C(M, v) 0.3^v 0.7^(M-v)) on the headline instance: N = 1024, 256
+    chains, single-spin-flip edges, beta = 1, split BF16 and FP64 pair sums (the line's
+    paths are too long for the field update)."""
+    import math
+    import torch
+    from paper_2102_05613_amd import inputs, native
+    w = inputs.workload("sk_n1024_m128_split")
+    J, scale = w.couplings_matrix()
+    M = 127
+    table = [math.comb(M, v) * 0.3 ** v * 0.7 ** (M - v) for v in range(M + 1)]
+    out = {"N": w.N, "M": M, "chains": w.chains, "beta": 1.0, "table": "C(M, v) 0.3^v 0.7^(M-v)"}
+    for prec, scorer in (("split_bf16", "gemm"), ("fp64", "gemm")):
+        cfg = native.make_config(w.N, M, w.chains, 1, 1, precision=prec, seed=w.seed, scorer=scorer, arity=1,
+                                 law="table", law_table=table)
+        ctx = native.Context(cfg)
+        ctx.init_couplings(J, scale)
+        ctx.init_chains()
+        ctx.step_n(0, 20, 1.0, 1.0, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step_n(20, steps, 1.0, 1.0, 1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        summ = ctx.measure()[2]
+        ctx.close()
+        out[f"{prec}_{scorer}"] = {"ms_per_step": ms, "candidates_per_s": w.chains * M / (ms / 1e3),
+                                   "moves_per_chain_step": summ["moves"] / (summ["steps_done"] * w.chains)}
+    return out
+
+
+def _set_variant(reps=20):
+    """mc3_set_generation timed on seeded synthetic two-body laws: one set of n = 20
+    (2^20 subsets) and 4096 sets of n = 12.  Work per subset X of size k: (n-k) k
+    multiply-adds of FP64, n(n-1) 2^(n-2) over all subsets of a set."""
+    import torch
+    from paper_2102_05613_amd import native
+    out = {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0x5EED0006)
+    for n, n_sets in ((20, 1), (12, 4096)):
+        G = torch.rand((n_sets, n, n), dtype=torch.float64, device="cuda", generator=gen)
+        G.diagonal(dim1=1, dim2=2).zero_()
+        G = G / G.sum(dim=1, keepdim=True)
+        native.set_generation(G)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            native.set_generation(G)
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / reps
+        flops = 2.0 * n_sets * n * (n - 1) * 2.0 ** (n - 2)
+        out[f"n{n}_sets{n_sets}"] = {"ms": ms, "subsets_per_s": n_sets * 2.0 ** n / (ms / 1e3),
+                                     "launches": n + 1, "achieved_gflops_fp64": flops / (ms / 1e3) / 1e9,
+                                     "frac_fp64_peak": flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS}
+    out["note"] = ("one launch per subset size (levels of decreasing popcount); small sets are bound by the "
+                   "launches, the largest by the levels' passes over 2^n entries")
+    return out
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -456,6 +519,7 @@ def main():
     ap.add_argument("--large-thermalize-steps", type=int, default=0,
                     help="steps of the N=8192 anneal study (0 skips it; 20000 is the workload's schedule)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--set-variant", type=int, default=1, help="0 skips the set-variant timing")
     ap.add_argument("--small-steps", type=int, default=10000,
                     help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
     ap.add_argument("--batch-instances", type=int, default=2000, help="0 skips the batched workload")
@@ -549,6 +613,11 @@ def main():
         Jl, sl = wl.couplings_matrix()
         out["precision_split_vs_fp64"]["sk_n8192_m1024"] = _precision_report(wl, Jl, sl)
         _log("large workload precision done")
+    if args.set_variant:
+        other["root_law_table_biased_line"] = _table_law_workload()
+        _log("root-law table workload done")
+        other["set_variant_generation"] = _set_variant()
+        _log("set variant done")
     if args.large_thermalize_steps > 0:
         out.setdefault("steps_to_thermalize", {})["large_workload"] = _large_thermalize(args.large_thermalize_steps)
     if other:

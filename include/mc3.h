@@ -339,6 +339,33 @@ mc3_status mc3_sync(mc3_ctx* ctx);
 /* Text of the last error on this context ("" if none); valid until the next call. */
 const char* mc3_last_error(const mc3_ctx* ctx);
 
+/* The set variant (App. "Markov chain of sets of configurations"): generation
+ * probabilities of a set from its subsets and the probabilities of visiting each
+ * subset, for n_sets sets of n elements at once; needs no context.
+ * A set S = {0..n-1} grows from a nonempty subset X by additions (Sec. "Stochastic
+ * generation of the set"): a parent chosen uniformly among the current elements
+ * generates the new element e with probability G[e][parent]; S is reached when the
+ * n - |X| additions bring exactly the elements of S \ X, in any order.
+ *   G        device [n_sets][n][n] FP64, G[e][p] = P_gen(e | p) (row: new element).
+ *   out      device [n_sets][2^n] FP64: out[X] = P_gen(S | X) for every bitmask X
+ *            (out[S] = 1, out[0] = 0), from the recursion of Sec. "Recursive
+ *            exponential formula for the generation probability" over subsets of
+ *            decreasing size, out[X] = (1/|X|) sum_{e not in X} (sum_{p in X} G[e][p])
+ *            out[X + e] (the prefactor fixed by the sum over insertion orders; the
+ *            printed ones are garbled).
+ *   peq      optional device [n_sets][2^n]: the equilibrium probabilities P_eq(X) of
+ *            the proper subsets (entry S ignored; App. "Markov chain of sets of
+ *            configurations": lambda_|X| w(X) / N_n); with it
+ *   peq_set  device [n_sets]: P_eq(S) = sum_{X != S} P_eq(X) out[X] (Eq. eq_P_eq_n),
+ *   psub     device [n_sets][2^n]: P_subset(X | S) = P_eq(X) out[X] / P_eq(S)
+ *            (Eq. eq_p_S_S), psub[S] = 0; it sums to 1 over X.
+ * Runs on `stream` (a hipStream_t, NULL = default) and returns without waiting.
+ * MC3_E_ARG for 1 > n or n > 20, n_sets < 1, n_sets 2^n > 2^28, a NULL G or out, peq
+ * without psub and peq_set (or the reverse), or a pointer that is not device memory;
+ * MC3_E_DEVICE if a launch fails.  The caller owns every buffer. */
+mc3_status mc3_set_generation(const double* G, int32_t n, int32_t n_sets, double* out, const double* peq,
+                              double* psub, double* peq_set, void* stream);
+
 /* Library version string. */
 const char* mc3_version(void);
 

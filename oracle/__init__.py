@@ -97,6 +97,8 @@ def lib():
         L.mc3o_root_table.argtypes = [u64, u32, u32, i32, P(u64)]
         L.mc3o_root_table.restype = i32
         L.mc3o_log_prior_table.argtypes = [i32, P(u64), P(dbl)]
+        L.mc3o_set_gen_brute.argtypes = [i32, P(dbl), u32, P(i32)]
+        L.mc3o_set_gen_brute.restype = dbl
         L.mc3o_build_nodes.argtypes = [i32, i32, i32, i32, P(ctypes.c_int8), P(ctypes.c_uint8), P(ctypes.c_int8)]
         L.mc3o_select_mcmcmc.argtypes = [i32, P(dbl), P(dbl), dbl, u64, P(dbl), P(dbl), P(u64)]
         L.mc3o_select_mcmcmc.restype = i32
@@ -268,3 +270,15 @@ def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kma
     if node_e is not None:
         out["node_e"] = node_e
     return out
+
+
+def set_gen_brute(G, X: int) -> float:
+    """P_gen(S | X) of the set variant (S = {0..n-1}, X a nonempty bitmask), summed over
+    every order of the added elements (at most 10 of them); G[e][p] = P_gen(e | p)."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    n = G.shape[0]
+    st = ctypes.c_int32()
+    v = lib().mc3o_set_gen_brute(n, _ptr(G, ctypes.c_double), int(X), ctypes.byref(st))
+    if st.value != 0:
+        raise ValueError("set_gen_brute: empty X, more than 10 additions or n > 30")
+    return float(v)

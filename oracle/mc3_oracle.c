@@ -44,6 +44,8 @@
  *  - Standard MCMC with the Metropolis rate min(1, ratio), Sec. "Problem statement",
  *    for the single-update baseline (rule METROPOLIS, M = 1).
  *  - Observables as node-weighted averages over the graph, Eq. eq_monte_carlo_graph.
+ *  - The set variant's generation probability P_gen(S | X), Sec. "Stochastic
+ *    generation of the set", summed over every order of the added elements.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), keyed by the seed; the counter names the
@@ -478,4 +480,54 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
     }
     free(flips); free(nodes); free(E); free(log_prior); free(Qcum);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ sets */
+
+/* The set variant's generation probability, from its definition (Sec. "Stochastic
+ * generation of the set"): a set grows from a nonempty subset X of S = {0..n-1} by
+ * additions; each addition chooses a parent uniformly among the current elements and
+ * generates the new element e with probability G[e*n + parent] (G[e][parent] =
+ * P_gen(e | parent)); S is reached when the n - |X| additions bring exactly the
+ * elements of S \ X, in some order.  P_gen(S | X) is the sum over the orders
+ * (e_1, .., e_r) of S \ X of prod_j (1/|X_j|) sum_{p in X_j} G[e_j][p], with
+ * X_j = X + {e_1 .. e_(j-1)}; every order is enumerated explicitly (r <= 10).
+ * Returns -1 for an empty X, r > 10, or n > 30. */
+double mc3o_set_gen_brute(int n, const double* G, uint32_t X, int* status)
+{
+    *status = 0;
+    if (n < 1 || n > 30 || X == 0u) { *status = -1; return 0.0; }
+    int add[32], r = 0;
+    for (int e = 0; e < n; ++e) if (!((X >> e) & 1u)) add[r++] = e;
+    if (r == 0) return 1.0;
+    if (r > 10) { *status = -1; return 0.0; }
+    /* orders in lexicographic order of index permutations */
+    int perm[32];
+    for (int i = 0; i < r; ++i) perm[i] = i;
+    double total = 0.0;
+    for (;;) {
+        uint32_t cur = X;
+        int size = 0;
+        for (int e = 0; e < n; ++e) size += (int)((X >> e) & 1u);
+        double prob = 1.0;
+        for (int j = 0; j < r; ++j) {
+            int e = add[perm[j]];
+            double s = 0.0;
+            for (int p = 0; p < n; ++p)
+                if ((cur >> p) & 1u) s += G[(size_t)e * n + p];
+            prob *= s / (double)size;
+            cur |= 1u << e;
+            ++size;
+        }
+        total += prob;
+        /* next permutation */
+        int i = r - 2;
+        while (i >= 0 && perm[i] > perm[i + 1]) --i;
+        if (i < 0) break;
+        int k = r - 1;
+        while (perm[k] < perm[i]) --k;
+        int t = perm[i]; perm[i] = perm[k]; perm[k] = t;
+        for (int a = i + 1, b = r - 1; a < b; ++a, --b) { t = perm[a]; perm[a] = perm[b]; perm[b] = t; }
+    }
+    return total;
 }

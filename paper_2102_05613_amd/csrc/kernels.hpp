@@ -6,3 +6,4 @@
 #include "score_f64.hpp"
 #include "select.hpp"
 #include "delta.hpp"
+#include "sets.hpp"

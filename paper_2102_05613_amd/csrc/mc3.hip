@@ -1233,4 +1233,40 @@ mc3_status mc3_sync(mc3_ctx* c) {
 
 const char* mc3_last_error(const mc3_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
 
+mc3_status mc3_set_generation(const double* G, int32_t n, int32_t n_sets, double* out, const double* peq,
+                              double* psub, double* peq_set, void* stream) {
+  if (!G || !out || n < 1 || n > 20 || n_sets < 1 || ((int64_t)n_sets << n) > (int64_t(1) << 28)) return MC3_E_ARG;
+  if ((peq != nullptr) != (psub != nullptr) || (peq != nullptr) != (peq_set != nullptr)) return MC3_E_ARG;
+  for (const void* ptr : {(const void*)G, (const void*)out, (const void*)peq, (const void*)psub,
+                          (const void*)peq_set}) {
+    if (!ptr) continue;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return MC3_E_ARG;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned masks = (1u << n);
+  const dim3 grid((masks + 255) / 256, (unsigned)n_sets);
+  auto binom = [](int b, int j) {
+    uint64_t c = 1;
+    for (int i = 0; i < j; ++i) c = c * (uint64_t)(b - i) / (uint64_t)(i + 1);
+    return (unsigned)c;
+  };
+  if (n <= mc3::kSetLdsMax) {
+    hipLaunchKernelGGL(mc3::k_set_gen_lds, dim3((unsigned)n_sets), dim3(256), 0, st, G, out, n);
+  } else {
+    hipLaunchKernelGGL(mc3::k_set_gen_ends, dim3((n_sets + 255) / 256), dim3(256), 0, st, out, n, n_sets);
+    for (int k = n - 1; k >= 1; --k)
+      hipLaunchKernelGGL(mc3::k_set_gen_level, dim3((binom(n, k) + 255) / 256, (unsigned)n_sets), dim3(256), 0, st,
+                         G, out, n, k);
+  }
+  if (peq) {
+    hipLaunchKernelGGL(mc3::k_set_peq, dim3((unsigned)n_sets), dim3(256), 0, st, peq, out, peq_set, n);
+    hipLaunchKernelGGL(mc3::k_set_psub, grid, dim3(256), 0, st, peq, out, peq_set, psub, n);
+  }
+  return hipGetLastError() == hipSuccess ? MC3_OK : MC3_E_DEVICE;
+}
+
 }  // extern "C"

@@ -35,7 +35,7 @@ EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_coupling
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
            "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
            "mc3_init_couplings_instance", "mc3_step_n_per_instance", "mc3_checkpoint_save",
-           "mc3_checkpoint_load"]
+           "mc3_checkpoint_load", "mc3_set_generation"]
 
 
 class Config(ctypes.Structure):
@@ -112,6 +112,7 @@ def lib() -> ctypes.CDLL:
     L.mc3_step_n_per_instance.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
     L.mc3_checkpoint_save.argtypes = [vp, vp, P(c.c_size_t)]
     L.mc3_checkpoint_load.argtypes = [vp, vp, c.c_size_t]
+    L.mc3_set_generation.argtypes = [vp, c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
     L.mc3_last_error.argtypes = [vp]
     L.mc3_last_error.restype = c.c_char_p
     L.mc3_version.restype = c.c_char_p
@@ -295,6 +296,31 @@ class Context:
 
     def sync(self):
         self._check(lib().mc3_sync(self.h), "mc3_sync")
+
+
+def set_generation(G, peq=None):
+    """mc3_set_generation on torch tensors: G float64 CUDA [n_sets, n, n] (G[s, e, p] =
+    P_gen(e | p)); optional peq [n_sets, 2^n].  Returns out [n_sets, 2^n] and, with peq,
+    (out, psub, peq_set); runs on the current stream."""
+    import torch
+    if G.dtype != torch.float64 or not G.is_cuda or G.dim() != 3 or G.shape[1] != G.shape[2]:
+        raise ValueError("G must be a float64 CUDA tensor [n_sets, n, n]")
+    G = G.contiguous()
+    n_sets, n = G.shape[0], G.shape[1]
+    out = torch.empty((n_sets, 1 << n), dtype=torch.float64, device=G.device)
+    psub = peq_set = None
+    if peq is not None:
+        peq = peq.contiguous()
+        if peq.dtype != torch.float64 or tuple(peq.shape) != (n_sets, 1 << n) or peq.device != G.device:
+            raise ValueError("peq must be a float64 tensor [n_sets, 2^n] on G's device")
+        psub = torch.empty_like(out)
+        peq_set = torch.empty(n_sets, dtype=torch.float64, device=G.device)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    st = lib().mc3_set_generation(ptr(G), n, n_sets, ptr(out), ptr(peq), ptr(psub), ptr(peq_set),
+                                  ctypes.c_void_p(torch.cuda.current_stream(G.device).cuda_stream))
+    if st != MC3_OK:
+        raise MC3Error(st, "mc3_set_generation")
+    return out if peq is None else (out, psub, peq_set)
 
 
 def bits_to_spins(bits: np.ndarray, N: int) -> np.ndarray:
