@@ -80,10 +80,11 @@ struct Unit {
   int32_t inst, p, ct, pad;
 };
 
-// A proposal block: edges edge0 .. edge0 + blockDim.x - 1 (flattened chain*M + e-1) of
-// instance inst.
+// A proposal block: edges edge0 .. edge0 + count - 1 (flattened chain*M + e-1) of
+// instance inst, count <= blockDim.x (whole chains when the tree's path sets are formed
+// inside the block).
 struct PBlock {
-  int32_t inst, edge0;
+  int32_t inst, edge0, count, pad;
 };
 
 // Asynchronous copy of 16 bytes per lane from global memory straight into LDS:

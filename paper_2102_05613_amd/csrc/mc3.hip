@@ -220,7 +220,16 @@ Plan make_plan(const mc3_batch_config& cfg) {
     InstH& h = pl.inst[i];
     const long long edges = (long long)h.desc.chains * h.desc.M;
     h.pblock_off = (int)pl.pblocks.size();
-    for (long long e0 = 0; e0 < edges; e0 += pl.prop_T) pl.pblocks.push_back(mc3::PBlock{i, (int32_t)e0});
+    if (h.arity < h.desc.M && h.desc.M <= pl.prop_T) {
+      // whole chains per block: the path sets are formed inside the block
+      const int cpb = pl.prop_T / h.desc.M;
+      for (int c0 = 0; c0 < h.desc.chains; c0 += cpb)
+        pl.pblocks.push_back(mc3::PBlock{i, (int32_t)((long long)c0 * h.desc.M),
+                                         std::min(cpb, h.desc.chains - c0) * h.desc.M, 0});
+    } else {
+      for (long long e0 = 0; e0 < edges; e0 += pl.prop_T)
+        pl.pblocks.push_back(mc3::PBlock{i, (int32_t)e0, (int32_t)std::min<long long>(pl.prop_T, edges - e0), 0});
+    }
     h.pblock_cnt = (int)pl.pblocks.size() - h.pblock_off;
     for (int c = 0; c < h.desc.chains; ++c) pl.chain_inst.push_back(i);
   }

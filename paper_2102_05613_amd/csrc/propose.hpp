@@ -123,13 +123,20 @@ __device__ __forceinline__ int flip_count(Key key, uint32_t gc, uint32_t step, u
 // words (W+1 where it fits, against bank collisions).  The thread of node 1 stores the
 // chain's root in roots_ring[slot][global chain].  With write_base, for the first step
 // only, the thread of node r (node 1 if r = 0) also writes base = s ^ P(r) from the
-// chain's current spins.  Dynamic LDS: rows * blockDim.x * stride words.
+// chain's current spins.
+// Trees other than the star whose chains fit a block (M <= blockDim.x; the host then
+// lays blocks on whole chains) instead draw every edge once: thread v-1 of a chain
+// draws F_v into its row, and the path sets follow by pointer jumping, P(v) ^= P(a(v))
+// and a(v) <- a(a(v)) starting from a(v) = parent(v), over ceil(log2(depth)) rounds
+// between the two row sets (no ordering by size there: each thread draws one set).
+// Dynamic LDS: rows * blockDim.x * stride words.
 __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts, const PBlock* __restrict__ blocks,
                           int32_t* __restrict__ roots_ring, int total_chains, uint32_t nslots, int write_base,
                           int stride, int rows, int metropolis, Key key, uint32_t chain_base, uint32_t step0) {
   extern __shared__ uint32_t lds_bits[];
   __shared__ int bucket_n[16], bucket_at[16];
   __shared__ int order[256];
+  __shared__ int anc_row[256];
   const int T = blockDim.x, tid = threadIdx.x;
   const uint32_t step = step0 + blockIdx.y;
   const uint32_t slot = step % nslots;
@@ -141,9 +148,61 @@ __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts,
   for (int i = tid; i < rows * T * stride; i += T) lds_bits[i] = 0u;
   if (tid < 16) bucket_n[tid] = 0;
   __syncthreads();
-  // 1. rank of this thread's own path by its number of insertions
   const long long g = (long long)blk0.edge0 + tid;
-  const bool real = g < total;
+  const bool real = tid < blk0.count && g < total;
+  if (!star && M <= T) {
+    // each edge once, then path sets by pointer jumping within the chain
+    const int c = real ? (int)(g / M) : 0;
+    const uint32_t e = real ? (uint32_t)(g % M) + 1u : 0u;
+    const uint32_t gc = chain_base + (uint32_t)(in.chain0 + c);
+    const int row0 = tid - (int)e + 1;   // row of node 1 of this chain
+    if (real) draw_flip_set(lds_bits + (size_t)tid * stride, key, gc, step, e, N, in.kmin, in.kmax);
+    int a = real ? (int)((e - 1u) / (uint32_t)in.arity) : 0;   // ancestor node, 0 = node 0
+    int depth = 0;
+    for (uint32_t u = (uint32_t)M; u >= 1u; u = (u - 1u) / (uint32_t)in.arity) ++depth;
+    int rounds = 0;
+    while ((1 << rounds) < depth) ++rounds;
+    anc_row[tid] = a;
+    __syncthreads();
+    uint32_t* src = lds_bits;
+    uint32_t* dst = lds_bits + (size_t)T * stride;
+    for (int rd = 0; rd < rounds; ++rd) {
+      int a_next = 0;
+      if (real) {
+        const uint32_t* me = src + (size_t)tid * stride;
+        uint32_t* out = dst + (size_t)tid * stride;
+        if (a >= 1) {
+          const int ra = row0 + a - 1;
+          const uint32_t* up = src + (size_t)ra * stride;
+          for (int w = 0; w < W; ++w) out[w] = me[w] ^ up[w];
+          a_next = anc_row[ra];
+        } else {
+          for (int w = 0; w < W; ++w) out[w] = me[w];
+        }
+      }
+      __syncthreads();
+      a = a_next;
+      anc_row[tid] = a;
+      uint32_t* t = src;
+      src = dst;
+      dst = t;
+      __syncthreads();
+    }
+    if (!real) return;
+    const uint32_t* path = src + (size_t)tid * stride;
+    const int r = root_of(key, gc, step, M, metropolis, in.law,
+                          in.root_q ? ws_at<const uint64_t>(ws, in.root_q) : nullptr);
+    if (e == 1u) roots_ring[(size_t)slot * total_chains + in.chain0 + c] = (int32_t)r;
+    uint32_t* flipsT = flips_at(ws, in, slot);
+    for (int w = 0; w < W; ++w) flipsT[(size_t)w * Bp + g] = path[w];
+    if (write_base && blockIdx.y == 0 && (int)e == (r == 0 ? 1 : r)) {
+      uint32_t* base = ws_at<uint32_t>(ws, in.base[step & 1u]);
+      const uint32_t* spins = ws_at<const uint32_t>(ws, in.spins);
+      for (int w = 0; w < W; ++w) base[(size_t)c * W + w] = spins[(size_t)c * W + w] ^ (r ? path[w] : 0u);
+    }
+    return;
+  }
+  // 1. rank of this thread's own path by its number of insertions
   const int c = real ? (int)(g / M) : 0;
   const uint32_t e = real ? (uint32_t)(g % M) + 1u : 0u;
   const uint32_t gc = chain_base + (uint32_t)(in.chain0 + c);
