@@ -599,7 +599,7 @@ mc3_status do_score(mc3_ctx* c, double* E_out) {
 // words of step+1 (whose flip sets and roots must already be proposed).
 mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n) {
   const Plan& pl = c->pl;
-  const size_t lds = (size_t)(pl.Mmax + 1) * 16 + (size_t)pl.Wmax * 4;
+  const size_t lds = (size_t)(pl.Mmax + 1) * 16;
   hipLaunchKernelGGL(mc3::k_select, dim3(n), dim3(256), lds, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
                      pl.total_chains, c->at<double>(pl.e_cur), c->roots(step), c->roots(step + 1u),
                      c->at<mc3::Record>(pl.ring), c->at<unsigned long long>(pl.moves),
