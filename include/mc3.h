@@ -13,16 +13,24 @@
  *     (App. "Markov chain of graphs of configurations", Eq.
  *     eq_det_balance_graph_solution with the normalisation of
  *     Eq. eq_normalization_p_c_T).
- *   - Graph: an M-ary star (hub = node 0, leaves 1..M) populated from a root drawn
- *     uniformly among the M+1 positions (App. "General graph populating process");
- *     each edge e carries a flip set F_e of k_e ~ U{kmin..kmax} distinct sites.
- *     Flip sets do not depend on the state, so the two-body law is symmetric and
- *     the tree is self-thermalising: P_node(v) = exp(-beta E_v) / sum_v' exp(-beta E_v').
+ *   - Graph: a tree on M+1 nodes populated from the position r of the current state
+ *     (App. "General graph populating process"): by default the M-ary star (hub =
+ *     node 0, leaves 1..M) with r drawn uniformly; breadth-first a-ary trees, the
+ *     line-graph addition process and caller-given root laws are chosen by arity and
+ *     law (mc3_graph_law).  Each edge e carries a flip set F_e of k_e ~ U{kmin..kmax}
+ *     distinct sites that does not depend on the state, so the two-body law is
+ *     symmetric: with a uniform root the tree is self-thermalising,
+ *     P_node(v) = exp(-beta E_v) / sum_v' exp(-beta E_v'); other root laws add their
+ *     log P_gen(T|c_v) to the exponents.
+ *   - The set variant's generation and subset-visit probabilities (App. "Markov chain
+ *     of sets of configurations") are a separate, context-free call
+ *     (mc3_set_generation).
  *   - Rule METROPOLIS (M = 1): the single-update Metropolis rate min(1, e^{-beta dE})
  *     of Sec. "Problem statement", the paper's baseline.
  *
  * Conventions
- *   - Spin bitsets: bit i of word i/32 set <=> s_i = -1.
+ *   - Spin bitsets passed through this ABI: bit i of word i/32 set <=> s_i = -1 (the
+ *     device keeps its own bit order inside each word).
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key (seed lo, seed hi)
  *     and counter (block, edge, step, tag<<28 | global chain).  Tags: 1 init,
  *     2 root, 3 edge, 4 select.  randint(w, n) = (w * n) >> 32.
@@ -61,7 +69,7 @@ typedef enum {
 } mc3_precision;
 
 typedef enum {
-    MC3_RULE_MCMCMC = 0,     /* node rule over the (M+1)-node star */
+    MC3_RULE_MCMCMC = 0,     /* node rule over the M+1 nodes of the graph */
     MC3_RULE_METROPOLIS = 1  /* single proposal, Metropolis rate; requires M == 1 */
 } mc3_rule;
 
