@@ -204,7 +204,9 @@ Plan make_plan(const mc3_batch_config& cfg) {
   pl.ahead = (int)std::max<size_t>(1, std::min<size_t>(kMaxAhead, kFlipBudget / slot_bytes));
   pl.nslots = pl.ahead + 1;
   // proposal blocks: one LDS bitset per thread (two when paths are longer than one
-  // edge), row stride W+1 where 64 threads fit
+  // edge) within 64 KiB, row stride W+1 where 64 threads fit; 64 to 256 threads in
+  // steps of 64, or 32 when two rows of the widest bitsets (W = 256) leave no room
+  // for 64
   pl.prop_rows = 1;
   for (const InstH& h : pl.inst)
     if (h.arity < h.desc.M) pl.prop_rows = 2;
@@ -214,8 +216,8 @@ Plan make_plan(const mc3_batch_config& cfg) {
     pl.prop_stride = pl.Wmax;
     T = (int)(65536 / ((size_t)pl.prop_rows * pl.prop_stride * 4));
   }
-  T = std::min(T, 256) / 64 * 64;
-  pl.prop_T = std::max(T, 64);
+  T = std::min(T, 256);
+  pl.prop_T = T >= 64 ? T / 64 * 64 : 32;
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
     const long long edges = (long long)h.desc.chains * h.desc.M;

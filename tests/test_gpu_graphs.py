@@ -53,6 +53,29 @@ def test_tree_candidates_bit_exact(M, arity, law, kmin, kmax):
             assert np.array_equal(cand[c], cols)
 
 
+@pytest.mark.parametrize("N,M,arity,kmin,kmax", [(4500, 14, 2, 1, 2), (8192, 14, 2, 1, 1), (8192, 40, 2, 1, 1),
+                                                  (8192, 20, 20, 1, 3), (8192, 31, 1, 1, 1)])
+def test_tree_candidates_wide_bitsets(N, M, arity, kmin, kmax):
+    """Wide bitsets (W = 144 and 256 words) leave room for only 32 proposal threads
+    when paths need two LDS rows: chains that fit such a block (M <= 32) and chains
+    that do not both give the oracle's candidates."""
+    chains = 5
+    announce(f"tree propose wide N={N} M={M} a={arity}")
+    J, scale = inputs.couplings_pm1(N, 6)
+    ctx = _ctx(N, M, chains, kmin, kmax, J, scale, arity, "uniform", seed=33)
+    del J
+    s = gpu_spins(ctx)
+    for step in (0, 2 ** 31 + 3):
+        ctx.propose(step)
+        bits, roots = ctx.read_candidates()
+        cand = native.bits_to_spins(bits, N)
+        for c in range(chains):
+            r, cols = oracle_candidates(33, c, step, N, M, kmin, kmax, s[c], arity=arity, law="uniform")
+            assert roots[c] == r
+            assert np.array_equal(cand[c], cols)
+    ctx.close()
+
+
 @pytest.mark.parametrize("M,arity,law,kmin,kmax", SHAPES)
 @pytest.mark.parametrize("prec,scorer", [("fp64", "gemm"), ("split_bf16", "gemm"), ("fp64", "delta")])
 def test_tree_pm1_trajectory_bit_exact(M, arity, law, kmin, kmax, prec, scorer):
