@@ -99,9 +99,9 @@ __device__ __forceinline__ void copy_a(SplitStage<WAVES>& st, const uint4* src, 
 }
 
 // One 32-k chunk: DMA of the next chunk's A fragments into `nxt`; this chunk's flip
-// and base words (loaded into registers two chunks ago) combined; the loads of the
-// words two chunks ahead issued into the same registers; then 2 k-steps x 12 A
-// fragments x 2 column fragments of MFMAs from `cur`.  The closing wait lets the
+// and base words (loaded into registers two chunks ago) combined into the columns'
+// spin words `w`; the loads of the words two chunks ahead issued into the same
+// registers; then 2 k-steps x 12 A fragments x 2 column fragments of MFMAs from `cur`.  The closing wait lets the
 // four word loads stay in flight (they were issued after the copies; loads complete
 // in order), so global latency of the words is hidden behind two chunks.
 template <int WAVES, int RF_LAST = 3>
@@ -109,10 +109,9 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStag
                                             SplitStage<WAVES>& nxt, const uint4* next_a, size_t row_stride,
                                             uint32_t (&rawf)[2], uint32_t (&rawb)[2], const uint32_t* pf0,
                                             const uint32_t* pf1, const uint32_t* pb0, const uint32_t* pb1,
-                                            uint32_t rootmask, int lane, int wave) {
+                                            uint32_t rootmask, int lane, int wave, uint32_t (&w)[2]) {
   copy_a<WAVES>(nxt, next_a, row_stride, wave);
   __builtin_amdgcn_sched_barrier(0);
-  uint32_t w[2];
 #pragma unroll
   for (int cf = 0; cf < 2; ++cf) w[cf] = rawb[cf] ^ (((rootmask >> cf) & 1u) ? 0u : rawf[cf]);
   rawf[0] = *pf0;
@@ -157,8 +156,9 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStag
 // filled by direct global->LDS copies one 32-k chunk ahead (two stages, the copy
 // running on from one row block into the next); each wave owns 64 columns, whose
 // flip-set and base words each lane loads into registers two chunks ahead, combines
-// and expands to +-1 BF16.  The epilogue multiplies h by the column's spins and sums
-// over rows in FP64; the unit writes one FP64 value per column.  Each block takes its
+// and expands to +-1 BF16.  The epilogue multiplies h by the column's spins (the words
+// of the block's first four chunks, kept in registers) and sums over rows in FP64; the
+// unit writes one FP64 value per column.  Each block takes its
 // unit from a table built by the host (the order of the table decides which XCD runs
 // which unit).
 template <int WAVES>
@@ -251,31 +251,39 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
 #define MC3_A(cn) (((cn) >= nchunk) ? src_n : src + (size_t)(cn) * 6 * 64)
 #define MC3_W(gg) flipsT + (size_t)kw_of(gg) * Bp + col0, flipsT + (size_t)kw_of(gg) * Bp + col1, \
                   brow0 + kw_of(gg), brow1 + kw_of(gg)
-    split_chunk<WAVES, 0>(acc, st0, st1, MC3_A(1), row_stride, rfE, rbE, MC3_W(g + 2), rootmask, lane, wave);
-    split_chunk<WAVES, 1>(acc, st1, st0, MC3_A(2), row_stride, rfO, rbO, MC3_W(g + 3), rootmask, lane, wave);
-    split_chunk<WAVES, 2>(acc, st0, st1, MC3_A(3), row_stride, rfE, rbE, MC3_W(g + 4), rootmask, lane, wave);
-    split_chunk<WAVES, 3>(acc, st1, st0, MC3_A(4), row_stride, rfO, rbO, MC3_W(g + 5), rootmask, lane, wave);
+    // the spin words of the block's own rows are those of its first four chunks (its
+    // K range starts at its first row): kept for the epilogue
+    uint32_t wblk[4][2], wsv[2];
+    split_chunk<WAVES, 0>(acc, st0, st1, MC3_A(1), row_stride, rfE, rbE, MC3_W(g + 2), rootmask, lane, wave,
+                          wblk[0]);
+    split_chunk<WAVES, 1>(acc, st1, st0, MC3_A(2), row_stride, rfO, rbO, MC3_W(g + 3), rootmask, lane, wave,
+                          wblk[1]);
+    split_chunk<WAVES, 2>(acc, st0, st1, MC3_A(3), row_stride, rfE, rbE, MC3_W(g + 4), rootmask, lane, wave,
+                          wblk[2]);
+    split_chunk<WAVES, 3>(acc, st1, st0, MC3_A(4), row_stride, rfO, rbO, MC3_W(g + 5), rootmask, lane, wave,
+                          wblk[3]);
     for (int c = 4; c < nchunk; c += 2) {
-      split_chunk<WAVES>(acc, st0, st1, MC3_A(c + 1), row_stride, rfE, rbE, MC3_W(g + c + 2), rootmask, lane, wave);
-      split_chunk<WAVES>(acc, st1, st0, MC3_A(c + 2), row_stride, rfO, rbO, MC3_W(g + c + 3), rootmask, lane, wave);
+      split_chunk<WAVES>(acc, st0, st1, MC3_A(c + 1), row_stride, rfE, rbE, MC3_W(g + c + 2), rootmask, lane, wave,
+                         wsv);
+      split_chunk<WAVES>(acc, st1, st0, MC3_A(c + 2), row_stride, rfO, rbO, MC3_W(g + c + 3), rootmask, lane, wave,
+                         wsv);
     }
 #undef MC3_A
 #undef MC3_W
     g += nchunk;
-    // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf + lane%32
+    // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf +
+    // lane%32, whose spins are bits site_bit(8(e/4) + 4(lane/32) + e%4) = 2(lane/32) +
+    // [16(e%2) + 4(e/4) + (e%4)/2] of word wblk[rf][cf]; the sign bit is added (an XOR)
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf) {
 #pragma unroll
       for (int cf = 0; cf < 2; ++cf) {
-        const int col = col_w + cf * 32 + (lane & 31);
-        const int rw = 4 * I + rf;
-        const uint32_t bw = col < B ? base[(size_t)(col / M) * W + rw] : 0u;
-        const uint32_t rb = ((rootmask >> cf) & 1u) ? bw : (bw ^ flipsT[(size_t)rw * Bp + col]);
+        const uint32_t sb = wblk[rf][cf] >> (2 * (lane >> 5));
         double sum = 0.0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const uint32_t bit = site_bit(8 * (e >> 2) + 4 * (lane >> 5) + (e & 3));
-          const float h = __uint_as_float(__float_as_uint(acc[rf][cf][e]) ^ (((rb >> bit) & 1u) << 31));
+          const uint32_t neg = __builtin_amdgcn_ubfe(sb, 16 * (e & 1) + 4 * (e >> 2) + ((e & 3) >> 1), 1);
+          const float h = __uint_as_float(__float_as_uint(acc[rf][cf][e]) + (neg << 31));
           sum += (double)h;
         }
         part[cf] += sum;
