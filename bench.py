@@ -41,13 +41,26 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_score_split_sk_n1024_m128_tr
 
 def kernel_source_hash() -> str:
     """sha256 over the sources the split scoring kernel is built from, to tie counter
-    measurements to the kernel they were taken on."""
+    measurements to the kernel they were taken on: the code only (line comments and
+    blank lines dropped, so that a comment edit does not retire a measurement)."""
     import hashlib
     h = hashlib.sha256()
     for name in ("common.hpp", "device_rng.hpp", "score_split.hpp"):
-        with open(os.path.join(ROOT, "paper_2102_05613_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2102_05613_amd", "csrc", name), encoding="utf-8") as f:
+            for code in code_lines(f.read()):
+                h.update(code.encode("utf-8") + b"\n")
     return h.hexdigest()
+
+
+def code_lines(text: str):
+    """The lines of a C++ source with line comments and trailing blanks removed, empty
+    lines dropped (the sources hashed here hold no '//' inside string literals)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            out.append(code)
+    return out
 
 
 def _traffic_from_profile():

@@ -117,8 +117,9 @@ __device__ __forceinline__ int flip_count(Key key, uint32_t gc, uint32_t step, u
 // one edge and the two rows are one).  A wave runs as long as its longest draw, so the
 // block first orders its paths by their number of insertions (the sum of k_u along
 // the path, in 16 buckets of 1/16 of the largest possible sum, kmax times the depth of
-// node M; ties in any order): thread i draws the path of rank i into row i.  Then thread i writes the path of its own column, (chain, v) =
-// edge0 + i, from the row that holds it: every word to flipsT[w][chain*M + v-1]
+// node M; ties in any order): thread i draws the path of rank i into row i.  Then
+// thread i writes the path of its own column, (chain, v) = edge0 + i, from the row
+// that holds it: every word to flipsT[w][chain*M + v-1]
 // (consecutive threads, consecutive addresses).  Rows have stride `stride` >= W
 // words (W+1 where it fits, against bank collisions).  The thread of node 1 stores the
 // chain's root in roots_ring[slot][global chain].  With write_base, for the first step

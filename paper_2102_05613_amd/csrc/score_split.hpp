@@ -101,9 +101,10 @@ __device__ __forceinline__ void copy_a(SplitStage<WAVES>& st, const uint4* src, 
 // One 32-k chunk: DMA of the next chunk's A fragments into `nxt`; this chunk's flip
 // and base words (loaded into registers two chunks ago) combined into the columns'
 // spin words `w`; the loads of the words two chunks ahead issued into the same
-// registers; then 2 k-steps x 12 A fragments x 2 column fragments of MFMAs from `cur`.  The closing wait lets the
-// four word loads stay in flight (they were issued after the copies; loads complete
-// in order), so global latency of the words is hidden behind two chunks.
+// registers; then 2 k-steps x 12 A fragments x 2 column fragments of MFMAs from
+// `cur`.  The closing wait lets the four word loads stay in flight (they were issued
+// after the copies; loads complete in order), so global latency of the words is hidden
+// behind two chunks.
 template <int WAVES, int RF_LAST = 3>
 __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStage<WAVES>& cur,
                                             SplitStage<WAVES>& nxt, const uint4* next_a, size_t row_stride,

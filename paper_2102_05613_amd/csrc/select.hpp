@@ -22,8 +22,9 @@ struct RuleOut {
   double e_new, ebar, margin;
 };
 
-__device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, int r, double ecur, int metropolis,
-                              double beta, uint64_t u53, int lane, const double* __restrict__ prior) {
+__device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long long* Qn, int M, int r, double ecur,
+                                              int metropolis, double beta, uint64_t u53, int lane,
+                                              const double* __restrict__ prior) {
   RuleOut o;
   const int nodes = M + 1;
   if (metropolis) {
@@ -115,9 +116,10 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
 
 // Per-chain bookkeeping of a selected step (one lane): carried energy, node-weighted
 // energy, counters and, with a ring, the step's record.
-__device__ __forceinline__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint32_t step, int trace_steps,
-                               int total_chains, double* e_cur, double* e_bar_out, unsigned long long* moves,
-                               unsigned long long* near_ties, double* min_margin, Record* ring) {
+__device__ __forceinline__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint32_t step,
+                                               int trace_steps, int total_chains, double* e_cur, double* e_bar_out,
+                                               unsigned long long* moves, unsigned long long* near_ties,
+                                               double* min_margin, Record* ring) {
   const bool moved = o.vstar != r;
   const bool near = o.margin < tol;
   e_cur[g] = o.e_new;
@@ -291,8 +293,9 @@ __global__ __launch_bounds__(256) void k_chain_means(double* __restrict__ trace,
 // ------------------------------------------------------------------- FP64 energy
 
 // E(s) = -scale * sum_{i<j} J_ij s_i s_j in FP64, one block (256 threads) per global
-// chain; optionally also the unscaled pair sum U = sum_{i<j} J_ij s_i s_j.  Thread t owns columns j = t, t+256, ...; row i is read coalesced; a
-// fixed-order tree combines the threads.
+// chain; optionally also the unscaled pair sum U = sum_{i<j} J_ij s_i s_j.  Thread t
+// owns columns j = t, t+256, ...; row i is read coalesced; a fixed-order tree combines
+// the threads.
 __global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, double* __restrict__ pair_sum,
                                                     char* __restrict__ ws, const Inst* __restrict__ insts,
                                                     const int32_t* __restrict__ chain_inst) {

@@ -87,3 +87,13 @@ def test_beta_schedule():
     assert b[0] == 0.1 and b[-1] == pytest.approx(3.0, rel=1e-15)
     assert np.all(np.diff(b) > 0)
     np.testing.assert_array_equal(inputs.beta_schedule(0.1, 3.0, 1000, 500, 10), b[500:510])
+
+
+def test_source_hash_ignores_comments():
+    """The counter record's source hash covers code only: a comment or blank-line edit
+    keeps it, a code edit changes it."""
+    a = "int x = 1;  // one\n\n// note\nint y;\n"
+    b = "int x = 1;\n// another note\nint y;   \n"
+    c = "int x = 2;\nint y;\n"
+    assert bench.code_lines(a) == bench.code_lines(b) == ["int x = 1;", "int y;"]
+    assert bench.code_lines(c) != bench.code_lines(a)
