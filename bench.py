@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "candidate configs scored/s + steps-to-thermalize, SK N=1024, mixed vs FP64"
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
+PEAK_CLOCK_GHZ = 2.4        # engine clock the published peaks assume
 TIMING_EVERY = 16           # the headline's scoring launches bracketed by events: every 16th
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 matrix peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
@@ -532,6 +533,8 @@ def main():
     ap.add_argument("--large-thermalize-steps", type=int, default=0,
                     help="steps of the N=8192 anneal study (0 skips it; 20000 is the workload's schedule)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ceiling-iters", type=int, default=12500,
+                    help="rounds of the matrix-core ceiling loop (0 skips it)")
     ap.add_argument("--set-variant", type=int, default=1, help="0 skips the set-variant timing")
     ap.add_argument("--small-steps", type=int, default=10000,
                     help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
@@ -566,6 +569,11 @@ def main():
         return
     split = _time_path(w, "split_bf16", args.steps, args.warmup, J, scale, every=TIMING_EVERY)
     _log(f"headline split: {split['total_ms'] / args.steps:.4f} ms/step")
+    ceiling = None
+    if args.ceiling_iters > 0:
+        from paper_2102_05613_amd import native
+        ceiling = native.mfma_ceiling(args.ceiling_iters)
+        _log(f"matrix-core ceiling: {ceiling['tflops']:.0f} TFLOP/s at {ceiling['clock_ghz']:.2f} GHz")
     fp64 = _time_path(w, "fp64", args.fp64_steps, min(args.warmup, 2), J, scale)
     _log(f"headline fp64: {fp64['total_ms'] / args.fp64_steps:.4f} ms/step")
 
@@ -598,7 +606,13 @@ def main():
                      "kernel": "k_score_split", "kernel_ms": split["score_ms_avg"],
                      "kernel_timing": f"HIP events on the scoring stream around every {TIMING_EVERY}th launch "
                                       f"of the timed steps ({split['timed_launches']} launches)",
-                     "flops_per_launch": flops_split},
+                     "flops_per_launch": flops_split,
+                     "ceiling": None if ceiling is None else {
+                         "kind": "plain loop of independent 32x32x16 BF16 MFMAs at the scoring kernel's occupancy "
+                                 "(libmc3ceil.so), run right after the timed steps",
+                         "tflops": ceiling["tflops"], "clock_ghz": ceiling["clock_ghz"],
+                         "peak_at_clock_tflops": PEAK_BF16_TFLOPS * ceiling["clock_ghz"] / PEAK_CLOCK_GHZ,
+                         "frac_of_ceiling": achieved / ceiling["tflops"] if ceiling["tflops"] > 0 else None}},
         "fp64_path": {"value": cand / (fp64_ms_step / 1e3), "unit": "candidates/s", "ms_per_step": fp64_ms_step,
                       "steps": args.fp64_steps, "kernel": "k_score_f64", "kernel_ms": fp64["score_ms_avg"],
                       "achieved_tflops": achieved64, "peak_tflops": PEAK_FP64_TFLOPS,

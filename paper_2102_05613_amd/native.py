@@ -13,6 +13,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmc3.so")
+CEIL_PATH = os.path.join(HERE, "libmc3ceil.so")
+CEIL_EXPORTS = ["mc3c_mfma_ceiling"]
 
 MC3_OK, MC3_E_ARG, MC3_E_DEVICE, MC3_E_STATE = 0, -1, -3, -4
 MC3_E_UNSUPPORTED, MC3_E_NUMERIC, MC3_E_WORKSPACE = -5, -6, -7
@@ -339,3 +341,32 @@ def spins_to_bits(spins: np.ndarray) -> np.ndarray:
     for i in range(N):
         out[..., i // 32] |= ((s[..., i] < 0).astype(np.uint32) << np.uint32(i % 32))
     return out
+
+
+_ceil = None
+
+
+def ceiling_lib() -> ctypes.CDLL:
+    """Load libmc3ceil.so (the matrix-core ceiling measurement); raises if it is missing."""
+    global _ceil
+    if _ceil is not None:
+        return _ceil
+    if not os.path.exists(CEIL_PATH):
+        raise ImportError(f"{CEIL_PATH} is not built; run paper_2102_05613_amd.build.build() first")
+    L = ctypes.CDLL(CEIL_PATH)
+    c = ctypes
+    L.mc3c_mfma_ceiling.argtypes = [c.c_int, c.c_int, c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_double)]
+    L.mc3c_mfma_ceiling.restype = c.c_int
+    _ceil = L
+    return L
+
+
+def mfma_ceiling(iters: int = 12500, blocks: int = 256, repeats: int = 3) -> dict:
+    """The attainable BF16 matrix-core rate (TFLOP/s, best of `repeats` launches) and the
+    engine clock (GHz, median over blocks) of a plain loop at the scoring kernel's
+    occupancy on the current device."""
+    t, g = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = ceiling_lib().mc3c_mfma_ceiling(iters, blocks, repeats, ctypes.byref(t), ctypes.byref(g))
+    if rc != 0:
+        raise RuntimeError(f"mc3c_mfma_ceiling failed ({rc})")
+    return {"tflops": t.value, "clock_ghz": g.value, "iters": iters, "blocks": blocks, "repeats": repeats}

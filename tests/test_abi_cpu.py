@@ -28,6 +28,19 @@ def _declared():
     return sorted(set(re.findall(r"\b(mc3_[a-z_0-9]+)\s*\(", txt)))
 
 
+def test_ceiling_library_exports_its_declared_symbol():
+    """libmc3ceil.so loads without a GPU and exports what include/mc3_ceiling.h declares."""
+    if not os.path.exists(native.CEIL_PATH):
+        from paper_2102_05613_amd import build
+        build.build()
+    txt = open(os.path.join(ROOT, "include", "mc3_ceiling.h")).read()
+    names = sorted(set(re.findall(r"\b(mc3c_[a-z_0-9]+)\s*\(", txt)))
+    assert names == sorted(native.CEIL_EXPORTS)
+    L = native.ceiling_lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
 def test_exports_every_declared_symbol(lib):
     names = _declared()
     assert names == sorted(native.EXPORTS)
