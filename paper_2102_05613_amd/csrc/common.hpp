@@ -77,7 +77,7 @@ __device__ __forceinline__ uint32_t* flips_at(char* ws, const Inst& in, uint32_t
 // A scoring work unit (row-block pair p, column tile ct of instance inst); inst < 0 is
 // an idle slot of the launch grid.
 struct Unit {
-  int32_t inst, p, ct, pad;
+  int32_t inst, p, ct, swap;   // swap: the split kernel takes row block NB-1-p first
 };
 
 // A proposal block: edges edge0 .. edge0 + count - 1 (flattened chain*M + e-1) of

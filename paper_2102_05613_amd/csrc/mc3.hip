@@ -237,12 +237,17 @@ Plan make_plan(const mc3_batch_config& cfg) {
   }
   // Scoring units.  One instance: XCD-major placement -- grid slot b runs on XCD b % 8
   // and the units of one XCD are consecutive in (pair, tile) order, so each XCD's L2
-  // holds the J rows of few pairs; trailing slots are idle.  A batch: all units by
-  // decreasing cost (stable, so instance order breaks ties), longest first.
-  struct Cand {
-    int inst, p, ct, cost;
+  // holds the J rows of few pairs; the tiles of a pair alternate which row block they
+  // take first; trailing slots are idle.  A batch: the pairs of every instance (each a
+  // group of its CT tiles, which read the same J rows) by decreasing cost, then
+  // decreasing CT (stable, so instance order breaks ties), longest first; eight groups
+  // at a time are laid out with stride 8 -- slot 8 j + x holds tile j of group x, so a
+  // group's tiles run together on one XCD and take the same row block first, and all
+  // but the first read of its J rows hit that XCD's L2; slots past a group's CT idle.
+  struct Group {
+    int inst, p, CT, cost;
   };
-  std::vector<Cand> all[kClasses];
+  std::vector<Group> groups[kClasses];
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
     h.cls = cfg.precision == MC3_SPLIT_BF16 ? split_class(h.B) : 0;
@@ -255,17 +260,29 @@ Plan make_plan(const mc3_batch_config& cfg) {
     for (int b = 0; b < 8 * per; ++b) {
       const int u = (b & 7) * per + (b >> 3);
       mc3::Unit un{-1, 0, 0, 0};
-      if (u < U) un = mc3::Unit{i, u / CT, u % CT, 0};
+      if (u < U) un = mc3::Unit{i, u / CT, u % CT, ((u / CT) + (u % CT)) & 1};
       pl.units_local.push_back(un);
     }
-    for (int u = 0; u < U; ++u) all[h.cls].push_back(Cand{i, u / CT, u % CT, unit_cost(h.NB, u / CT)});
+    for (int p = 0; p < h.P; ++p) groups[h.cls].push_back(Group{i, p, CT, unit_cost(h.NB, p)});
   }
   if (n == 1) {
     pl.units_global[pl.inst[0].cls] = pl.units_local;
   } else {
     for (int k = 0; k < kClasses; ++k) {
-      std::stable_sort(all[k].begin(), all[k].end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
-      for (const Cand& c : all[k]) pl.units_global[k].push_back(mc3::Unit{c.inst, c.p, c.ct, 0});
+      std::vector<Group>& gs = groups[k];
+      std::stable_sort(gs.begin(), gs.end(),
+                       [](const Group& a, const Group& b) { return a.cost != b.cost ? a.cost > b.cost : a.CT > b.CT; });
+      for (size_t g0 = 0; g0 < gs.size(); g0 += 8) {
+        const size_t ng = std::min<size_t>(8, gs.size() - g0);
+        int cmax = 0;
+        for (size_t x = 0; x < ng; ++x) cmax = std::max(cmax, gs[g0 + x].CT);
+        for (int j = 0; j < cmax; ++j)
+          for (size_t x = 0; x < 8; ++x) {
+            mc3::Unit un{-1, 0, 0, 0};
+            if (x < ng && j < gs[g0 + x].CT) un = mc3::Unit{gs[g0 + x].inst, gs[g0 + x].p, j, 0};
+            pl.units_global[k].push_back(un);
+          }
+      }
     }
   }
   // workspace layout

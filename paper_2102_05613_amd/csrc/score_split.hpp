@@ -206,7 +206,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
   double part[2] = {0.0, 0.0};
 
   const int nblk = (p == NB - 1 - p) ? 1 : 2;
-  const int first = ((p + ct) & 1) ? NB - 1 - p : p;
+  const int first = un.swap ? NB - 1 - p : p;
   const int second = NB - 1 - first;
   const int nA = (Np - first * kRowBlock) / 32;
   const int nTot = nA + (nblk == 2 ? (Np - second * kRowBlock) / 32 : 0);
