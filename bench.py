@@ -573,7 +573,9 @@ def main():
     if args.ceiling_iters > 0:
         from paper_2102_05613_amd import native
         ceiling = native.mfma_ceiling(args.ceiling_iters)
-        _log(f"matrix-core ceiling: {ceiling['tflops']:.0f} TFLOP/s at {ceiling['clock_ghz']:.2f} GHz")
+        ceiling["mix_tflops"] = {name: native.mfma_mix(m, args.ceiling_iters) for m, name in native.MFMA_MIXES.items()}
+        _log(f"matrix-core ceiling: {ceiling['tflops']:.0f} TFLOP/s at {ceiling['clock_ghz']:.2f} GHz; "
+             f"with the split kernel's traffic mix {ceiling['mix_tflops']['split_kernel']:.0f}")
     fp64 = _time_path(w, "fp64", args.fp64_steps, min(args.warmup, 2), J, scale)
     _log(f"headline fp64: {fp64['total_ms'] / args.fp64_steps:.4f} ms/step")
 
@@ -612,7 +614,13 @@ def main():
                                  "(libmc3ceil.so), run right after the timed steps",
                          "tflops": ceiling["tflops"], "clock_ghz": ceiling["clock_ghz"],
                          "peak_at_clock_tflops": PEAK_BF16_TFLOPS * ceiling["clock_ghz"] / PEAK_CLOCK_GHZ,
-                         "frac_of_ceiling": achieved / ceiling["tflops"] if ceiling["tflops"] > 0 else None}},
+                         "frac_of_ceiling": achieved / ceiling["tflops"] if ceiling["tflops"] > 0 else None,
+                         "mix_tflops": ceiling["mix_tflops"],
+                         "mix_note": "the same loop with, per 64 MFMAs, the split kernel's other traffic (32 LDS "
+                                     "128-bit reads, 72 VALU, 5 global loads, 1 barrier), a 64x128 wave tile's "
+                                     "(16, 120, 11, 1), or LDS reads alone",
+                         "frac_of_split_mix": (achieved / ceiling["mix_tflops"]["split_kernel"]
+                                               if ceiling["mix_tflops"]["split_kernel"] > 0 else None)}},
         "fp64_path": {"value": cand / (fp64_ms_step / 1e3), "unit": "candidates/s", "ms_per_step": fp64_ms_step,
                       "steps": args.fp64_steps, "kernel": "k_score_f64", "kernel_ms": fp64["score_ms_avg"],
                       "achieved_tflops": achieved64, "peak_tflops": PEAK_FP64_TFLOPS,

@@ -28,6 +28,21 @@ extern "C" {
  * iters < 1, blocks < 1 or repeats < 1, or a HIP error code. */
 int mc3c_mfma_ceiling(int iters, int blocks, int repeats, double* tflops, double* ghz);
 
+/* The same kind of loop (256 blocks of 512 threads, operands of the same kind) with
+ * the scoring kernel's other traffic mixed in, per round of 64 matrix-core operations:
+ *   mix 0: none;
+ *   mix 1: the split scoring kernel's own mix, scaled from its 48 MFMAs a wave per
+ *          32-k chunk: 32 LDS reads of 128 bits, 72 VALU operations, 5 global 32-bit
+ *          loads, 1 workgroup barrier;
+ *   mix 2: the mix of a 64-row x 128-column wave tile (half the LDS reads, twice the
+ *          B expansion and word loads): 16, 120, 11, 1;
+ *   mix 3: 32 LDS reads only;  mix 4: 16 LDS reads only.
+ * One untimed launch, then `repeats` timed launches of `iters` rounds; tflops (out,
+ * host): the best rate, timed with HIP events.  Allocates and frees its own device
+ * buffers.  Returns 0, -1 for a mix outside 0..4, iters < 1 or repeats < 1, or a HIP
+ * error code. */
+int mc3c_mfma_mix(int mix, int iters, int repeats, double* tflops);
+
 #ifdef __cplusplus
 }
 #endif

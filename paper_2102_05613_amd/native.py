@@ -14,7 +14,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmc3.so")
 CEIL_PATH = os.path.join(HERE, "libmc3ceil.so")
-CEIL_EXPORTS = ["mc3c_mfma_ceiling"]
+CEIL_EXPORTS = ["mc3c_mfma_ceiling", "mc3c_mfma_mix"]
+MFMA_MIXES = {0: "none", 1: "split_kernel", 2: "tile_64x128", 3: "lds_reads_32", 4: "lds_reads_16"}
 
 MC3_OK, MC3_E_ARG, MC3_E_DEVICE, MC3_E_STATE = 0, -1, -3, -4
 MC3_E_UNSUPPORTED, MC3_E_NUMERIC, MC3_E_WORKSPACE = -5, -6, -7
@@ -357,6 +358,8 @@ def ceiling_lib() -> ctypes.CDLL:
     c = ctypes
     L.mc3c_mfma_ceiling.argtypes = [c.c_int, c.c_int, c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_double)]
     L.mc3c_mfma_ceiling.restype = c.c_int
+    L.mc3c_mfma_mix.argtypes = [c.c_int, c.c_int, c.c_int, c.POINTER(c.c_double)]
+    L.mc3c_mfma_mix.restype = c.c_int
     _ceil = L
     return L
 
@@ -370,3 +373,13 @@ def mfma_ceiling(iters: int = 12500, blocks: int = 256, repeats: int = 3) -> dic
     if rc != 0:
         raise RuntimeError(f"mc3c_mfma_ceiling failed ({rc})")
     return {"tflops": t.value, "clock_ghz": g.value, "iters": iters, "blocks": blocks, "repeats": repeats}
+
+
+def mfma_mix(mix: int, iters: int = 12500, repeats: int = 3) -> float:
+    """TFLOP/s of the matrix-core loop with the traffic mix `mix` (see MFMA_MIXES and
+    include/mc3_ceiling.h) per round of 64 MFMAs, best of `repeats` launches."""
+    t = ctypes.c_double(0.0)
+    rc = ceiling_lib().mc3c_mfma_mix(mix, iters, repeats, ctypes.byref(t))
+    if rc != 0:
+        raise RuntimeError(f"mc3c_mfma_mix failed ({rc})")
+    return t.value
