@@ -322,6 +322,9 @@ def _large_workload(args):
     return out
 
 
+SPLIT_RTOL = 1e-4   # split-BF16 energies against FP64: relative, with the same absolute floor
+
+
 def _precision_report(w, J, scale, step=3):
     """Relative error of the split-BF16 energies of every candidate of one step against
     the FP64 scorer's energies of the same candidates (same seed and step; the FP64
@@ -344,7 +347,12 @@ def _precision_report(w, J, scale, step=3):
     # differences between nodes of one chain (what the weights see): E_v - E of the chain's first column
     ds, d64 = (E[p].reshape(w.chains, w.M) for p in ("split_bf16", "fp64"))
     dd = np.abs((ds - ds[:, :1]) - (d64 - d64[:, :1]))[:, 1:]
-    return {"candidates": int(rel.size), "rel_max": float(rel.max()), "rel_p9999": float(np.quantile(rel, 0.9999)),
+    # the split path's tolerance, 1e-4 relative with an absolute floor of 1e-4 (the
+    # parity tests' rtol and atol): |E_split - E_fp64| <= 1e-4 (|E_fp64| + 1)
+    over_tol = d / (SPLIT_RTOL * (np.abs(E["fp64"]) + 1.0))
+    return {"candidates": int(rel.size), "tolerance": "|E_split - E_fp64| <= 1e-4 (|E_fp64| + 1)",
+            "max_err_over_tolerance": float(over_tol.max()), "within_tolerance": bool(over_tol.max() <= 1.0),
+            "rel_max": float(rel.max()), "rel_p9999": float(np.quantile(rel, 0.9999)),
             "rel_mean": float(rel.mean()), "abs_max": float(d.max()), "abs_p9999": float(np.quantile(d, 0.9999)),
             "abs_mean": float(d.mean()), "energy_abs_mean": float(np.abs(E["fp64"]).mean()),
             "node_difference_abs_max": float(dd.max()), "node_difference_abs_p9999": float(np.quantile(dd, 0.9999)),
