@@ -281,6 +281,20 @@ mc3_status mc3_select(mc3_ctx* ctx, uint32_t step, double beta);
  * the results are those of the step-by-step calls. */
 mc3_status mc3_step_n(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
 
+/* The steps of mc3_step_n (same arguments, same results bit for bit), replayed from a
+ * HIP graph: the launches of L steps (L a multiple of the proposal group of up to 16
+ * steps, of the proposal ring's length and of 2, at most 272) are captured once on a
+ * stream of the context's own and replayed on the context's stream; a step counter in
+ * the workspace gives the replayed proposal, selection and means kernels their step,
+ * and the selection forms beta_t from (beta0, beta1, total) on the device in the
+ * host's operation order.  The capture is kept for later calls with the same schedule
+ * and the same step0 modulo L.  Runs of fewer than L + 16 steps, and the last 16 to
+ * L + 15 steps of a run, are launched as in mc3_step_n; with the field-update scorer
+ * this is mc3_step_n.  Scoring launches inside replays are not timed
+ * (mc3_timing_enable).  For step loops whose launches, not their kernels, take the
+ * time (small N and M). */
+mc3_status mc3_step_n_graph(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
+
 /* The steps of mc3_step_n, launched instance by instance (propose, score and select
  * of instance 0, then of instance 1, ...) on the context's stream, without the
  * overlap of proposal and scoring.  Same results as mc3_step_n; it is the cost of

@@ -60,6 +60,7 @@ struct Plan {
   std::vector<mc3::PBlock> pblocks;
   std::vector<int32_t> chain_inst;
   size_t insts = 0, chain_inst_off = 0, units_global_off[kClasses] = {0, 0, 0}, units_local_off = 0, pblocks_off = 0;
+  size_t clock = 0;   // the step clock of replayed graphs (one uint32)
   size_t e_cur = 0, e_bar = 0, roots = 0, candT = 0, ring = 0, means = 0, moves = 0, near = 0, minm = 0, drift = 0,
          erecomp = 0, u_cur = 0, vals = 0, total = 0;
 };
@@ -298,6 +299,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
   for (int k = 0; k < kClasses; ++k) pl.units_global_off[k] = take(pl.units_global[k].size() * sizeof(mc3::Unit));
   pl.units_local_off = take(pl.units_local.size() * sizeof(mc3::Unit));
   pl.pblocks_off = take(pl.pblocks.size() * sizeof(mc3::PBlock));
+  pl.clock = take(4);
   pl.e_cur = take(C * 8);
   pl.e_bar = take(C * 8);
   pl.roots = take((size_t)pl.nslots * C * 4);
@@ -379,6 +381,12 @@ struct mc3_ctx {
   size_t t_next = 0;
   double t_total_ms = 0.0;
   int64_t t_count = 0;
+  // mc3_step_n_graph: the captured body, the stream it is captured on, and what it was
+  // captured for (schedule, and the first step's residue modulo the body length)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_beta0 = 0.0, g_beta1 = 0.0;
+  int64_t g_total = 0, g_len = 0, g_phase = -1;
   std::string err;
 
   template <class T>
@@ -527,18 +535,19 @@ mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, 
 
 // Proposal blocks [b0, b0 + nb) of the block table for steps step0 .. step0+nsteps-1
 // (at most nslots - 1 of them); with write_base, also the base words of step0.
-mc3_status launch_propose(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base, int b0, int nb) {
+mc3_status launch_propose(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base, int b0, int nb,
+                          const uint32_t* clk = nullptr) {
   const Plan& pl = c->pl;
   const size_t lds = (size_t)pl.prop_rows * pl.prop_T * pl.prop_stride * 4;
   hipLaunchKernelGGL(mc3::k_propose, dim3(nb, nsteps), dim3(pl.prop_T), lds, c->stream, c->ws, c->insts(),
                      c->at<const mc3::PBlock>(pl.pblocks_off) + b0, c->at<int32_t>(pl.roots), pl.total_chains,
                      (uint32_t)pl.nslots, write_base ? 1 : 0, pl.prop_stride, pl.prop_rows, c->metropolis() ? 1 : 0,
-                     c->key(), c->cfg.chain_base, step0);
+                     c->key(), c->cfg.chain_base, step0, clk);
   return check_launch(c, "propose kernel");
 }
 
-mc3_status propose_all(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base) {
-  return launch_propose(c, step0, nsteps, write_base, 0, (int)c->pl.pblocks.size());
+mc3_status propose_all(mc3_ctx* c, uint32_t step0, int nsteps, bool write_base, const uint32_t* clk = nullptr) {
+  return launch_propose(c, step0, nsteps, write_base, 0, (int)c->pl.pblocks.size(), clk);
 }
 
 mc3_status timing_collect(mc3_ctx* c, size_t i) {
@@ -614,28 +623,44 @@ mc3_status do_score(mc3_ctx* c, double* E_out) {
   return MC3_OK;
 }
 
+// The step clock of a captured graph body: its kernels take steps relative to `base`
+// and add the clock's value, and the selection forms beta from the schedule.
+struct ClockArg {
+  const uint32_t* clk = nullptr;
+  uint32_t base = 0;
+  double beta0 = 0.0, beta1 = 0.0;
+  int64_t total = 0;
+};
+
 // Selection of global chains [g0, g0 + n) at `step`; with next_base, also the base
-// words of step+1 (whose flip sets and roots must already be proposed).
-mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n) {
+// words of step+1 (whose flip sets and roots must already be proposed).  Ring slots are
+// those of `step` itself; with a clock the kernel takes step - base.
+mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n,
+                         const ClockArg& ck = ClockArg{}) {
   const Plan& pl = c->pl;
   const size_t lds = (size_t)(pl.Mmax + 1) * 16;
   hipLaunchKernelGGL(mc3::k_select, dim3(n), dim3(256), lds, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
                      pl.total_chains, c->at<double>(pl.e_cur), c->roots(step), c->roots(step + 1u),
                      c->at<mc3::Record>(pl.ring), c->at<unsigned long long>(pl.moves),
                      c->at<unsigned long long>(pl.near), c->at<double>(pl.minm), c->at<double>(pl.e_bar),
-                     c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base, step, c->slot(step),
-                     c->slot(step + 1u), c->cfg.trace_steps, next_base ? 1 : 0);
+                     c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base,
+                     ck.clk ? step - ck.base : step, c->slot(step), c->slot(step + 1u), c->cfg.trace_steps,
+                     next_base ? 1 : 0, ck.clk, ck.beta0, ck.beta1, (long long)ck.total);
   return check_launch(c, "select kernel");
 }
 
-mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
+mc3_status launch_means(mc3_ctx* c, uint32_t step, const ClockArg& ck = ClockArg{}) {
   const Plan& pl = c->pl;
-  if (c->cfg.mean_steps > 0) {
-    hipLaunchKernelGGL(mc3::k_chain_means, dim3(1), dim3(256), 0, c->stream, c->at<double>(pl.means),
-                       c->at<const double>(pl.e_cur), c->at<const double>(pl.e_bar), pl.total_chains,
-                       step % (uint32_t)c->cfg.mean_steps, step);
-    MC3_TRY(check_launch(c, "means kernel"));
-  }
+  if (c->cfg.mean_steps <= 0) return MC3_OK;
+  hipLaunchKernelGGL(mc3::k_chain_means, dim3(1), dim3(256), 0, c->stream, c->at<double>(pl.means),
+                     c->at<const double>(pl.e_cur), c->at<const double>(pl.e_bar), pl.total_chains,
+                     step % (uint32_t)c->cfg.mean_steps, ck.clk ? step - ck.base : step, ck.clk,
+                     (uint32_t)c->cfg.mean_steps);
+  return check_launch(c, "means kernel");
+}
+
+mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
+  MC3_TRY(launch_means(c, step));
   c->have_proposal = next_base;
   c->have_scores = false;
   if (next_base) c->proposal_step = step + 1u;
@@ -672,6 +697,108 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
     if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
     MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last));
   }
+  c->have_proposal = false;
+  return MC3_OK;
+}
+
+// Steps t0 .. t0+n-1 of mc3_step_n whose first group of proposals is already drawn.
+mc3_status step_groups(mc3_ctx* c, uint32_t t0, int64_t n, double beta0, double beta1, int64_t total) {
+  const int64_t K = c->pl.ahead;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint32_t t = t0 + (uint32_t)i;
+    const bool last = i + 1 == n;
+    MC3_TRY(do_score(c, nullptr));
+    if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
+    MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last));
+  }
+  return MC3_OK;
+}
+
+int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
+
+// Body length of a replayed graph: a multiple of the proposal group (K), of the ring
+// (nslots) and of 2 (the base words alternate), so that every captured launch finds
+// its ring slots and base words at the same place on every replay.
+int64_t graph_body(const Plan& pl) {
+  const int64_t K = pl.ahead, S = pl.nslots;
+  const int64_t KS = K / gcd64(K, S) * S;
+  return KS % 2 ? 2 * KS : KS;
+}
+
+// Capture the body for steps a .. a+L-1 on the capture stream: per step the scoring,
+// every K-th step the next group's proposals, the selection (always followed by a
+// step: next_base), the means; then the clock advances by L.
+mc3_status capture_body(mc3_ctx* c, uint32_t a, int64_t L, double beta0, double beta1, int64_t total) {
+  const int64_t K = c->pl.ahead;
+  const ClockArg ck{c->at<const uint32_t>(c->pl.clock), a, beta0, beta1, total};
+  hipStream_t user = c->stream;
+  const bool timing = c->timing;
+  c->stream = c->cap;
+  c->timing = false;
+  hipGraph_t g = nullptr;
+  mc3_status st = hip_ok(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "graph capture");
+  if (st == MC3_OK) {
+    for (int64_t j = 0; j < L && st == MC3_OK; ++j) {
+      const uint32_t t = a + (uint32_t)j;
+      c->proposal_step = t;
+      st = do_score(c, nullptr);
+      if (st == MC3_OK && (j + 1) % K == 0) st = propose_all(c, (uint32_t)(j + 1), (int)K, false, ck.clk);
+      if (st == MC3_OK) st = launch_select(c, t, 0.0, true, 0, c->pl.total_chains, ck);
+      if (st == MC3_OK) st = launch_means(c, t, ck);
+    }
+    if (st == MC3_OK) {
+      hipLaunchKernelGGL(mc3::k_clock, dim3(1), dim3(64), 0, c->stream, c->at<uint32_t>(c->pl.clock), (uint32_t)L, 1);
+      st = check_launch(c, "clock kernel");
+    }
+    const hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (st == MC3_OK) st = hip_ok(c, e, "graph capture");
+  }
+  c->stream = user;
+  c->timing = timing;
+  if (st == MC3_OK) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    st = hip_ok(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (st != MC3_OK) {
+    c->g_phase = -1;
+    return st;
+  }
+  c->g_beta0 = beta0;
+  c->g_beta1 = beta1;
+  c->g_total = total;
+  c->g_len = L;
+  c->g_phase = (int64_t)(a % (uint32_t)L);
+  return MC3_OK;
+}
+
+// mc3_step_n through a replayed graph: the first group's proposals, then R replays of
+// the captured L-step body (captured once per schedule and step residue modulo L), then
+// the remaining n - R L >= K steps launch by launch.  The same launches in the same
+// order as do_step_n, so the same results.
+mc3_status do_step_n_graph(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
+  const Plan& pl = c->pl;
+  const int64_t K = pl.ahead, L = graph_body(pl);
+  const int64_t R = n >= L + K ? (n - K) / L : 0;
+  if (R == 0) return do_step_n(c, step0, n, beta0, beta1, total);
+  MC3_TRY(propose_all(c, step0, (int)K, true));
+  c->have_proposal = true;
+  c->proposal_step = step0;
+  if (!c->cap) MC3_TRY(hip_ok(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "capture stream"));
+  if (!c->gexec || c->g_len != L || c->g_phase != (int64_t)(step0 % (uint32_t)L) || c->g_beta0 != beta0 ||
+      c->g_beta1 != beta1 || c->g_total != total)
+    MC3_TRY(capture_body(c, step0, L, beta0, beta1, total));
+  // the body's launches take steps relative to its first; replay r starts at step0 + r L
+  hipLaunchKernelGGL(mc3::k_clock, dim3(1), dim3(64), 0, c->stream, c->at<uint32_t>(pl.clock), step0, 0);
+  MC3_TRY(check_launch(c, "clock kernel"));
+  for (int64_t r = 0; r < R; ++r) MC3_TRY(hip_ok(c, hipGraphLaunch(c->gexec, c->stream), "graph launch"));
+  const uint32_t t1 = step0 + (uint32_t)(R * L);
+  c->steps_done += R * L;
+  c->have_proposal = true;
+  c->proposal_step = t1;
+  c->have_scores = false;
+  MC3_TRY(step_groups(c, t1, n - R * L, beta0, beta1, total));
   c->have_proposal = false;
   return MC3_OK;
 }
@@ -890,6 +1017,8 @@ mc3_status mc3_destroy(mc3_ctx* ctx) {
   if (!ctx) return MC3_E_ARG;
   for (hipEvent_t e : ctx->t_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return MC3_OK;
 }
@@ -968,6 +1097,12 @@ mc3_status mc3_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, doubl
   MC3_TRY(step_args(c, step0, n, beta0, beta1));
   if (c->pl.delta) return do_step_n_delta(c, step0, n, beta0, beta1, total);
   return do_step_n(c, step0, n, beta0, beta1, total);
+}
+
+mc3_status mc3_step_n_graph(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
+  MC3_TRY(step_args(c, step0, n, beta0, beta1));
+  if (c->pl.delta) return do_step_n_delta(c, step0, n, beta0, beta1, total);
+  return do_step_n_graph(c, step0, n, beta0, beta1, total);
 }
 
 mc3_status mc3_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1,

@@ -130,16 +130,18 @@ __device__ __forceinline__ int flip_count(Key key, uint32_t gc, uint32_t step, u
 // draws F_v into its row, and the path sets follow by pointer jumping, P(v) ^= P(a(v))
 // and a(v) <- a(a(v)) starting from a(v) = parent(v), over ceil(log2(depth)) rounds
 // between the two row sets (no ordering by size there: each thread draws one set).
+// With a step clock (clk non-null, replayed graphs) the steps start at *clk + step0.
 // Dynamic LDS: rows * blockDim.x * stride words.
 __global__ void k_propose(char* __restrict__ ws, const Inst* __restrict__ insts, const PBlock* __restrict__ blocks,
                           int32_t* __restrict__ roots_ring, int total_chains, uint32_t nslots, int write_base,
-                          int stride, int rows, int metropolis, Key key, uint32_t chain_base, uint32_t step0) {
+                          int stride, int rows, int metropolis, Key key, uint32_t chain_base, uint32_t step0,
+                          const uint32_t* __restrict__ clk) {
   extern __shared__ uint32_t lds_bits[];
   __shared__ int bucket_n[16], bucket_at[16];
   __shared__ int order[256];
   __shared__ int anc_row[256];
   const int T = blockDim.x, tid = threadIdx.x;
-  const uint32_t step = step0 + blockIdx.y;
+  const uint32_t step = (clk ? *clk : 0u) + step0 + blockIdx.y;
   const uint32_t slot = step % nslots;
   const PBlock blk0 = blocks[blockIdx.x];
   const Inst& in = insts[blk0.inst];

@@ -204,7 +204,9 @@ struct ChainWords {
 };
 
 // One block of 256 threads per chain: node rule (MCMCMC) or Metropolis rate, move,
-// record, and (next_base) the base words of step t+1.
+// record, and (next_base) the base words of step t+1.  With a step clock (clk non-null,
+// replayed graphs) the step is *clk + step and beta that step's value of the linear
+// schedule beta0 -> beta1 over `total` steps, in the host's operation order.
 //   1. all threads: the node energies (node_energies);
 //   2. wave 0: the rule (apply_rule) and the bookkeeping;
 //   3. thread w: the new state's word and the next step's base word (ChainWords),
@@ -216,8 +218,13 @@ __global__ __launch_bounds__(256) void k_select(
     const int32_t* __restrict__ roots_next_all, Record* __restrict__ ring, unsigned long long* __restrict__ moves,
     unsigned long long* __restrict__ near_ties, double* __restrict__ min_margin, double* __restrict__ e_bar_out,
     int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, uint32_t slot,
-    uint32_t slot_next, int trace_steps, int next_base) {
+    uint32_t slot_next, int trace_steps, int next_base, const uint32_t* __restrict__ clk, double beta0,
+    double beta1, long long total) {
   extern __shared__ double sel_lds[];
+  if (clk) {
+    step += *clk;
+    beta = total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)step / (double)(total - 1));
+  }
   __shared__ int sh_vstar;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = chain_off + blockIdx.x;   // global chain
@@ -263,10 +270,16 @@ __global__ __launch_bounds__(256) void k_select(
 // ------------------------------------------------------------------- means trace
 
 // Chain means of the current and node-weighted energies of this step, one block of
-// 256 threads, fixed-order tree: trace[slot] = {step, mean e_cur, mean e_bar}.
+// 256 threads, fixed-order tree: trace[slot] = {step, mean e_cur, mean e_bar}.  With a
+// step clock the step is *clk + step and the slot step % mean_steps.
 __global__ __launch_bounds__(256) void k_chain_means(double* __restrict__ trace, const double* __restrict__ e_cur,
                                                      const double* __restrict__ e_bar, int chains, uint32_t slot,
-                                                     uint32_t step) {
+                                                     uint32_t step, const uint32_t* __restrict__ clk,
+                                                     uint32_t mean_steps) {
+  if (clk) {
+    step += *clk;
+    slot = step % mean_steps;
+  }
   __shared__ double red[2][256];
   double a = 0.0, b = 0.0;
   for (int c = threadIdx.x; c < chains; c += 256) {
@@ -288,6 +301,13 @@ __global__ __launch_bounds__(256) void k_chain_means(double* __restrict__ trace,
     trace[3 * (size_t)slot + 1] = red[0][0] / (double)chains;
     trace[3 * (size_t)slot + 2] = red[1][0] / (double)chains;
   }
+}
+
+// ------------------------------------------------------------------- step clock
+
+// The step clock of replayed graphs: clk = value (add = 0) or clk += value (one thread).
+__global__ void k_clock(uint32_t* __restrict__ clk, uint32_t value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clk[0] = add ? clk[0] + value : value;
 }
 
 // ------------------------------------------------------------------- FP64 energy

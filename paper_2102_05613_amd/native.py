@@ -37,7 +37,7 @@ EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_coupling
            "mc3_propose", "mc3_score_candidates", "mc3_select", "mc3_step_n", "mc3_recompute", "mc3_measure",
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
            "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
-           "mc3_init_couplings_instance", "mc3_step_n_per_instance", "mc3_checkpoint_save",
+           "mc3_init_couplings_instance", "mc3_step_n_per_instance", "mc3_step_n_graph", "mc3_checkpoint_save",
            "mc3_checkpoint_load", "mc3_set_generation"]
 
 
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
     L.mc3_batch_create.argtypes = [P(BatchConfig), vp, c.c_size_t, vp, P(vp)]
     L.mc3_init_couplings_instance.argtypes = [vp, c.c_int32, P(c.c_double), c.c_int64, c.c_double]
     L.mc3_step_n_per_instance.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
+    L.mc3_step_n_graph.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
     L.mc3_checkpoint_save.argtypes = [vp, vp, P(c.c_size_t)]
     L.mc3_checkpoint_load.argtypes = [vp, vp, c.c_size_t]
     L.mc3_set_generation.argtypes = [vp, c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
@@ -245,6 +246,9 @@ class Context:
 
     def step_n(self, step0: int, n: int, beta0: float, beta1: float, total: int):
         self._check(lib().mc3_step_n(self.h, step0, n, float(beta0), float(beta1), total), "mc3_step_n")
+
+    def step_n_graph(self, step0: int, n: int, beta0: float, beta1: float, total: int):
+        self._check(lib().mc3_step_n_graph(self.h, step0, n, float(beta0), float(beta1), total), "mc3_step_n_graph")
 
     def step_n_per_instance(self, step0: int, n: int, beta0: float, beta1: float, total: int):
         self._check(lib().mc3_step_n_per_instance(self.h, step0, n, float(beta0), float(beta1), total),
