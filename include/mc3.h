@@ -149,6 +149,11 @@ typedef struct {
     int32_t law;             /* mc3_graph_law */
     const double* law_table; /* law TABLE: host [M+1] root weights, copied by mc3_create;
                                 otherwise ignored */
+    int32_t tile_cols;       /* split-BF16 scoring tile width (columns per work unit): 0 = by
+                                the instance's column count (512 from 2048 columns up, 128 up
+                                to 128, 256 between); 128, 256 or 512 = that width.  Results
+                                do not depend on it.  Ignored by the FP64 and field-update
+                                scorers; any other value is MC3_E_ARG */
 } mc3_config;
 
 /* One instance of a batch: its size, graph size, chains and flip-set range, with the
@@ -178,6 +183,8 @@ typedef struct {
     const double* law_table; /* law TABLE: host root weights of every instance, instance i's
                                 M_i+1 values after those of instances 0..i-1; copied by
                                 mc3_batch_create; otherwise ignored */
+    int32_t tile_cols;       /* split-BF16 scoring tile width of every instance, as in
+                                mc3_config */
 } mc3_batch_config;
 
 /* Per-step, per-chain record (40 bytes). */
@@ -211,7 +218,8 @@ mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes);
 /* Create a context on the current HIP device.  `workspace` is a device pointer of at
  * least mc3_workspace_size bytes, borrowed for the lifetime of the context; `stream`
  * is a hipStream_t (NULL = default stream), borrowed likewise; every kernel of the
- * context runs on it.  Performs no device memory allocation and creates no stream.
+ * context runs on it.  Performs no device memory allocation and creates no stream
+ * (mc3_step_n_graph later creates one to capture on).
  * Validates the configuration before any HIP call. */
 mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out);
 

@@ -106,6 +106,8 @@ const char* validate_batch(const mc3_batch_config* c) {
   if (c->law == MC3_LAW_TABLE && !c->law_table) return "law TABLE needs law_table";
   if (c->trace_steps < 0) return "trace_steps must be >= 0";
   if (c->mean_steps < 0) return "mean_steps must be >= 0";
+  if (c->tile_cols != 0 && c->tile_cols != 128 && c->tile_cols != 256 && c->tile_cols != 512)
+    return "tile_cols must be 0, 128, 256 or 512";
   if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
   long long chains = 0, cols = 0;
   size_t table_at = 0;
@@ -167,6 +169,7 @@ int resolve_delta(const mc3_batch_config& c, size_t* lds) {
 // (2 waves) for at most 128 columns, 256 otherwise.
 int split_class(int B) { return B >= 2048 ? 2 : (B > 128 ? 1 : 0); }
 int class_waves(int cls) { return 2 << cls; }
+int tile_class(int tile_cols) { return tile_cols == 512 ? 2 : (tile_cols == 256 ? 1 : 0); }
 
 // Cost of a scoring unit in 128x128 K blocks: the pair (p, NB-1-p) spans NB+1 blocks
 // of the upper triangle, the self-paired middle block row NB-p.
@@ -251,7 +254,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
   std::vector<Group> groups[kClasses];
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
-    h.cls = cfg.precision == MC3_SPLIT_BF16 ? split_class(h.B) : 0;
+    h.cls = cfg.precision != MC3_SPLIT_BF16 ? 0 : cfg.tile_cols ? tile_class(cfg.tile_cols) : split_class(h.B);
     const int TN = cfg.precision == MC3_SPLIT_BF16 ? 64 * class_waves(h.cls) : kTileF64;
     const int CT = (h.B + TN - 1) / TN;  // tiles holding at least one real column
     const int U = h.P * CT;
@@ -356,6 +359,7 @@ mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
   b.arity = c->arity;
   b.law = c->law;
   b.law_table = c->law_table;
+  b.tile_cols = c->tile_cols;
   return b;
 }
 

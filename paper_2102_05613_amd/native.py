@@ -47,7 +47,8 @@ class Config(ctypes.Structure):
                 ("rule", ctypes.c_int32), ("trace_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("chain_base", ctypes.c_uint32), ("mean_steps", ctypes.c_int32),
                 ("near_tie_tol", ctypes.c_double), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
-                ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double))]
+                ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double)),
+                ("tile_cols", ctypes.c_int32)]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -60,7 +61,8 @@ class BatchConfig(ctypes.Structure):
                 ("trace_steps", ctypes.c_int32), ("mean_steps", ctypes.c_int32), ("chain_base", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("near_tie_tol", ctypes.c_double),
                 ("instances", ctypes.POINTER(InstanceDesc)), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
-                ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double))]
+                ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double)),
+                ("tile_cols", ctypes.c_int32)]
 
 
 class Summary(ctypes.Structure):
@@ -130,13 +132,14 @@ def lib() -> ctypes.CDLL:
 def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: str = "split_bf16",
                 rule: str = "mcmcmc", trace_steps: int = 0, seed: int = 0, chain_base: int = 0,
                 near_tie_tol: float = -1.0, mean_steps: int = 0, scorer: str = "gemm", arity: int = 0,
-                law: str = "uniform", law_table=None) -> Config:
+                law: str = "uniform", law_table=None, tile_cols: int = 0) -> Config:
     """arity 0: the M-ary star; law "line" (arity 1): the line-graph addition process;
-    law "table": root weights law_table[0..M]."""
+    law "table": root weights law_table[0..M]; tile_cols 0: the split scoring tile width
+    by column count, else 128, 256 or 512."""
     tab = _table(law_table)
     cfg = Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base,
                  mean_steps, near_tie_tol, SCORERS[scorer], arity, LAWS[law],
-                 None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                 None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols)
     cfg._keep_table = tab   # the table lives as long as the config
     return cfg
 
@@ -150,14 +153,15 @@ def _table(law_table):
 def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcmcmc", trace_steps: int = 0,
                       seed: int = 0, chain_base: int = 0, near_tie_tol: float = -1.0,
                       mean_steps: int = 0, scorer: str = "gemm", arity: int = 0, law: str = "uniform",
-                      law_table=None) -> BatchConfig:
+                      law_table=None, tile_cols: int = 0) -> BatchConfig:
     """instances: sequence of (N, M, chains, kmin, kmax); law "table": law_table holds
-    the root weights of every instance, M_i+1 values each, in instance order."""
+    the root weights of every instance, M_i+1 values each, in instance order;
+    tile_cols as in make_config."""
     arr = (InstanceDesc * len(instances))(*[InstanceDesc(*map(int, d)) for d in instances])
     tab = _table(law_table)
     cfg = BatchConfig(len(instances), PRECISIONS[precision], RULES[rule], trace_steps, mean_steps, chain_base, seed,
                       near_tie_tol, ctypes.cast(arr, ctypes.POINTER(InstanceDesc)), SCORERS[scorer], arity, LAWS[law],
-                      None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                      None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols)
     cfg._keep = arr   # the descriptor array lives as long as the config
     cfg._keep_table = tab
     return cfg
