@@ -206,15 +206,16 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def _timed_steps(ctx, step0, n, beta0, beta1, total):
-    """Wall time (torch events on the context's stream) of n steps of mc3_step_n."""
+def _timed_steps(ctx, step0, n, beta0, beta1, total, graph=False):
+    """Wall time (torch events on the context's stream) of n steps of mc3_step_n, or of
+    mc3_step_n_graph (the same steps replayed from a captured HIP graph)."""
     import torch
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
-    ctx.step_n(step0, n, beta0, beta1, total)
+    (ctx.step_n_graph if graph else ctx.step_n)(step0, n, beta0, beta1, total)
     end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end)
@@ -230,13 +231,16 @@ def _small_workload(w, steps):
     out = {"N": w.N, "chains": w.chains, "precision": w.precision, "steps": steps,
            "beta": [w.beta0, w.beta1], "bound": "launch latency (no roofline applies)",
            "scorers": {"gemm": "pair sums on the matrix cores, one scoring and one selection launch per step",
+                       "gemm_graph": "the same launches replayed from a captured HIP graph (mc3_step_n_graph)",
                        "delta": "FP64 field update, every step of a chain in one persistent workgroup"}}
     for name, rule, M, kmin, kmax in variants:
         out[name] = {"M": M}
-        for scorer in ("gemm", "delta"):
-            ctx = _context(w, w.precision, rule, M, kmin, kmax, J, scale, scorer=scorer)
+        for scorer, graph in (("gemm", False), ("gemm_graph", True), ("delta", False)):
+            ctx = _context(w, w.precision, rule, M, kmin, kmax, J, scale, scorer=scorer.split("_")[0])
             ctx.step_n(0, 100, w.beta0, w.beta0, 1)
-            ms = _timed_steps(ctx, 100, steps, w.beta0, w.beta1, w.steps)
+            if graph:   # capture outside the timed steps: same schedule, same first step
+                ctx.step_n_graph(100, 300, w.beta0, w.beta1, w.steps)
+            ms = _timed_steps(ctx, 100, steps, w.beta0, w.beta1, w.steps, graph=graph)
             ctx.close()
             out[name][scorer] = {"us_per_step": ms * 1e3 / steps,
                                  "candidates_per_s": w.chains * M * steps / (ms / 1e3)}
