@@ -22,6 +22,7 @@ frequencies; long-run Boltzmann averages by exhaustive enumeration.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional
@@ -98,6 +99,8 @@ def lib():
         L.mc3o_root_table.restype = i32
         L.mc3o_log_prior_table.argtypes = [i32, P(u64), P(dbl)]
         L.mc3o_set_gen_brute.argtypes = [i32, P(dbl), u32, P(i32)]
+        L.mc3o_couplings.argtypes = [i32, i32, u64, P(dbl)]
+        L.mc3o_couplings.restype = ctypes.c_int
         L.mc3o_set_gen_brute.restype = dbl
         L.mc3o_build_nodes.argtypes = [i32, i32, i32, i32, P(ctypes.c_int8), P(ctypes.c_uint8), P(ctypes.c_int8)]
         L.mc3o_select_mcmcmc.argtypes = [i32, P(dbl), P(dbl), dbl, u64, P(dbl), P(dbl), P(u64)]
@@ -144,6 +147,18 @@ def floyd_words(N: int, k: int, words) -> np.ndarray:
     m = np.zeros(N, dtype=np.uint8)
     lib().mc3o_floyd_words(N, k, _ptr(w, ctypes.c_uint32), _ptr(m, ctypes.c_uint8))
     return m
+
+
+COUPLINGS_PM1, COUPLINGS_GAUSS = 0, 1
+
+
+def couplings(N: int, kind: int, seed: int):
+    """(J, scale) of the seeded instance generator: kind 0 +-1 couplings with scale
+    1/sqrt(N), kind 1 Gaussian couplings of variance 1/N with scale 1."""
+    J = np.zeros((N, N), dtype=np.float64)
+    if lib().mc3o_couplings(N, kind, seed, _ptr(J, ctypes.c_double)) != 0:
+        raise ValueError("unknown coupling kind")
+    return J, (1.0 / math.sqrt(N) if kind == COUPLINGS_PM1 else 1.0)
 
 
 def energy(J: np.ndarray, scale: float, s: np.ndarray) -> float:

@@ -117,6 +117,41 @@ uint64_t mc3o_u53(uint32_t w0, uint32_t w1)
     return ((uint64_t)(w0 >> 5) << 26) | (uint64_t)(w1 >> 6);
 }
 
+/* Couplings of an SK instance from a seed (the instance generator; the paper draws
+ * Gaussian couplings, Sec. "The Sherrington-Kirkpatrick model"; the +-1 kind gives
+ * integer energies).  Pair a < b reads block b of the coupling stream (tag 5,
+ * chain 0, step 0, edge a), words w0..w3.
+ *   kind 0: J_ab = +1 if bit 0 of w0 is set, else -1 (energy scale 1/sqrt(N)).
+ *   kind 1: Box-Muller, u1 = (u53(w0, w1) + 1) / 2^53 in (0, 1],
+ *           u2 = u53(w2, w3) / 2^53 in [0, 1), z = sqrt(-2 ln u1) cos(2 pi u2),
+ *           J_ab = z * (1 / sqrt(N)) (energy scale 1).
+ * J is N x N row-major, symmetric, zero diagonal.  Returns 0, or -1 for a bad kind. */
+int mc3o_couplings(int N, int kind, uint64_t seed, double* J)
+{
+    if (kind != 0 && kind != 1) return -1;
+    const double inv_sqrt_n = 1.0 / sqrt((double)N);
+    const double two_pi = 6.283185307179586;
+    for (int a = 0; a < N; ++a) {
+        J[(size_t)a * N + a] = 0.0;
+        for (int b = a + 1; b < N; ++b) {
+            uint32_t w[4];
+            for (int q = 0; q < 4; ++q) w[q] = mc3o_word(seed, 5u, 0u, 0u, (uint32_t)a, 4u * (uint32_t)b + (uint32_t)q);
+            double v;
+            if (kind == 0) {
+                v = (w[0] & 1u) ? 1.0 : -1.0;
+            } else {
+                const double u1 = ((double)mc3o_u53(w[0], w[1]) + 1.0) * 0x1.0p-53;
+                const double u2 = (double)mc3o_u53(w[2], w[3]) * 0x1.0p-53;
+                const double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+                v = z * inv_sqrt_n;
+            }
+            J[(size_t)a * N + b] = v;
+            J[(size_t)b * N + a] = v;
+        }
+    }
+    return 0;
+}
+
 /* --------------------------------------------------------------------------- exp */
 
 /* exp(x) for x <= 0.  x = k ln2 + r with |r| <= ln2/2 (Cody-Waite: ln 2 split into
