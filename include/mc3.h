@@ -130,6 +130,12 @@ typedef enum {
     MC3_SCORER_AUTO = 2
 } mc3_scorer;
 
+/* Kinds of seeded couplings (mc3_generate_couplings). */
+typedef enum {
+    MC3_J_PM1 = 0,
+    MC3_J_GAUSS = 1
+} mc3_coupling;
+
 /* One SK instance and its chains.  Constraints: 2 <= N <= 8192, 1 <= M <= 4000,
  * 1 <= chains, 1 <= kmin <= kmax <= N, chains * M <= 2^24, rule METROPOLIS => M == 1. */
 typedef struct {
@@ -243,6 +249,20 @@ mc3_status mc3_destroy(mc3_ctx* ctx);
  * precision, as three BF16 terms hi = bf16(J), mid = bf16(J - hi),
  * lo = bf16(J - hi - mid), each packed in matrix-core fragment order. */
 mc3_status mc3_init_couplings(mc3_ctx* ctx, const double* J, int64_t ld, double scale);
+
+/* Seeded SK instances generated on the device, in place of mc3_init_couplings for
+ * instance `instance` (0 for a single-instance context).  The paper's SK couplings
+ * are Gaussian (Sec. "The Sherrington-Kirkpatrick model"); the +-1 kind has integer
+ * energies, so trajectories can be compared bit for bit.  Pair i < j reads block j
+ * of the coupling stream (Philox4x32-10, key = seed, counter = (j, i, 0, 5 << 28)),
+ * words w0..w3:
+ *   MC3_J_PM1:   J_ij = +1 if bit 0 of w0 is set, else -1; energy scale 1/sqrt(N).
+ *   MC3_J_GAUSS: Box-Muller, u1 = (u53(w0, w1) + 1) / 2^53, u2 = u53(w2, w3) / 2^53,
+ *                J_ij = (sqrt(-2 ln u1) cos(2 pi u2)) * (1/sqrt(N)); energy scale 1
+ *                (device log and cos: within an ulp or two of any other libm).
+ * J is symmetric with a zero diagonal.  Synchronises like mc3_init_couplings.  Errors:
+ * MC3_E_ARG for an unknown kind or instance. */
+mc3_status mc3_generate_couplings(mc3_ctx* ctx, int32_t instance, int32_t kind, uint64_t seed);
 
 /* mc3_init_couplings for instance `instance` of a batch (mc3_init_couplings loads
  * instance 0).  Every instance needs its couplings before mc3_init_chains. */

@@ -7,3 +7,4 @@
 #include "select.hpp"
 #include "delta.hpp"
 #include "sets.hpp"
+#include "couplings.hpp"

@@ -902,6 +902,8 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
   return MC3_OK;
 }
 
+mc3_status pack_couplings(mc3_ctx* c, InstH& h, double scale);
+
 mc3_status init_couplings_impl(mc3_ctx* c, int32_t instance, const double* J, int64_t ld, double scale) {
   MC3_TRY(usable(c));
   if (instance < 0 || instance >= (int32_t)c->pl.inst.size())
@@ -917,6 +919,14 @@ mc3_status init_couplings_impl(mc3_ctx* c, int32_t instance, const double* J, in
   MC3_TRY(hip_ok(c, hipMemsetAsync(J64, 0, (size_t)Np * Np * 8, c->stream), "clear J"));
   MC3_TRY(hip_ok(c, hipMemcpy2DAsync(J64, (size_t)Np * 8, J, (size_t)ld * 8, (size_t)N * 8, N, hipMemcpyHostToDevice,
                                      c->stream), "upload J"));
+  return pack_couplings(c, h, scale);
+}
+
+// The scorer's packed copy of an instance's J64 (three BF16 terms or FP64 fragments),
+// then the instance's scale and tables.
+mc3_status pack_couplings(mc3_ctx* c, InstH& h, double scale) {
+  const int Np = h.Np;
+  const double* J64 = c->at<const double>(h.J64);
   if (c->cfg.precision == MC3_SPLIT_BF16) {
     const long long n = (long long)(Np / 32) * (Np / 16) * 64;
     hipLaunchKernelGGL(mc3::k_pack_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
@@ -1025,6 +1035,22 @@ mc3_status mc3_destroy(mc3_ctx* ctx) {
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return MC3_OK;
+}
+
+mc3_status mc3_generate_couplings(mc3_ctx* c, int32_t instance, int32_t kind, uint64_t seed) {
+  MC3_TRY(usable(c));
+  if (instance < 0 || instance >= (int32_t)c->pl.inst.size())
+    return fail(c, MC3_E_ARG, "instance %d is not in the batch", instance);
+  if (kind != MC3_J_PM1 && kind != MC3_J_GAUSS) return fail(c, MC3_E_ARG, "unknown coupling kind %d", kind);
+  InstH& h = c->pl.inst[instance];
+  const int N = h.desc.N, Np = h.Np;
+  const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
+  const long long n = (long long)Np * Np;
+  hipLaunchKernelGGL(mc3::k_gen_couplings, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                     c->at<double>(h.J64), N, Np, (int)kind, mc3::Key{(uint32_t)seed, (uint32_t)(seed >> 32)},
+                     inv_sqrt_n);
+  MC3_TRY(check_launch(c, "coupling generator"));
+  return pack_couplings(c, h, kind == MC3_J_PM1 ? inv_sqrt_n : 1.0);
 }
 
 mc3_status mc3_init_couplings(mc3_ctx* c, const double* J, int64_t ld, double scale) {

@@ -6,6 +6,7 @@ current HIP stream; every computation happens in the library's kernels.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional
 
@@ -18,6 +19,7 @@ CEIL_EXPORTS = ["mc3c_mfma_ceiling", "mc3c_mfma_mix"]
 MFMA_MIXES = {0: "none", 1: "split_kernel", 2: "tile_64x128", 3: "lds_reads_32", 4: "lds_reads_16"}
 
 MC3_OK, MC3_E_ARG, MC3_E_DEVICE, MC3_E_STATE = 0, -1, -3, -4
+MC3_J_PM1, MC3_J_GAUSS = 0, 1
 MC3_E_UNSUPPORTED, MC3_E_NUMERIC, MC3_E_WORKSPACE = -5, -6, -7
 MC3_FP64, MC3_SPLIT_BF16 = 0, 1
 MC3_RULE_MCMCMC, MC3_RULE_METROPOLIS = 0, 1
@@ -37,7 +39,7 @@ EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_coupling
            "mc3_propose", "mc3_score_candidates", "mc3_select", "mc3_step_n", "mc3_recompute", "mc3_measure",
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
            "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
-           "mc3_init_couplings_instance", "mc3_step_n_per_instance", "mc3_step_n_graph", "mc3_checkpoint_save",
+           "mc3_init_couplings_instance", "mc3_generate_couplings", "mc3_step_n_per_instance", "mc3_step_n_graph", "mc3_checkpoint_save",
            "mc3_checkpoint_load", "mc3_set_generation"]
 
 
@@ -116,6 +118,7 @@ def lib() -> ctypes.CDLL:
     L.mc3_init_couplings_instance.argtypes = [vp, c.c_int32, P(c.c_double), c.c_int64, c.c_double]
     L.mc3_step_n_per_instance.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
     L.mc3_step_n_graph.argtypes = [vp, c.c_uint32, c.c_int64, c.c_double, c.c_double, c.c_int64]
+    L.mc3_generate_couplings.argtypes = [vp, c.c_int32, c.c_int32, c.c_uint64]
     L.mc3_checkpoint_save.argtypes = [vp, vp, P(c.c_size_t)]
     L.mc3_checkpoint_load.argtypes = [vp, vp, c.c_size_t]
     L.mc3_set_generation.argtypes = [vp, c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
@@ -226,6 +229,13 @@ class Context:
         self._check(lib().mc3_init_couplings_instance(self.h, instance,
                                                       J.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), N,
                                                       float(scale)), "mc3_init_couplings_instance")
+
+    def generate_couplings(self, kind: int, seed: int, instance: int = 0) -> float:
+        """Seeded couplings generated on the device (kind MC3_J_PM1 or MC3_J_GAUSS);
+        returns the energy scale they carry."""
+        self._check(lib().mc3_generate_couplings(self.h, instance, int(kind), int(seed)), "mc3_generate_couplings")
+        N = self.instances[instance][0]
+        return 1.0 / math.sqrt(N) if kind == MC3_J_PM1 else 1.0
 
     def init_chains(self, spins: Optional[np.ndarray] = None):
         """spins: None, or int8 [chains, N] (one instance) / the instances' blocks
