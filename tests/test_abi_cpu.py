@@ -65,6 +65,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(mc3_config, arity), offsetof(mc3_config, law),
          offsetof(mc3_batch_config, arity), offsetof(mc3_batch_config, law));
   printf("%zu %zu\n", offsetof(mc3_config, law_table), offsetof(mc3_batch_config, law_table));
+  printf("%zu %zu\n", offsetof(mc3_config, tile_cols), offsetof(mc3_batch_config, tile_cols));
   return 0;
 }
 '''
@@ -82,7 +83,8 @@ int main(void) {
                     native.BatchConfig.instances.offset, native.BatchConfig.scorer.offset,
                     native.Config.scorer.offset, native.Config.arity.offset, native.Config.law.offset,
                     native.BatchConfig.arity.offset, native.BatchConfig.law.offset,
-                    native.Config.law_table.offset, native.BatchConfig.law_table.offset]
+                    native.Config.law_table.offset, native.BatchConfig.law_table.offset,
+                    native.Config.tile_cols.offset, native.BatchConfig.tile_cols.offset]
 
 
 def test_version(lib):
