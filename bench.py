@@ -82,23 +82,25 @@ def _traffic_from_profile():
     return rec, "measured"
 
 
-def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0, scorer="gemm", arity=0, law="uniform"):
+def _context(w, precision, rule, M, kmin, kmax, J, scale, mean_steps=0, scorer="gemm", arity=0, law="uniform",
+             energy_update="exact", recompute_every=0):
     from paper_2102_05613_amd import native
     cfg = native.make_config(w.N, M, w.chains, kmin, kmax, precision=precision, rule=rule, seed=w.seed,
-                             mean_steps=mean_steps, scorer=scorer, arity=arity, law=law)
+                             mean_steps=mean_steps, scorer=scorer, arity=arity, law=law,
+                             energy_update=energy_update, recompute_every=recompute_every)
     ctx = native.Context(cfg)
     ctx.init_couplings(J, scale)
     ctx.init_chains()
     return ctx
 
 
-def _time_path(w, precision, steps, warmup, J, scale, every=1):
+def _time_path(w, precision, steps, warmup, J, scale, every=1, energy_update="exact"):
     """Time `steps` pipelined steps after `warmup`; the scoring kernel is timed live by
     HIP events on its stream (mc3_timing_*) around every `every`-th launch of the timed
     steps, so that the events' own cost (a few microseconds a record) stays out of the
     throughput of a fast step."""
     import torch
-    ctx = _context(w, precision, "mcmcmc", w.M, w.kmin, w.kmax, J, scale)
+    ctx = _context(w, precision, "mcmcmc", w.M, w.kmin, w.kmax, J, scale, energy_update=energy_update)
     stream = torch.cuda.current_stream()
     if warmup:
         ctx.step_n(0, warmup, w.beta0, w.beta0, 1)
@@ -121,6 +123,21 @@ def _time_path(w, precision, steps, warmup, J, scale, every=1):
             "moves": summ["moves"], "near_ties": summ["near_ties"]}
 
 
+def _kernel_pass(w, precision, launches, J, scale, warmup=8):
+    """The scoring kernel's average duration over `launches` consecutive steps of the
+    same workload, every launch bracketed by HIP events on its stream (a pass of its
+    own after the throughput timing, whose events would otherwise be in the timed
+    steps)."""
+    ctx = _context(w, precision, "mcmcmc", w.M, w.kmin, w.kmax, J, scale)
+    ctx.step_n(0, warmup, w.beta0, w.beta0, 1)
+    ctx.timing_enable(True, every=1)
+    ctx.step_n(warmup, launches, w.beta0, w.beta0, 1)
+    score_ms, n = ctx.timing_read()
+    ctx.close()
+    assert n == launches
+    return {"score_ms_avg": score_ms / n, "launches": n, "first_step": warmup}
+
+
 def _t_within(e, ref, window, tol=0.01):
     """First t such that every window [t', t'+window) with t' >= t has mean within
     tol*|ref| of ref; None if there is none."""
@@ -137,68 +154,107 @@ def _t_within(e, ref, window, tol=0.01):
     return t if t <= T - window else None
 
 
-def _thermalize_study(w, J, scale, T, beta, k_edge, label, specs=None):
-    """MCMCMC (split-BF16 and FP64 pair sums, and the FP64 field-update scorer where
-    the flip sets are small enough; M = w.M, flip sets of k_edge = (kmin, kmax)) and
-    single-flip Metropolis (field-update scorer) on the same instance, chains and
-    initial states.  specs: (name, precision, rule, M, kmin, kmax, scorer, arity, law)
-    to run instead."""
+def _run_means(w, J, scale, prec, rule, M, kmin, kmax, scorer, arity, law, T, beta0, beta1, total,
+               chunk=200000):
+    """Chain-mean node-weighted energy per spin of every step of a T-step run from the
+    init states, and its wall time (steps issued in chunks with a sync after each, so a
+    long run reports progress)."""
     import torch
+    ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T, scorer=scorer, arity=arity, law=law)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s0 in range(0, T, chunk):
+        ctx.step_n(s0, min(chunk, T - s0), beta0, beta1, total)
+        ctx.sync()
+    wall = time.perf_counter() - t0
+    means = ctx.read_means(0, T) / w.N
+    ctx.close()
+    return means[:, 1], wall
+
+
+def _thermalize_study(w, J, scale, beta, label, specs, window):
+    """Runs on the same instance, chains and initial states at a fixed beta.  specs:
+    (name, precision, rule, M, kmin, kmax, scorer, arity, law, T).  The reference energy
+    is the lowest tail mean (last 25% of a run) among the runs: every run starts from
+    random states, far above the equilibrium energy, and approaches it from above, so
+    the lowest tail is the best-converged estimate; the long runs in the specs exist to
+    provide it.  t_1% uses one window for every run."""
     runs = {}
-    if specs is None:
-        specs = [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm", 0, "uniform"),
-                 ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "gemm", 0, "uniform")]
-        if k_edge[1] <= 16:
-            specs.append(("mcmcmc_fp64_field_update", "fp64", "mcmcmc", w.M, k_edge[0], k_edge[1], "delta", 0,
-                          "uniform"))
-        specs.append(("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform"))
-    for name, prec, rule, M, kmin, kmax, scorer, arity, law in specs:
-        ctx = _context(w, prec, rule, M, kmin, kmax, J, scale, mean_steps=T, scorer=scorer, arity=arity, law=law)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.step_n(0, T, beta, beta, 1)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        means = ctx.read_means(0, T) / w.N
-        ctx.close()
-        runs[name] = {"wall_s": wall, "e_bar": means[:, 1], "M": M, "scorer": scorer, "precision": prec,
+    for name, prec, rule, M, kmin, kmax, scorer, arity, law, T in specs:
+        e, wall = _run_means(w, J, scale, prec, rule, M, kmin, kmax, scorer, arity, law, T, beta, beta, 1)
+        runs[name] = {"wall_s": wall, "e_bar": e, "M": M, "T": T, "scorer": scorer, "precision": prec,
                       "graph": "star" if arity == 0 else (f"line, {M + 1} nodes" if law == "line"
                                                           else f"{arity}-ary tree, {M + 1} nodes")}
-    tail = {name: float(np.mean(r["e_bar"][-T // 4:])) for name, r in runs.items()}
-    ref = min(tail.values())
-    window = max(10, T // 100)
-    out = {"setting": label, "beta": beta, "flip_set_sizes": list(k_edge), "M": w.M, "chains": w.chains,
-           "T": T, "window": window, "reference_energy_per_spin": ref}
+        _log(f"thermalize {label[:30]}.. {name}: {T} steps in {wall:.1f} s")
+    tail = {name: float(np.mean(r["e_bar"][-r["T"] // 4:])) for name, r in runs.items()}
+    ref_name = min(tail, key=tail.get)
+    ref = tail[ref_name]
+    out = {"setting": label, "beta": beta, "chains": w.chains, "window": window,
+           "reference_energy_per_spin": ref, "reference_run": ref_name}
     for name, r in runs.items():
         t = _t_within(r["e_bar"], ref, window)
-        per_step_s = r["wall_s"] / T
-        out[name] = {"t_steps": t if t is not None else f"> {T}",
+        per_step_s = r["wall_s"] / r["T"]
+        out[name] = {"T": r["T"], "t_steps": t if t is not None else f"> {r['T']}",
                      "t_seconds": None if t is None else t * per_step_s,
                      "t_candidates": None if t is None else t * w.chains * r["M"],
-                     "tail_energy_per_spin": tail[name], "ms_per_step": per_step_s * 1e3,
+                     "M": r["M"], "tail_energy_per_spin": tail[name], "ms_per_step": per_step_s * 1e3,
                      "scorer": r["scorer"], "precision": r["precision"], "graph": r["graph"]}
     return out
 
 
-def _thermalize(w, J, scale, T):
+def _ratios_vs(study, base):
+    """t_1% of `base` over each other run's, per step, per candidate and per second."""
+    b = study[base]
+    out = {}
+    for name, r in study.items():
+        if not isinstance(r, dict) or name == base or "t_steps" not in r:
+            continue
+        if isinstance(r["t_steps"], int) and isinstance(b["t_steps"], int) and r["t_steps"] > 0:
+            out[name] = {"per_step": b["t_steps"] / r["t_steps"],
+                         "per_candidate": b["t_candidates"] / r["t_candidates"],
+                         "per_second": b["t_seconds"] / r["t_seconds"]}
+        else:
+            out[name] = None
+    return out
+
+
+def _thermalize(w, J, scale, T, T_long):
+    """The paper's SK comparison (Fig. fig_sk) on this instance and the benchmark
+    workload's own setting.  T: steps of the graph runs; T_long: steps of the
+    single-update Metropolis runs (field-update scorer, microseconds a step), long
+    enough for them to converge too."""
+    window = max(10, T // 100)
+    paper = _thermalize_study(
+        w, J, scale, 1.0,
+        "the paper's SK comparison (Fig. fig_sk) on this instance: L = 1024, T = 1, single-spin-flip edges; "
+        "line-graph addition process of 2^7 nodes, binary tree of depth 7, ternary of depth 5, 16-ary of "
+        "depth 3 (uniform root), the 129-node star, against single-update Metropolis",
+        [("line_2e7", "split_bf16", "mcmcmc", 127, 1, 1, "gemm", 1, "line", T),
+         ("binary_depth7", "fp64", "mcmcmc", 126, 1, 1, "delta", 2, "uniform", T),
+         ("ternary_depth5", "fp64", "mcmcmc", 120, 1, 1, "delta", 3, "uniform", T),
+         ("16ary_depth3", "fp64", "mcmcmc", 272, 1, 1, "delta", 16, "uniform", T),
+         ("star_129_split_bf16", "split_bf16", "mcmcmc", 128, 1, 1, "gemm", 0, "uniform", T),
+         ("star_129_fp64", "fp64", "mcmcmc", 128, 1, 1, "gemm", 0, "uniform", max(10 * window, T // 10)),
+         ("star_129_field_update", "fp64", "mcmcmc", 128, 1, 1, "delta", 0, "uniform", T),
+         ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform", T_long)],
+        window)
+    paper["t1pct_ratio_metropolis_over_graph"] = _ratios_vs(paper, "metropolis_m1_single_flip")
+    paper["paper_claim"] = ("thermalization time decreased by two orders of magnitude against local single-update "
+                            "Metropolis (Sec. 'Numerical results', Fig. fig_sk; hardware and precision not stated)")
+    own = _thermalize_study(
+        w, J, scale, w.beta0, "the benchmark workload's own flip sets (1..128 sites) and beta = 2",
+        [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax, "gemm", 0, "uniform", T),
+         ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, w.kmin, w.kmax, "gemm", 0, "uniform", max(10 * window, T // 10)),
+         ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform", T_long)],
+        window)
+    own["t1pct_ratio_metropolis_over_graph"] = _ratios_vs(own, "metropolis_m1_single_flip")
     return {
-        "definition": "t_1%: first step after which every window of max(10, T/100) steps of the chain-mean "
-                      "node-weighted energy per spin stays within 1% of the reference; reference = lowest tail "
-                      "mean (last 25% of steps) among the runs of the study",
-        "paper_setting": _thermalize_study(w, J, scale, T, 1.0, (1, 1),
-                                           "single-spin-flip edges at T = Tc = 1 (the paper's SK experiment)"),
-        "paper_graph_shapes": _thermalize_study(
-            w, J, scale, T, 1.0, (1, 1),
-            "the paper's SK comparison (Fig. fig_sk) on this instance: L = 1024, T = 1, single-spin-flip edges; "
-            "line-graph addition process of 2^7 nodes, binary tree of depth 7, ternary of depth 5, 16-ary of "
-            "depth 3 (uniform root), against single-update Metropolis",
-            specs=[("line_2e7", "split_bf16", "mcmcmc", 127, 1, 1, "gemm", 1, "line"),
-                   ("binary_depth7", "fp64", "mcmcmc", 126, 1, 1, "delta", 2, "uniform"),
-                   ("ternary_depth5", "fp64", "mcmcmc", 120, 1, 1, "delta", 3, "uniform"),
-                   ("16ary_depth3", "fp64", "mcmcmc", 272, 1, 1, "delta", 16, "uniform"),
-                   ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform")]),
-        "configured_workload": _thermalize_study(w, J, scale, T, w.beta0, (w.kmin, w.kmax),
-                                                 "the benchmark workload's own flip sets and beta"),
+        "definition": "e(t) = chain mean of the node-weighted energy per spin; t_1% = first step after which "
+                      "every window of max(10, T/100) steps (T of the graph runs; one window for every run) "
+                      "has mean within 1% of the reference; reference = the lowest tail mean (last 25% of a "
+                      "run) among the runs of the study, long runs included",
+        "paper_graph_shapes": paper,
+        "configured_workload": own,
     }
 
 
@@ -537,7 +593,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="sk_n1024_m128_split")
     ap.add_argument("--fp64-steps", type=int, default=40)
+    ap.add_argument("--kernel-launches", type=int, default=200,
+                    help="scoring launches timed one by one for the roofline figure (a pass of their own)")
     ap.add_argument("--thermalize-steps", type=int, default=20000)
+    ap.add_argument("--metropolis-steps", type=int, default=2000000,
+                    help="steps of the single-update Metropolis runs of the thermalization study")
     ap.add_argument("--cpu-chains", type=int, default=320)
     ap.add_argument("--cpu-threads", type=int, default=16,
                     help="oracle threads for the CPU baseline (capped by the host's CPUs)")
@@ -581,6 +641,10 @@ def main():
         return
     split = _time_path(w, "split_bf16", args.steps, args.warmup, J, scale, every=TIMING_EVERY)
     _log(f"headline split: {split['total_ms'] / args.steps:.4f} ms/step")
+    scored = _time_path(w, "split_bf16", args.steps, args.warmup, J, scale, every=TIMING_EVERY,
+                        energy_update="scored")
+    kpass = _kernel_pass(w, "split_bf16", args.kernel_launches, J, scale)
+    _log(f"headline scoring kernel: {kpass['score_ms_avg'] * 1e3:.2f} us over {kpass['launches']} launches")
     ceiling = None
     if args.ceiling_iters > 0:
         from paper_2102_05613_amd import native
@@ -604,7 +668,7 @@ def main():
                   + (w.chains + 1) * (Np // 32) * 4.0   # base words
                   + (Np // 256) * Bp * 8.0)      # FP64 partial energies written
     traffic, traffic_note = _traffic_from_profile()
-    achieved = flops_split / (split["score_ms_avg"] / 1e3) / 1e12
+    achieved = flops_split / (kpass["score_ms_avg"] / 1e3) / 1e12
     achieved64 = flops_fp64 / (fp64["score_ms_avg"] / 1e3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
@@ -617,9 +681,12 @@ def main():
                      "traffic": None if traffic is None else traffic["fetch_bytes"] + traffic["write_bytes"],
                      "traffic_detail": {"status": traffic_note, "algorithmic_bytes": algo_bytes,
                                         **({} if traffic is None else traffic)},
-                     "kernel": "k_score_split", "kernel_ms": split["score_ms_avg"],
-                     "kernel_timing": f"HIP events on the scoring stream around every {TIMING_EVERY}th launch "
-                                      f"of the timed steps ({split['timed_launches']} launches)",
+                     "kernel": "k_score_split", "kernel_ms": kpass["score_ms_avg"],
+                     "kernel_timing": f"HIP events on the scoring stream around each of {kpass['launches']} "
+                                      f"consecutive scoring launches (steps {kpass['first_step']}.."
+                                      f"{kpass['first_step'] + kpass['launches'] - 1} of a separate pass after the "
+                                      f"timed steps); in the timed steps, every {TIMING_EVERY}th launch: "
+                                      f"{split['score_ms_avg']:.5f} ms over {split['timed_launches']} launches",
                      "flops_per_launch": flops_split,
                      "ceiling": None if ceiling is None else {
                          "kind": "plain loop of independent 32x32x16 BF16 MFMAs at the scoring kernel's occupancy "
@@ -638,12 +705,18 @@ def main():
                       "achieved_tflops": achieved64, "peak_tflops": PEAK_FP64_TFLOPS,
                       "frac": achieved64 / PEAK_FP64_TFLOPS},
         "split_vs_fp64": fp64_ms_step / ms_step,
+        "energy_update": {
+            "headline": "exact: the carried energy advances by the FP64 difference of each move, from the |D*| "
+                        "coupling rows of the sites the move flips",
+            "exact_ms_per_step": ms_step, "scored_ms_per_step": scored["total_ms"] / args.steps,
+            "scored": "the chosen candidate's split-BF16 energy carried instead (no coupling rows read)",
+            "moves_per_chain_step": split["moves"] / ((args.warmup + args.steps) * w.chains)},
         "selection": {"moves": split["moves"], "near_ties": split["near_ties"],
                       "near_ties_per_1e4_chain_steps": split["near_ties"] * 1e4 / ((args.warmup + args.steps) * w.chains)},
     }
     out["precision_split_vs_fp64"] = {"headline": _precision_report(w, J, scale)}
     if args.thermalize_steps > 0:
-        out["steps_to_thermalize"] = _thermalize(w, J, scale, args.thermalize_steps)
+        out["steps_to_thermalize"] = _thermalize(w, J, scale, args.thermalize_steps, args.metropolis_steps)
         out["steps_to_thermalize"]["anneal_workload"] = _anneal_thermalize(args.anneal_steps)
         _log("thermalization study done")
     other = {}

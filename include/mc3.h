@@ -130,6 +130,20 @@ typedef enum {
     MC3_SCORER_AUTO = 2
 } mc3_scorer;
 
+/* How the pair-sum scorers carry each chain's energy from step to step (the field-
+ * update scorer always carries exact FP64 differences).  The carried quantity is the
+ * unscaled pair sum U = sum_{i<j} J_ij s_i s_j in FP64, E = -(scale U).
+ *   EXACT:  on a move, U += dU(D*) computed in FP64 from the |D*| rows of J, D* the set
+ *           of sites where the new state differs from the old one:
+ *           dU = -2 sum_{i in D*} s_i sum_{j not in D*} J_ij s_j (old spins); exact
+ *           integers for +-1 couplings.  Costs |D*| N coupling reads per move.
+ *   SCORED: U = the chosen candidate's pair sum as scored (split BF16 on the split
+ *           path), no extra reads. */
+typedef enum {
+    MC3_ENERGY_EXACT = 0,
+    MC3_ENERGY_SCORED = 1
+} mc3_energy_update;
+
 /* Kinds of seeded couplings (mc3_generate_couplings). */
 typedef enum {
     MC3_J_PM1 = 0,
@@ -149,7 +163,10 @@ typedef struct {
     uint64_t seed;           /* Philox key */
     uint32_t chain_base;     /* global index of chain 0 in the Philox counter */
     int32_t mean_steps;      /* capacity of the per-step chain-mean trace ring (>= 0) */
-    double near_tie_tol;     /* selection margin below which a step is flagged; < 0 => default */
+    double near_tie_tol;     /* selection margin below which a step is flagged (a fixed threshold);
+                                < 0 => the default 4 beta eps_E per step, eps_E = N 2^-24 for
+                                split-BF16 scores and N 2^-40 for FP64 scores (the largest change
+                                of an energy's rounding, see mc3_select) */
     int32_t scorer;          /* mc3_scorer */
     int32_t arity;           /* graph tree arity; 0 or >= M: the M-ary star */
     int32_t law;             /* mc3_graph_law */
@@ -160,6 +177,13 @@ typedef struct {
                                 to 128, 256 between); 128, 256 or 512 = that width.  Results
                                 do not depend on it.  Ignored by the FP64 and field-update
                                 scorers; any other value is MC3_E_ARG */
+    int32_t recompute_every; /* K > 0: after the selection of every global step t with
+                                (t + 1) % K == 0 every chain's energy is recomputed in FP64
+                                from its spins (as mc3_recompute); 0: only mc3_recompute */
+    int32_t energy_update;   /* an mc3_energy_update value, for the pair-sum scorers */
+    double drift_tol;        /* a recompute whose |E_carried - E_recomputed| exceeds
+                                drift_tol (|E_recomputed| + 1) counts as a drift event;
+                                < 0 => 1e-9 */
 } mc3_config;
 
 /* One instance of a batch: its size, graph size, chains and flip-set range, with the
@@ -191,18 +215,21 @@ typedef struct {
                                 mc3_batch_create; otherwise ignored */
     int32_t tile_cols;       /* split-BF16 scoring tile width of every instance, as in
                                 mc3_config */
+    int32_t recompute_every; /* as in mc3_config */
+    int32_t energy_update;   /* as in mc3_config */
+    double drift_tol;        /* as in mc3_config */
 } mc3_batch_config;
 
 /* Per-step, per-chain record (40 bytes). */
 typedef struct {
     int32_t r;          /* position of the state the graph was generated from (root) */
     int32_t vstar;      /* selected node; METROPOLIS: 1 = accepted, 0 = rejected */
-    double e_cur;       /* energy of the state after the step */
+    double e_cur;       /* carried energy of the state after the step (-(scale U)) */
     double e_bar;       /* node-weighted energy sum_v P_node(v) E_v (Eq. eq_monte_carlo_graph);
                            METROPOLIS: e_cur */
     double margin;      /* distance of the draw to the edges of the selected interval,
                            as a fraction of the total weight (METROPOLIS: |u - rate|) */
-    uint32_t flags;     /* bit 0: near tie (margin < near_tie_tol); bit 1: moved */
+    uint32_t flags;     /* bit 0: near tie (margin below the step's threshold); bit 1: moved */
     uint32_t step;      /* global step number */
 } mc3_record;
 
@@ -212,8 +239,17 @@ typedef struct {
     int64_t moves;         /* chain-steps that changed the state */
     int64_t near_ties;     /* chain-steps flagged as near ties */
     double min_margin;     /* smallest selection margin seen */
-    double max_drift;      /* largest |E_carried - E_recomputed| at mc3_recompute */
+    double max_drift;      /* largest |E_carried - E_recomputed| at a recompute */
+    int64_t recomputes;    /* recomputes (periodic and mc3_recompute) */
+    int64_t drift_events;  /* chain recomputes whose drift exceeded the drift tolerance */
 } mc3_summary;
+
+/* A linear inverse-temperature schedule: step t has
+ * beta0 + (beta1 - beta0) (t / (total - 1)), beta0 if total <= 1. */
+typedef struct {
+    double beta0, beta1;
+    int64_t total;
+} mc3_schedule;
 
 typedef struct mc3_ctx mc3_ctx;
 
@@ -242,9 +278,11 @@ mc3_status mc3_batch_create(const mc3_batch_config* cfg, void* workspace, size_t
 mc3_status mc3_destroy(mc3_ctx* ctx);
 
 /* Load couplings: J is a host array of N*N doubles, row-major with leading dimension
- * ld >= N; only the strict upper triangle i<j is used (J is taken as symmetric with
- * zero diagonal).  Energies are E = -scale * sum_{i<j} J_ij s_i s_j.  Values must
- * be finite (MC3_E_NUMERIC otherwise).  The array is copied before return
+ * ld >= N; only the strict upper triangle i<j is read (J is taken as symmetric with
+ * zero diagonal: the device mirrors the upper triangle below the diagonal and clears
+ * the diagonal, so whatever the array holds at or below the diagonal, NaN included,
+ * is ignored by every scorer).  Energies are E = -scale * sum_{i<j} J_ij s_i s_j.
+ * Values i<j must be finite (MC3_E_NUMERIC otherwise).  The array is copied before return
  * (synchronous on the stream); the device keeps J in FP64 and, for the split
  * precision, as three BF16 terms hi = bf16(J), mid = bf16(J - hi),
  * lo = bf16(J - hi - mid), each packed in matrix-core fragment order. */
@@ -299,8 +337,18 @@ mc3_status mc3_score_candidates(mc3_ctx* ctx, double* E_out);
  * Q_v their inclusive prefix sum in node order 0..M, W = Q_M;
  * t = floor(u53 W / 2^53) with u53 from words 0,1 of (tag 4);
  * v* = min{v : Q_v > t}.  METROPOLIS: accept iff dE <= 0 or u53/2^53 < exp(-(beta dE)).
- * Writes one mc3_record per chain into the ring (slot step % trace_steps). */
+ * The carried energy then follows the configuration's energy_update.  The margin (the
+ * draw's distance to the edges of its interval, as a fraction of W) is flagged as a
+ * near tie below the threshold: errors of at most eps_E in every node energy move
+ * each interval edge by at most beta eps_E of W, so an unflagged draw picks the node
+ * exact arithmetic would.  Writes one mc3_record per chain into the ring (slot
+ * step % trace_steps); with recompute_every = K and (step + 1) % K == 0 the periodic
+ * recompute follows. */
 mc3_status mc3_select(mc3_ctx* ctx, uint32_t step, double beta);
+
+/* mc3_select with an inverse temperature per instance: beta is a host array
+ * [n_instances] (copied; the call waits for the stream before taking it). */
+mc3_status mc3_select_betas(mc3_ctx* ctx, uint32_t step, const double* beta);
 
 /* n steps starting at global step step0: propose, score, select each step, with
  * beta_t = beta0 + (beta1 - beta0) * (t / (total - 1)) for t = step0 .. step0+n-1
@@ -308,6 +356,12 @@ mc3_status mc3_select(mc3_ctx* ctx, uint32_t step, double beta);
  * proposals of up to 16 steps are drawn in one launch into a ring in the workspace;
  * the results are those of the step-by-step calls. */
 mc3_status mc3_step_n(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
+
+/* mc3_step_n with a schedule per instance: sched is a host array [n_instances] (copied;
+ * the call waits for the stream before taking it); instance i's chains take beta_t of
+ * sched[i].  MC3_E_ARG for a negative or non-finite beta or a total outside
+ * [0, 2^53]. */
+mc3_status mc3_step_n_schedules(mc3_ctx* ctx, uint32_t step0, int64_t n, const mc3_schedule* sched);
 
 /* The steps of mc3_step_n (same arguments, same results bit for bit), replayed from a
  * HIP graph: the launches of L steps (L a multiple of the proposal group of up to 16
@@ -318,7 +372,7 @@ mc3_status mc3_step_n(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, dou
  * host's operation order.  The capture is kept for later calls with the same schedule
  * and the same step0 modulo L.  Runs of fewer than L + 16 steps, and the last 16 to
  * L + 15 steps of a run, are launched as in mc3_step_n; with the field-update scorer
- * this is mc3_step_n.  Scoring launches inside replays are not timed
+ * or a periodic recompute (recompute_every > 0) this is mc3_step_n.  Scoring launches inside replays are not timed
  * (mc3_timing_enable).  For step loops whose launches, not their kernels, take the
  * time (small N and M). */
 mc3_status mc3_step_n_graph(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total);
@@ -331,9 +385,11 @@ mc3_status mc3_step_n_graph(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta
 mc3_status mc3_step_n_per_instance(mc3_ctx* ctx, uint32_t step0, int64_t n, double beta0, double beta1,
                                    int64_t total);
 
-/* Recompute every chain's energy from its spins in FP64 (plain pair sum on the
- * device), record max |carried - recomputed| in the summary, and replace the
- * carried energy by the recomputed one. */
+/* Recompute every chain's energy from its spins in FP64 on the matrix cores
+ * (U = (1/2) sum_i s_i (J s)_i, the symmetric zero-diagonal J), record
+ * |E_carried - E_recomputed| (its largest value per chain, and a drift event when it
+ * exceeds drift_tol (|E| + 1)) in the summary, and carry the recomputed value (the
+ * repair).  Synchronises. */
 mc3_status mc3_recompute(mc3_ctx* ctx);
 
 /* Synchronise; copy the chains' energies (host [chains], may be NULL), spins (host

@@ -63,7 +63,9 @@ struct Inst {
   int32_t arity;    // tree arity: the parent of node v >= 1 is (v-1)/arity (arity M: the star)
   int32_t law;      // root law: 0 uniform over the M+1 nodes, 1 line-graph addition process
   double scale;
+  double tie_coef;  // near-tie threshold per unit of beta (4 eps_E of the precision), 0 with a fixed one
   uint64_t J64, Jpack, flips, flip_slot, base[2], partial, spins;
+  uint64_t upart;   // [Np/16][chains] FP64 partial sums of the FP64 recompute
   uint64_t field;   // [chains][Np] FP64 local fields (field-update path only)
   uint64_t prior;   // [M+1] FP64 log-prior of the nodes (line and table laws), 0 = none
   uint64_t root_q;  // [M+1] uint64 cumulative fixed-point root weights (table law), 0 = none

@@ -33,4 +33,18 @@ __global__ void k_gen_couplings(double* __restrict__ J64, int N, int Np, int kin
   J64[idx] = v;
 }
 
+// The couplings as every scorer reads them: the strict upper triangle of a loaded J64
+// (rows i < j) mirrored below the diagonal and the diagonal cleared, so that the pair
+// sums (which read i < j only) and the field update (which reads whole rows and
+// columns) see the same symmetric, zero-diagonal matrix whatever the caller left
+// below the diagonal.  One thread per element at or below the diagonal; the upper
+// triangle is only read.
+__global__ void k_mirror_upper(double* __restrict__ J64, int Np) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)Np * Np) return;
+  const int i = (int)(idx / Np), j = (int)(idx % Np);
+  if (j > i) return;
+  J64[idx] = j == i ? 0.0 : J64[(size_t)j * Np + i];
+}
+
 }  // namespace mc3

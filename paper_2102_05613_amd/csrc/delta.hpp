@@ -116,7 +116,9 @@ __device__ __forceinline__ int path_set(const uint16_t* sites, const uint8_t* ks
 //   3. wave 0: the rule (apply_rule) and the bookkeeping;
 //   4. on a move: h -= 2 J[:, D*] s_D* (rows of J, coalesced), then the spins of D*
 //      flip and U += dU(D*).
-// beta_t = beta0 + (beta1 - beta0) (t / (total - 1)) as on the host.  Per-step chain
+// beta_t = beta0 + (beta1 - beta0) (t / (total - 1)) as on the host, the schedule of the
+// chain's instance from sched ([instances][3]) when it is non-null.  Near ties: margin
+// < tol + beta tie_coef.  Per-step chain
 // values (e_cur, e_bar) go to vals[t % mean_steps][g] for the means trace.
 // Dynamic LDS: delta_lds_bytes(Nmax, Mmax, Wmax).
 __global__ __launch_bounds__(256) void k_step_delta(
@@ -126,13 +128,19 @@ __global__ __launch_bounds__(256) void k_step_delta(
     unsigned long long* __restrict__ moves, unsigned long long* __restrict__ near_ties,
     double* __restrict__ min_margin, double* __restrict__ e_bar_out, double* __restrict__ vals, int mean_steps,
     int metropolis, double beta0, double beta1, long long total, double tol, Key key, uint32_t chain_base,
-    uint32_t step0, int nsteps, int trace_steps) {
+    uint32_t step0, int nsteps, int trace_steps, const double* __restrict__ sched) {
   extern __shared__ double dl[];
   __shared__ int sh_r, sh_vstar, sh_nd;
   __shared__ uint16_t dstar[2 * kDeltaMaxK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
-  const Inst& in = insts[chain_inst[g]];
+  const int ii = chain_inst[g];
+  const Inst& in = insts[ii];
+  if (sched) {
+    beta0 = sched[3 * ii];
+    beta1 = sched[3 * ii + 1];
+    total = (long long)sched[3 * ii + 2];
+  }
   const int c = g - in.chain0;
   const int N = in.N, Np = in.Np, W = in.W, M = in.M;
   const double scale = in.scale;
@@ -157,7 +165,7 @@ __global__ __launch_bounds__(256) void k_step_delta(
 
   for (int it = 0; it < nsteps; ++it) {
     const uint32_t step = step0 + (uint32_t)it;
-    const double beta = total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)step / (double)(total - 1));
+    const double beta = beta_of(beta0, beta1, total, step);
     // 1. root and flip sets
     if (tid == 0)
       sh_r = root_of(key, gc, step, M, metropolis, in.law, in.root_q ? ws_at<const uint64_t>(ws, in.root_q) : nullptr);
@@ -207,8 +215,8 @@ __global__ __launch_bounds__(256) void k_step_delta(
                                    in.prior ? ws_at<const double>(ws, in.prior) : nullptr);
       if (lane == 0) {
         sh_vstar = o.vstar;
-        record_outcome(o, g, r, tol, step, trace_steps, total_chains, e_cur, e_bar_out, moves, near_ties,
-                       min_margin, ring);
+        record_outcome(o, o.e_new, g, r, tol + beta * in.tie_coef, step, trace_steps, total_chains, e_cur,
+                       e_bar_out, moves, near_ties, min_margin, ring);
         if (mean_steps > 0) {
           double* vv = vals + ((size_t)(step % (uint32_t)mean_steps) * total_chains + g) * 2;
           vv[0] = o.e_new;

@@ -8,3 +8,4 @@
 #include "delta.hpp"
 #include "sets.hpp"
 #include "couplings.hpp"
+#include "recompute.hpp"

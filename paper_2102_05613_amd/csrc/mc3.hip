@@ -41,7 +41,9 @@ struct InstH {
   size_t J64, Jpack, flips, base[2], partial, spins;  // byte offsets into the workspace
   size_t flip_slot;                                    // bytes of one step's flip sets
   size_t field = 0;                                    // [chains][Np] FP64 fields (field-update path)
+  size_t upart = 0;                                    // [Np/16][chains] FP64 recompute partial sums
   double scale = 1.0;
+  double tie_coef = 0.0;                               // near-tie threshold per unit of beta
   bool have_J = false;
   int cls = 0;                         // scoring tile class (split: 64 << cls ... columns)
   int unit_off = 0, unit_grid = 0;     // this instance's own unit table (per-instance launches)
@@ -58,11 +60,15 @@ struct Plan {
   int nslots = 2;   // flip-set and root ring slots (ahead + 1)
   std::vector<mc3::Unit> units_global[kClasses], units_local;
   std::vector<mc3::PBlock> pblocks;
+  std::vector<mc3::RecUnit> rec_units;   // the FP64 recompute's units, every instance
   std::vector<int32_t> chain_inst;
-  size_t insts = 0, chain_inst_off = 0, units_global_off[kClasses] = {0, 0, 0}, units_local_off = 0, pblocks_off = 0;
+  size_t insts = 0, chain_inst_off = 0, units_global_off[kClasses] = {0, 0, 0}, units_local_off = 0, pblocks_off = 0,
+         rec_units_off = 0;
+  size_t sched = 0;   // [instances][3] per-instance beta schedules (beta0, beta1, total)
+  size_t drift_ev = 0;   // [chains] drift events of the periodic recompute
   size_t clock = 0;   // the step clock of replayed graphs (one uint32)
   size_t e_cur = 0, e_bar = 0, roots = 0, candT = 0, ring = 0, means = 0, moves = 0, near = 0, minm = 0, drift = 0,
-         erecomp = 0, u_cur = 0, vals = 0, total = 0;
+         u_cur = 0, vals = 0, total = 0;
 };
 
 const char* validate_instance(const mc3_instance_desc& d, int rule) {
@@ -109,6 +115,9 @@ const char* validate_batch(const mc3_batch_config* c) {
   if (c->tile_cols != 0 && c->tile_cols != 128 && c->tile_cols != 256 && c->tile_cols != 512)
     return "tile_cols must be 0, 128, 256 or 512";
   if (!(c->near_tie_tol == c->near_tie_tol)) return "near_tie_tol is NaN";
+  if (c->recompute_every < 0) return "recompute_every must be >= 0";
+  if (c->energy_update != MC3_ENERGY_EXACT && c->energy_update != MC3_ENERGY_SCORED) return "unknown energy_update";
+  if (!(c->drift_tol == c->drift_tol)) return "drift_tol is NaN";
   long long chains = 0, cols = 0;
   size_t table_at = 0;
   for (int i = 0; i < c->n_instances; ++i) {
@@ -238,6 +247,8 @@ Plan make_plan(const mc3_batch_config& cfg) {
     }
     h.pblock_cnt = (int)pl.pblocks.size() - h.pblock_off;
     for (int c = 0; c < h.desc.chains; ++c) pl.chain_inst.push_back(i);
+    for (int ct = 0; ct < (h.desc.chains + 63) / 64; ++ct)
+      for (int rt = 0; rt < h.Np / 16; ++rt) pl.rec_units.push_back(mc3::RecUnit{i, rt, ct, 0});
   }
   // Scoring units.  One instance: XCD-major placement -- grid slot b runs on XCD b % 8
   // and the units of one XCD are consecutive in (pair, tile) order, so each XCD's L2
@@ -302,6 +313,8 @@ Plan make_plan(const mc3_batch_config& cfg) {
   for (int k = 0; k < kClasses; ++k) pl.units_global_off[k] = take(pl.units_global[k].size() * sizeof(mc3::Unit));
   pl.units_local_off = take(pl.units_local.size() * sizeof(mc3::Unit));
   pl.pblocks_off = take(pl.pblocks.size() * sizeof(mc3::PBlock));
+  pl.rec_units_off = take(pl.rec_units.size() * sizeof(mc3::RecUnit));
+  pl.sched = take((size_t)n * 3 * sizeof(double));
   pl.clock = take(4);
   pl.e_cur = take(C * 8);
   pl.e_bar = take(C * 8);
@@ -310,13 +323,11 @@ Plan make_plan(const mc3_batch_config& cfg) {
   pl.near = take(C * 8);
   pl.minm = take(C * 8);
   pl.drift = take(C * 8);
-  pl.erecomp = take(C * 8);
+  pl.drift_ev = take(C * 8);
+  pl.u_cur = take(C * 8);
   pl.ring = take((size_t)cfg.trace_steps * C * sizeof(mc3::Record));
   pl.means = take((size_t)cfg.mean_steps * 3 * sizeof(double));
-  if (pl.delta) {
-    pl.u_cur = take(C * 8);
-    pl.vals = take((size_t)cfg.mean_steps * C * 2 * sizeof(double));
-  }
+  if (pl.delta) pl.vals = take((size_t)cfg.mean_steps * C * 2 * sizeof(double));
   size_t candT = 0;
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
@@ -329,6 +340,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
     h.partial = take((size_t)h.P * h.Bp * 8);
     h.spins = take((size_t)h.desc.chains * h.W * 4);
     if (pl.delta) h.field = take((size_t)h.desc.chains * h.Np * 8);
+    h.upart = take((size_t)(h.Np / 16) * h.desc.chains * 8);
     if (cfg.law == MC3_LAW_LINE || cfg.law == MC3_LAW_TABLE) h.prior = take((size_t)(h.desc.M + 1) * 8);
     if (cfg.law == MC3_LAW_TABLE) h.root_q = take((size_t)(h.desc.M + 1) * 8);
     candT = std::max(candT, (size_t)h.W * h.Bp * 4);
@@ -360,6 +372,9 @@ mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
   b.law = c->law;
   b.law_table = c->law_table;
   b.tile_cols = c->tile_cols;
+  b.recompute_every = c->recompute_every;
+  b.energy_update = c->energy_update;
+  b.drift_tol = c->drift_tol;
   return b;
 }
 
@@ -374,8 +389,11 @@ struct mc3_ctx {
   int device = 0;
   bool have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
   uint32_t proposal_step = 0;
-  double tol = 0.0;
+  double tol = 0.0;          // fixed part of the near-tie threshold (plus beta * tie_coef per instance)
+  double drift_tol = 1e-9;   // relative drift counted as an event by the periodic recompute
   int64_t steps_done = 0;
+  int64_t recomputes = 0;    // periodic or explicit FP64 recomputes since init_chains
+  std::vector<double> sched_host;   // the last per-instance schedules uploaded
   // optional HIP-event timing of the scoring launches
   bool timing = false;
   int32_t t_every = 1;      // bracket every t_every-th scoring launch
@@ -470,6 +488,8 @@ mc3_status upload_insts(mc3_ctx* c) {
     d.arity = h.arity;
     d.law = c->cfg.law;
     d.scale = h.scale;
+    d.tie_coef = h.tie_coef;
+    d.upart = h.upart;
     d.J64 = h.J64;
     d.Jpack = h.Jpack;
     d.flips = h.flips;
@@ -487,19 +507,34 @@ mc3_status upload_insts(mc3_ctx* c) {
   return hip_ok(c, hipStreamSynchronize(c->stream), "upload sync");
 }
 
-// FP64 energies of every chain into `out`; for the field-update path also the pair
-// sums U and the fields h.
-mc3_status launch_energy(mc3_ctx* c, double* out) {
+// Every chain's pair sum U and energy recomputed in FP64 from its spins on the matrix
+// cores (k_recompute_f64, then k_recompute_finish): mode 0 sets them (init, resume);
+// mode 1 is the periodic check -- records the drift of the carried energy, counts
+// drift events, carries the recomputed values.  The field-update path also recomputes
+// its fields h = J s.
+mc3_status launch_recompute(mc3_ctx* c, int mode) {
   const Plan& pl = c->pl;
-  hipLaunchKernelGGL(mc3::k_energy_f64, dim3(pl.total_chains), dim3(256), 0, c->stream, out,
-                     pl.delta ? c->at<double>(pl.u_cur) : nullptr, c->ws, c->insts(), c->chain_inst());
-  MC3_TRY(check_launch(c, "energy kernel"));
+  hipLaunchKernelGGL(mc3::k_recompute_f64, dim3((unsigned)pl.rec_units.size()), dim3(256), 0, c->stream, c->ws,
+                     c->insts(), c->at<const mc3::RecUnit>(pl.rec_units_off));
+  MC3_TRY(check_launch(c, "recompute kernel"));
+  hipLaunchKernelGGL(mc3::k_recompute_finish, dim3((pl.total_chains + 255) / 256), dim3(256), 0, c->stream, c->ws,
+                     c->insts(), c->chain_inst(), pl.total_chains, c->at<double>(pl.u_cur), c->at<double>(pl.e_cur),
+                     c->at<double>(pl.drift), c->at<unsigned long long>(pl.drift_ev), c->drift_tol, mode);
+  MC3_TRY(check_launch(c, "recompute finish kernel"));
   if (pl.delta) {
     hipLaunchKernelGGL(mc3::k_field_init, dim3(pl.total_chains), dim3(256), 0, c->stream, c->ws, c->insts(),
                        c->chain_inst());
     MC3_TRY(check_launch(c, "field kernel"));
   }
+  if (mode == 1) c->recomputes += 1;
   return MC3_OK;
+}
+
+// The periodic recompute after the selection of global step t.
+mc3_status maybe_recompute(mc3_ctx* c, uint32_t t) {
+  const int32_t K = c->cfg.recompute_every;
+  if (K <= 0 || ((uint64_t)t + 1u) % (uint64_t)K != 0u) return MC3_OK;
+  return launch_recompute(c, 1);
 }
 
 mc3_status no_delta(mc3_ctx* c, const char* what) {
@@ -509,21 +544,28 @@ mc3_status no_delta(mc3_ctx* c, const char* what) {
 
 // n steps of the field-update path: persistent per-chain launches of at most 2048
 // steps each, then the chain means of the steps still in the trace ring.
-mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
+mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total,
+                           const double* sched = nullptr) {
   const Plan& pl = c->pl;
   int Nmax = 0;
   for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
+  const int64_t K = c->cfg.recompute_every;
   for (int64_t done = 0; done < n;) {
-    const int chunk = (int)std::min<int64_t>(2048, n - done);
+    int chunk = (int)std::min<int64_t>(2048, n - done);
+    if (K > 0) {   // end the launch at the next step t with (t + 1) % K == 0
+      const int64_t t0 = (int64_t)step0 + done;
+      chunk = (int)std::min<int64_t>(chunk, K - t0 % K);
+    }
     hipLaunchKernelGGL(mc3::k_step_delta, dim3(pl.total_chains), dim3(256), pl.delta_lds, c->stream, c->ws,
                        c->insts(), c->chain_inst(), pl.total_chains, Nmax, pl.Mmax, pl.Wmax,
                        c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->at<mc3::Record>(pl.ring),
                        c->at<unsigned long long>(pl.moves), c->at<unsigned long long>(pl.near),
                        c->at<double>(pl.minm), c->at<double>(pl.e_bar), c->at<double>(pl.vals), c->cfg.mean_steps,
                        c->metropolis() ? 1 : 0, beta0, beta1, (long long)total, c->tol, c->key(),
-                       c->cfg.chain_base, step0 + (uint32_t)done, chunk, c->cfg.trace_steps);
+                       c->cfg.chain_base, step0 + (uint32_t)done, chunk, c->cfg.trace_steps, sched);
     MC3_TRY(check_launch(c, "field-update step kernel"));
     done += chunk;
+    MC3_TRY(maybe_recompute(c, step0 + (uint32_t)(done - 1)));
   }
   if (c->cfg.mean_steps > 0) {
     const int64_t keep = std::min<int64_t>(n, c->cfg.mean_steps);
@@ -640,16 +682,20 @@ struct ClockArg {
 // words of step+1 (whose flip sets and roots must already be proposed).  Ring slots are
 // those of `step` itself; with a clock the kernel takes step - base.
 mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n,
-                         const ClockArg& ck = ClockArg{}) {
+                         const ClockArg& ck = ClockArg{}, const double* sched = nullptr) {
   const Plan& pl = c->pl;
-  const size_t lds = (size_t)(pl.Mmax + 1) * 16;
+  int Nmax = 0;
+  for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
+  const size_t lds = std::max((size_t)(pl.Mmax + 1) * 16, (size_t)8 * pl.Wmax + (size_t)2 * Nmax);
   hipLaunchKernelGGL(mc3::k_select, dim3(n), dim3(256), lds, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
-                     pl.total_chains, c->at<double>(pl.e_cur), c->roots(step), c->roots(step + 1u),
+                     pl.total_chains, c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->roots(step),
+                     c->roots(step + 1u),
                      c->at<mc3::Record>(pl.ring), c->at<unsigned long long>(pl.moves),
                      c->at<unsigned long long>(pl.near), c->at<double>(pl.minm), c->at<double>(pl.e_bar),
                      c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base,
                      ck.clk ? step - ck.base : step, c->slot(step), c->slot(step + 1u), c->cfg.trace_steps,
-                     next_base ? 1 : 0, ck.clk, ck.beta0, ck.beta1, (long long)ck.total);
+                     next_base ? 1 : 0, ck.clk, ck.beta0, ck.beta1, (long long)ck.total, sched,
+                     c->cfg.energy_update == MC3_ENERGY_EXACT ? 1 : 0);
   return check_launch(c, "select kernel");
 }
 
@@ -665,6 +711,7 @@ mc3_status launch_means(mc3_ctx* c, uint32_t step, const ClockArg& ck = ClockArg
 
 mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
   MC3_TRY(launch_means(c, step));
+  MC3_TRY(maybe_recompute(c, step));
   c->have_proposal = next_base;
   c->have_scores = false;
   if (next_base) c->proposal_step = step + 1u;
@@ -672,8 +719,9 @@ mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
   return MC3_OK;
 }
 
-mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = false) {
-  MC3_TRY(launch_select(c, step, beta, next_base, 0, c->pl.total_chains));
+mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = false,
+                     const double* sched = nullptr) {
+  MC3_TRY(launch_select(c, step, beta, next_base, 0, c->pl.total_chains, ClockArg{}, sched));
   return after_select(c, step, next_base);
 }
 
@@ -688,7 +736,8 @@ double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
 // flip sets of step a for the base words a's scoring uses, and whose own slot is the
 // one slot the group does not touch.  Per step: one scoring launch and one selection
 // launch (which also forms the next step's base words).
-mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
+mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total,
+                     const double* sched = nullptr) {
   if (n <= 0) return MC3_OK;
   const int64_t K = c->pl.ahead;
   MC3_TRY(propose_all(c, step0, (int)std::min<int64_t>(K, n), true));
@@ -699,7 +748,7 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
     const bool last = i + 1 == n;
     MC3_TRY(do_score(c, nullptr));
     if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
-    MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last));
+    MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last, sched));
   }
   c->have_proposal = false;
   return MC3_OK;
@@ -785,7 +834,8 @@ mc3_status do_step_n_graph(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, 
   const Plan& pl = c->pl;
   const int64_t K = pl.ahead, L = graph_body(pl);
   const int64_t R = n >= L + K ? (n - K) / L : 0;
-  if (R == 0) return do_step_n(c, step0, n, beta0, beta1, total);
+  // the periodic recompute is launched by the host between steps: not in a replay
+  if (R == 0 || c->cfg.recompute_every > 0) return do_step_n(c, step0, n, beta0, beta1, total);
   MC3_TRY(propose_all(c, step0, (int)K, true));
   c->have_proposal = true;
   c->proposal_step = step0;
@@ -853,10 +903,17 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
   c->ws = (char*)workspace;
   c->stream = (hipStream_t)stream;
   c->device = dev;
-  if (cfg->near_tie_tol >= 0.0)
-    c->tol = cfg->near_tie_tol;
-  else
-    c->tol = cfg->precision == MC3_SPLIT_BF16 ? 1e-4 : 1e-9;
+  // Near ties: a fixed threshold when the caller gives one; otherwise 4 beta eps_E
+  // per instance, eps_E = N 2^-24 the split path's bound on an energy's error (FP32
+  // accumulation of N terms of a field of order one) and N 2^-40 the FP64 paths'.
+  // A draw whose margin exceeds the largest change that errors of eps_E in every
+  // energy can make to the cumulative weights (beta eps_E per unit of total weight)
+  // picks the same node as exact arithmetic would.
+  const bool split_scores = cfg->precision == MC3_SPLIT_BF16 && !c->pl.delta;
+  c->tol = cfg->near_tie_tol >= 0.0 ? cfg->near_tie_tol : 0.0;
+  for (InstH& h : c->pl.inst)
+    h.tie_coef = cfg->near_tie_tol >= 0.0 ? 0.0 : 4.0 * h.desc.N * (split_scores ? 0x1.0p-24 : 0x1.0p-40);
+  c->drift_tol = cfg->drift_tol >= 0.0 ? cfg->drift_tol : 1e-9;
   // the static tables
   const Plan& P = c->pl;
   auto up = [&](size_t off, const void* src, size_t n) {
@@ -867,6 +924,7 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
     e = up(P.units_global_off[k], P.units_global[k].data(), P.units_global[k].size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.units_local_off, P.units_local.data(), P.units_local.size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.pblocks_off, P.pblocks.data(), P.pblocks.size() * sizeof(mc3::PBlock));
+  if (e == hipSuccess) e = up(P.rec_units_off, P.rec_units.data(), P.rec_units.size() * sizeof(mc3::RecUnit));
   // log-priors: the line law's log C(M, v) = lgamma(M+1) - lgamma(v+1) - lgamma(M-v+1);
   // the table law's log q_v (q_v = 0: -infinity) and its cumulative weights
   std::vector<std::vector<double>> priors;
@@ -919,6 +977,9 @@ mc3_status init_couplings_impl(mc3_ctx* c, int32_t instance, const double* J, in
   MC3_TRY(hip_ok(c, hipMemsetAsync(J64, 0, (size_t)Np * Np * 8, c->stream), "clear J"));
   MC3_TRY(hip_ok(c, hipMemcpy2DAsync(J64, (size_t)Np * 8, J, (size_t)ld * 8, (size_t)N * 8, N, hipMemcpyHostToDevice,
                                      c->stream), "upload J"));
+  const long long n = (long long)Np * Np;
+  hipLaunchKernelGGL(mc3::k_mirror_upper, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, J64, Np);
+  MC3_TRY(check_launch(c, "mirror kernel"));
   return pack_couplings(c, h, scale);
 }
 
@@ -958,6 +1019,8 @@ mc3_status reset_buffers(mc3_ctx* c) {
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.moves), 0, C * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.near), 0, C * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift), 0, C * 8, c->stream), "clear"));
+  MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift_ev), 0, C * 8, c->stream), "clear"));
+  c->recomputes = 0;
   {
     std::vector<double> big(C, HUGE_VAL);
     MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.minm), big.data(), big.size() * 8, hipMemcpyHostToDevice,
@@ -983,6 +1046,15 @@ mc3_status reset_buffers(mc3_ctx* c) {
   return MC3_OK;
 }
 
+
+// Upload per-instance schedules (beta0, beta1, total) to the workspace table; waits for
+// the stream first, so that no launch still reading the previous table is overtaken.
+mc3_status upload_sched(mc3_ctx* c, const std::vector<double>& tab) {
+  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "schedule sync"));
+  c->sched_host = tab;
+  return hip_ok(c, hipMemcpyAsync(c->at<double>(c->pl.sched), c->sched_host.data(), tab.size() * 8,
+                                  hipMemcpyHostToDevice, c->stream), "upload schedules");
+}
 
 mc3_status step_args(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1) {
   MC3_TRY(usable(c));
@@ -1087,7 +1159,7 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
                        c->insts(), c->chain_inst(), pl.total_chains, c->key(), c->cfg.chain_base);
     MC3_TRY(check_launch(c, "init spins kernel"));
   }
-  MC3_TRY(launch_energy(c, c->at<double>(pl.e_cur)));
+  MC3_TRY(launch_recompute(c, 0));
   MC3_TRY(reset_buffers(c));
   c->have_chains = true;
   c->have_proposal = c->have_scores = false;
@@ -1123,6 +1195,45 @@ mc3_status mc3_select(mc3_ctx* c, uint32_t step, double beta) {
   return do_select(c, step, beta);
 }
 
+mc3_status mc3_select_betas(mc3_ctx* c, uint32_t step, const double* beta) {
+  MC3_TRY(usable(c));
+  MC3_TRY(no_delta(c, "mc3_select_betas"));
+  if (!beta) return fail(c, MC3_E_ARG, "beta is NULL");
+  if (!c->have_scores) return fail(c, MC3_E_STATE, "select before score_candidates");
+  if (step != c->proposal_step)
+    return fail(c, MC3_E_ARG, "select step %u differs from propose step %u", step, c->proposal_step);
+  const size_t n = c->pl.inst.size();
+  std::vector<double> tab(3 * n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!std::isfinite(beta[i]) || beta[i] < 0.0) return fail(c, MC3_E_ARG, "beta[%zu] must be finite and >= 0", i);
+    tab[3 * i] = beta[i];
+    tab[3 * i + 1] = beta[i];
+    tab[3 * i + 2] = 1.0;
+  }
+  MC3_TRY(upload_sched(c, tab));
+  return do_select(c, step, 0.0, false, c->at<const double>(c->pl.sched));
+}
+
+mc3_status mc3_step_n_schedules(mc3_ctx* c, uint32_t step0, int64_t n, const mc3_schedule* sched) {
+  MC3_TRY(step_args(c, step0, n, 0.0, 0.0));
+  if (!sched) return fail(c, MC3_E_ARG, "sched is NULL");
+  const size_t ni = c->pl.inst.size();
+  std::vector<double> tab(3 * ni);
+  for (size_t i = 0; i < ni; ++i) {
+    const mc3_schedule& q = sched[i];
+    if (!std::isfinite(q.beta0) || !std::isfinite(q.beta1) || q.beta0 < 0.0 || q.beta1 < 0.0)
+      return fail(c, MC3_E_ARG, "schedule %zu: beta must be finite and >= 0", i);
+    if (q.total < 0 || q.total > (int64_t(1) << 53)) return fail(c, MC3_E_ARG, "schedule %zu: bad total", i);
+    tab[3 * i] = q.beta0;
+    tab[3 * i + 1] = q.beta1;
+    tab[3 * i + 2] = (double)q.total;
+  }
+  MC3_TRY(upload_sched(c, tab));
+  const double* dev = c->at<const double>(c->pl.sched);
+  if (c->pl.delta) return do_step_n_delta(c, step0, n, 0.0, 0.0, 1, dev);
+  return do_step_n(c, step0, n, 0.0, 0.0, 1, dev);
+}
+
 mc3_status mc3_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total) {
   MC3_TRY(step_args(c, step0, n, beta0, beta1));
   if (c->pl.delta) return do_step_n_delta(c, step0, n, beta0, beta1, total);
@@ -1145,25 +1256,7 @@ mc3_status mc3_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double
 mc3_status mc3_recompute(mc3_ctx* c) {
   MC3_TRY(usable(c));
   if (!c->have_chains) return fail(c, MC3_E_STATE, "recompute before init_chains");
-  const Plan& pl = c->pl;
-  const size_t C = (size_t)pl.total_chains;
-  MC3_TRY(launch_energy(c, c->at<double>(pl.erecomp)));
-  std::vector<double> er(C), ec(C), dr(C);
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(er.data(), c->at<double>(pl.erecomp), C * 8, hipMemcpyDeviceToHost, c->stream),
-                 "read energies"));
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(ec.data(), c->at<double>(pl.e_cur), C * 8, hipMemcpyDeviceToHost, c->stream),
-                 "read energies"));
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(dr.data(), c->at<double>(pl.drift), C * 8, hipMemcpyDeviceToHost, c->stream),
-                 "read drift"));
-  MC3_TRY(hip_ok(c, hipStreamSynchronize(c->stream), "recompute sync"));
-  for (size_t i = 0; i < C; ++i) {
-    const double x = std::fabs(ec[i] - er[i]);
-    if (x > dr[i]) dr[i] = x;
-  }
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.drift), dr.data(), C * 8, hipMemcpyHostToDevice, c->stream),
-                 "write drift"));
-  MC3_TRY(hip_ok(c, hipMemcpyAsync(c->at<double>(pl.e_cur), er.data(), C * 8, hipMemcpyHostToDevice, c->stream),
-                 "write energies"));
+  MC3_TRY(launch_recompute(c, 1));
   return hip_ok(c, hipStreamSynchronize(c->stream), "recompute sync");
 }
 
@@ -1188,8 +1281,9 @@ mc3_status mc3_measure(mc3_ctx* c, double* e_cur, uint32_t* spin_bits, mc3_summa
     }
   }
   if (summary) {
-    std::vector<unsigned long long> mv(C), nt(C);
+    std::vector<unsigned long long> mv(C), nt(C), de(C);
     std::vector<double> mm(C), dr(C);
+    MC3_TRY(hip_ok(c, hipMemcpy(de.data(), c->at<char>(pl.drift_ev), C * 8, hipMemcpyDeviceToHost), "read"));
     MC3_TRY(hip_ok(c, hipMemcpy(mv.data(), c->at<char>(pl.moves), C * 8, hipMemcpyDeviceToHost), "read"));
     MC3_TRY(hip_ok(c, hipMemcpy(nt.data(), c->at<char>(pl.near), C * 8, hipMemcpyDeviceToHost), "read"));
     MC3_TRY(hip_ok(c, hipMemcpy(mm.data(), c->at<char>(pl.minm), C * 8, hipMemcpyDeviceToHost), "read"));
@@ -1199,11 +1293,14 @@ mc3_status mc3_measure(mc3_ctx* c, double* e_cur, uint32_t* spin_bits, mc3_summa
     summary->near_ties = 0;
     summary->min_margin = HUGE_VAL;
     summary->max_drift = 0.0;
+    summary->recomputes = c->recomputes;
+    summary->drift_events = 0;
     for (size_t i = 0; i < C; ++i) {
       summary->moves += (int64_t)mv[i];
       summary->near_ties += (int64_t)nt[i];
       if (mm[i] < summary->min_margin) summary->min_margin = mm[i];
-      if (dr[i] > summary->max_drift) summary->max_drift = dr[i];
+      if (!(dr[i] <= summary->max_drift)) summary->max_drift = dr[i];
+      summary->drift_events += (int64_t)de[i];
     }
   }
   return MC3_OK;
@@ -1312,7 +1409,7 @@ struct CkHeader {
   char magic[8];
   uint32_t version;
   int32_t n_instances, total_chains, delta;
-  int64_t steps_done;
+  int64_t steps_done, recomputes;
   uint64_t payload;
 };
 struct CkShape {
@@ -1329,7 +1426,8 @@ std::vector<std::pair<char*, size_t>> checkpoint_items(mc3_ctx* c) {
   const size_t C = (size_t)pl.total_chains;
   std::vector<std::pair<char*, size_t>> it;
   it.emplace_back(c->at<char>(pl.e_cur), C * 8);
-  if (pl.delta) it.emplace_back(c->at<char>(pl.u_cur), C * 8);
+  it.emplace_back(c->at<char>(pl.u_cur), C * 8);
+  it.emplace_back(c->at<char>(pl.drift_ev), C * 8);
   it.emplace_back(c->at<char>(pl.moves), C * 8);
   it.emplace_back(c->at<char>(pl.near), C * 8);
   it.emplace_back(c->at<char>(pl.minm), C * 8);
@@ -1366,11 +1464,12 @@ mc3_status mc3_checkpoint_save(mc3_ctx* c, void* buf, size_t* bytes) {
   CkHeader hd;
   std::memset(&hd, 0, sizeof hd);
   std::memcpy(hd.magic, "MC3CKPT1", 8);
-  hd.version = 1;
+  hd.version = 2;
   hd.n_instances = (int32_t)c->pl.inst.size();
   hd.total_chains = c->pl.total_chains;
   hd.delta = c->pl.delta ? 1 : 0;
   hd.steps_done = c->steps_done;
+  hd.recomputes = c->recomputes;
   hd.payload = need - sizeof hd;
   std::memcpy(p, &hd, sizeof hd);
   p += sizeof hd;
@@ -1397,7 +1496,7 @@ mc3_status mc3_checkpoint_load(mc3_ctx* c, const void* buf, size_t bytes) {
   CkHeader hd;
   std::memcpy(&hd, p, sizeof hd);
   p += sizeof hd;
-  if (std::memcmp(hd.magic, "MC3CKPT1", 8) != 0 || hd.version != 1) return fail(c, MC3_E_ARG, "not a checkpoint");
+  if (std::memcmp(hd.magic, "MC3CKPT1", 8) != 0 || hd.version != 2) return fail(c, MC3_E_ARG, "not a checkpoint");
   if (hd.n_instances != (int32_t)c->pl.inst.size() || hd.total_chains != c->pl.total_chains ||
       hd.delta != (c->pl.delta ? 1 : 0) || hd.payload != need - sizeof hd)
     return fail(c, MC3_E_ARG, "checkpoint of a different batch shape or scorer");
@@ -1416,6 +1515,7 @@ mc3_status mc3_checkpoint_load(mc3_ctx* c, const void* buf, size_t bytes) {
   c->have_chains = true;
   c->have_proposal = c->have_scores = false;
   c->steps_done = hd.steps_done;
+  c->recomputes = hd.recomputes;
   return MC3_OK;
 }
 

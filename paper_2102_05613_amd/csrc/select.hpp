@@ -114,15 +114,16 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
   return o;
 }
 
-// Per-chain bookkeeping of a selected step (one lane): carried energy, node-weighted
-// energy, counters and, with a ring, the step's record.
-__device__ __forceinline__ void record_outcome(const RuleOut& o, int g, int r, double tol, uint32_t step,
-                                               int trace_steps, int total_chains, double* e_cur, double* e_bar_out,
-                                               unsigned long long* moves, unsigned long long* near_ties,
-                                               double* min_margin, Record* ring) {
+// Per-chain bookkeeping of a selected step (one lane): carried energy e_new,
+// node-weighted energy, counters and, with a ring, the step's record.  tau is the
+// near-tie threshold of this step.
+__device__ __forceinline__ void record_outcome(const RuleOut& o, double e_new, int g, int r, double tau,
+                                               uint32_t step, int trace_steps, int total_chains, double* e_cur,
+                                               double* e_bar_out, unsigned long long* moves,
+                                               unsigned long long* near_ties, double* min_margin, Record* ring) {
   const bool moved = o.vstar != r;
-  const bool near = o.margin < tol;
-  e_cur[g] = o.e_new;
+  const bool near = o.margin < tau;
+  e_cur[g] = e_new;
   e_bar_out[g] = o.ebar;
   moves[g] += moved ? 1ull : 0ull;
   near_ties[g] += near ? 1ull : 0ull;
@@ -131,13 +132,19 @@ __device__ __forceinline__ void record_outcome(const RuleOut& o, int g, int r, d
     Record rec;
     rec.r = r;
     rec.vstar = o.vstar;
-    rec.e_cur = o.e_new;
+    rec.e_cur = e_new;
     rec.e_bar = o.ebar;
     rec.margin = o.margin;
     rec.flags = (near ? 1u : 0u) | (moved ? 2u : 0u);
     rec.step = step;
     ring[(size_t)(step % (uint32_t)trace_steps) * total_chains + g] = rec;
   }
+}
+
+// beta of step t under the linear schedule beta0 -> beta1 over `total` steps, in the
+// host's operation order: beta0 + (beta1 - beta0) (t / (total - 1)), beta0 if total <= 1.
+__device__ __forceinline__ double beta_of(double beta0, double beta1, long long total, uint32_t t) {
+  return total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)t / (double)(total - 1));
 }
 
 // Node energies of chain c into En (LDS), by the threads t = 0 .. nt-1 of a group: the
@@ -181,55 +188,144 @@ struct ChainWords {
     }
   }
 
-  // The move to node vstar (base ^ P(v*), the base alone for node 0; unchanged when
-  // v* = r) and, with next_base, the next step's base = new state ^ P(r').
+  // Word k of the state after the move to node vstar: base ^ P(v*) (the base alone
+  // for node 0), the old word when v* = r.
+  __device__ __forceinline__ uint32_t new_word(const uint32_t* __restrict__ flipsT, size_t Bp, size_t col0,
+                                               int vstar, int r, int W, int t, int k) const {
+    const int w = t + k * NT;
+    if (w >= W || vstar == r) return s_old[k];
+    uint32_t x = b_cur[k];
+    if (vstar >= 1) x ^= flipsT[(size_t)w * Bp + col0 + (size_t)(vstar - 1)];
+    return x;
+  }
+
+  // The move (x[k] = new_word(.., k)) and, with next_base, the next step's base = new
+  // state ^ P(r').
   __device__ __forceinline__ void store(uint32_t* __restrict__ spins_c, uint32_t* __restrict__ base_next_c,
-                                        const uint32_t* __restrict__ flipsT, size_t Bp, size_t col0, int vstar,
-                                        int r, bool next_base, int W, int t) const {
-    const bool moved = vstar != r;
+                                        const uint32_t (&x)[K], bool moved, bool next_base, int W, int t) const {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int w = t + k * NT;
       if (w < W) {
-        uint32_t x = s_old[k];
-        if (moved) {
-          x = b_cur[k];
-          if (vstar >= 1) x ^= flipsT[(size_t)w * Bp + col0 + (size_t)(vstar - 1)];
-          spins_c[w] = x;
-        }
-        if (next_base) base_next_c[w] = x ^ f_next[k];
+        if (moved) spins_c[w] = x[k];
+        if (next_base) base_next_c[w] = x[k] ^ f_next[k];
       }
     }
   }
 };
 
+// Sum over 256 threads in a fixed order: each wave's DPP tree, then waves 0..3 in order.
+// red4: 4 doubles of LDS.  Every thread gets the result.
+__device__ __forceinline__ double block_sum256(double x, double* red4, int tid) {
+  x = wave_sum(x);
+  if ((tid & 63) == 0) red4[tid >> 6] = x;
+  __syncthreads();
+  const double t = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+  __syncthreads();
+  return t;
+}
+
+// The exact change of the pair sum U = sum_{i<j} J_ij s_i s_j when the sites of D flip
+// (s the old state): the pairs with one site in D change sign, so
+//   dU = -2 sum_{i in D} s_i sum_{j not in D} J_ij s_j,
+// |D| rows of the symmetric J64 in FP64 (exact integers for +-1 couplings).  Called
+// by all 256 threads; dW, sW: the words of D and of the old state in LDS; Dl: LDS for
+// |D| site entries (site | sign << 15).  Wave 0 lists the sites in word order (lane l
+// takes words 4l .. 4l+3, W <= 256); then thread t takes columns j = t, t+256, ..
+// outside D and sums s_i J_ij over the listed rows, eight rows of loads at a time.
+__device__ __forceinline__ double flip_delta_u(const double* __restrict__ J64, int N, int Np, int W,
+                                               const uint32_t* dW, const uint32_t* sW, uint16_t* Dl, int* sh_nd,
+                                               double* red4, int tid) {
+  const int lane = tid & 63;
+  if (tid < 64) {
+    uint32_t wd[4];
+    unsigned long long cnt = 0ull;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = 4 * lane + q;
+      wd[q] = w < W ? dW[w] : 0u;
+      cnt += (unsigned long long)__popc(wd[q]);
+    }
+    const unsigned long long incl = wave_scan_u64(cnt, lane);
+    int pos = (int)(incl - cnt);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = 4 * lane + q;
+      uint32_t bits = wd[q];
+      while (bits) {
+        const int b = __ffs((int)bits) - 1;
+        bits &= bits - 1u;
+        const int k = b < 16 ? 2 * b : 2 * (b - 16) + 1;   // inverse of site_bit
+        const uint32_t neg = (sW[w] >> b) & 1u;
+        Dl[pos++] = (uint16_t)((32 * w + k) | (int)(neg << 15));
+      }
+    }
+    if (lane == 63) *sh_nd = (int)incl;
+  }
+  __syncthreads();
+  const int nd = *sh_nd;
+  double cross = 0.0;
+  for (int j = tid; j < N; j += 256) {
+    const uint32_t wj = (uint32_t)j >> 5, bj = site_bit((uint32_t)j & 31u);
+    if ((dW[wj] >> bj) & 1u) continue;
+    const double* __restrict__ col = J64 + j;
+    double gsum = 0.0;
+    int a = 0;
+    for (; a + 8 <= nd; a += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = col[(size_t)(Dl[a + q] & 0x7FFF) * Np];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) gsum = gsum + ((Dl[a + q] >> 15) ? -v[q] : v[q]);
+    }
+    for (; a < nd; ++a) {
+      const double v = col[(size_t)(Dl[a] & 0x7FFF) * Np];
+      gsum = gsum + ((Dl[a] >> 15) ? -v : v);
+    }
+    cross = cross + (((sW[wj] >> bj) & 1u) ? -gsum : gsum);
+  }
+  return -2.0 * block_sum256(cross, red4, tid);
+}
+
 // One block of 256 threads per chain: node rule (MCMCMC) or Metropolis rate, move,
-// record, and (next_base) the base words of step t+1.  With a step clock (clk non-null,
-// replayed graphs) the step is *clk + step and beta that step's value of the linear
-// schedule beta0 -> beta1 over `total` steps, in the host's operation order.
-//   1. all threads: the node energies (node_energies);
-//   2. wave 0: the rule (apply_rule) and the bookkeeping;
+// record, and (next_base) the base words of step t+1.  beta: the kernel argument;
+// per instance from sched ([instances][3]: beta0, beta1, total) when sched is
+// non-null; with a step clock (clk non-null, replayed graphs) the step is
+// *clk + step and beta that step's value of the schedule (beta0, beta1, total).  The
+// chain carries its unscaled pair sum U (u_cur; E = -(scale U)).  Near ties: margin <
+// tol + beta tie_coef.
+//   1. all threads: the node energies (node_energies; the current node's is
+//      -(scale U));
+//   2. wave 0: the rule (apply_rule);
 //   3. thread w: the new state's word and the next step's base word (ChainWords),
-//      loaded before step 1.
-// Dynamic LDS: 16 (M+1) bytes.
+//      loaded before step 1;
+//   4. the new U: exact = 1: U + dU(D*) in FP64 from the rows of the path set D*
+//      between the old and the new state (flip_delta_u); exact = 0: the chosen
+//      column's pair sum as scored;
+//   5. thread 0: the bookkeeping and the record.
+// Dynamic LDS: max(16 (M+1), 8 W + 2 N) bytes.
 __global__ __launch_bounds__(256) void k_select(
     char* __restrict__ ws, const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
-    int total_chains, double* __restrict__ e_cur, const int32_t* __restrict__ roots_all,
+    int total_chains, double* __restrict__ e_cur, double* __restrict__ u_cur, const int32_t* __restrict__ roots_all,
     const int32_t* __restrict__ roots_next_all, Record* __restrict__ ring, unsigned long long* __restrict__ moves,
     unsigned long long* __restrict__ near_ties, double* __restrict__ min_margin, double* __restrict__ e_bar_out,
     int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, uint32_t slot,
     uint32_t slot_next, int trace_steps, int next_base, const uint32_t* __restrict__ clk, double beta0,
-    double beta1, long long total) {
+    double beta1, long long total, const double* __restrict__ sched, int exact) {
   extern __shared__ double sel_lds[];
-  if (clk) {
-    step += *clk;
-    beta = total <= 1 ? beta0 : beta0 + (beta1 - beta0) * ((double)step / (double)(total - 1));
-  }
-  __shared__ int sh_vstar;
+  __shared__ int sh_vstar, sh_nd;
+  __shared__ double sh_red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = chain_off + blockIdx.x;   // global chain
   if (g >= total_chains) return;
-  const Inst& in = insts[chain_inst[g]];
+  const int ii = chain_inst[g];
+  if (clk) {
+    step += *clk;
+    beta = beta_of(beta0, beta1, total, step);
+  } else if (sched) {
+    beta = beta_of(sched[3 * ii], sched[3 * ii + 1], (long long)sched[3 * ii + 2], step);
+  }
+  const Inst& in = insts[ii];
   const int c = g - in.chain0;            // chain within the instance
   const int M = in.M, W = in.W;
   const size_t Bp = (size_t)in.Bp, col0 = (size_t)c * M;
@@ -238,11 +334,13 @@ __global__ __launch_bounds__(256) void k_select(
   const uint32_t* __restrict__ base = ws_at<const uint32_t>(ws, in.base[step & 1u]) + (size_t)c * W;
   const uint32_t* __restrict__ flipsT_next = flips_at(ws, in, slot_next);
   uint32_t* __restrict__ base_next = ws_at<uint32_t>(ws, in.base[(step + 1u) & 1u]) + (size_t)c * W;
+  const double* __restrict__ partial = ws_at<const double>(ws, in.partial);
   const int nodes = M + 1;
   double* En = sel_lds;                                                              // [nodes]
   unsigned long long* Qn = reinterpret_cast<unsigned long long*>(sel_lds + nodes);   // [nodes]
   const int r = metropolis ? 0 : roots_all[in.chain0 + c];
-  const double ecur = e_cur[g];
+  const double U = u_cur[g];
+  const double ecur = -(in.scale * U);
   long long col_next = -1;
   if (next_base) {
     const int r1 = roots_next_all[in.chain0 + c];
@@ -251,20 +349,46 @@ __global__ __launch_bounds__(256) void k_select(
   ChainWords<256> cw;
   cw.load(spins, base, flipsT_next, Bp, col_next, W, tid);
 
-  node_energies(En, ws_at<const double>(ws, in.partial), in.P, Bp, col0, M, r, in.scale, ecur, tid, 256);
+  node_energies(En, partial, in.P, Bp, col0, M, r, in.scale, ecur, tid, 256);
   __syncthreads();
+  RuleOut o;
   if (wave == 0) {
     const uint4 ub = stream_block(key, kTagSelect, chain_base + (uint32_t)g, step, 0u, 0u);
-    const RuleOut o = apply_rule(En, Qn, M, r, ecur, metropolis, beta, u53_of(ub.x, ub.y), lane,
-                                 in.prior ? ws_at<const double>(ws, in.prior) : nullptr);
-    if (lane == 0) {
-      sh_vstar = o.vstar;
-      record_outcome(o, g, r, tol, step, trace_steps, total_chains, e_cur, e_bar_out, moves, near_ties, min_margin,
-                     ring);
-    }
+    o = apply_rule(En, Qn, M, r, ecur, metropolis, beta, u53_of(ub.x, ub.y), lane,
+                   in.prior ? ws_at<const double>(ws, in.prior) : nullptr);
+    if (lane == 0) sh_vstar = o.vstar;
   }
   __syncthreads();
-  cw.store(spins, base_next, flipsT, Bp, col0, sh_vstar, r, next_base != 0, W, tid);
+  const int vstar = sh_vstar;
+  const bool moved = vstar != r;
+  uint32_t x[ChainWords<256>::K];
+  x[0] = cw.new_word(flipsT, Bp, col0, vstar, r, W, tid, 0);
+  cw.store(spins, base_next, x, moved, next_base != 0, W, tid);
+  double u_new = U;
+  if (moved) {
+    if (exact) {
+      uint32_t* dW = reinterpret_cast<uint32_t*>(sel_lds);   // En and Qn are no longer read
+      uint32_t* sW = dW + W;
+      if (tid < W) {
+        dW[tid] = cw.s_old[0] ^ x[0];
+        sW[tid] = cw.s_old[0];
+      }
+      __syncthreads();
+      u_new = U + flip_delta_u(ws_at<const double>(ws, in.J64), in.N, in.Np, W, dW, sW,
+                               reinterpret_cast<uint16_t*>(sW + W), &sh_nd, sh_red, tid);
+    } else if (tid == 0) {
+      // the chosen node's column: node v >= 1 is column v-1, the hub (r >= 1) column r-1
+      const size_t col = col0 + (size_t)(vstar >= 1 ? vstar - 1 : r - 1);
+      double acc = 0.0;
+      for (int q = 0; q < in.P; ++q) acc += partial[(size_t)q * Bp + col];
+      u_new = acc;
+    }
+  }
+  if (tid == 0) {
+    u_cur[g] = u_new;
+    record_outcome(o, -(in.scale * u_new), g, r, tol + beta * in.tie_coef, step, trace_steps, total_chains, e_cur,
+                   e_bar_out, moves, near_ties, min_margin, ring);
+  }
 }
 
 // ------------------------------------------------------------------- means trace
@@ -308,48 +432,6 @@ __global__ __launch_bounds__(256) void k_chain_means(double* __restrict__ trace,
 // The step clock of replayed graphs: clk = value (add = 0) or clk += value (one thread).
 __global__ void k_clock(uint32_t* __restrict__ clk, uint32_t value, int add) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clk[0] = add ? clk[0] + value : value;
-}
-
-// ------------------------------------------------------------------- FP64 energy
-
-// E(s) = -scale * sum_{i<j} J_ij s_i s_j in FP64, one block (256 threads) per global
-// chain; optionally also the unscaled pair sum U = sum_{i<j} J_ij s_i s_j.  Thread t
-// owns columns j = t, t+256, ...; row i is read coalesced; a fixed-order tree combines
-// the threads.
-__global__ __launch_bounds__(256) void k_energy_f64(double* __restrict__ out, double* __restrict__ pair_sum,
-                                                    char* __restrict__ ws, const Inst* __restrict__ insts,
-                                                    const int32_t* __restrict__ chain_inst) {
-  __shared__ double red[256];
-  const int g = blockIdx.x;
-  const Inst& in = insts[chain_inst[g]];
-  const int c = g - in.chain0;
-  const int N = in.N, Np = in.Np, W = in.W;
-  const double scale = in.scale;
-  const double* __restrict__ J64 = ws_at<const double>(ws, in.J64);
-  const uint32_t* s = ws_at<const uint32_t>(ws, in.spins) + (size_t)c * W;
-  double acc = 0.0;
-  for (int i = 0; i < N; ++i) {
-    const double si = ((s[i >> 5] >> site_bit(i & 31)) & 1u) ? -1.0 : 1.0;
-    const double* row = J64 + (size_t)i * Np;
-    double rs = 0.0;
-    for (int j = (int)threadIdx.x; j < N; j += 256) {
-      if (j > i) {
-        const double sj = ((s[j >> 5] >> site_bit(j & 31)) & 1u) ? -1.0 : 1.0;
-        rs += row[j] * sj;
-      }
-    }
-    acc += si * rs;
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[g] = -(scale * red[0]);
-    if (pair_sum) pair_sum[g] = red[0];
-  }
 }
 
 }  // namespace mc3

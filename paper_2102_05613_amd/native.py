@@ -25,11 +25,13 @@ MC3_FP64, MC3_SPLIT_BF16 = 0, 1
 MC3_RULE_MCMCMC, MC3_RULE_METROPOLIS = 0, 1
 MC3_SCORER_GEMM, MC3_SCORER_DELTA, MC3_SCORER_AUTO = 0, 1, 2
 MC3_LAW_UNIFORM, MC3_LAW_LINE, MC3_LAW_TABLE = 0, 1, 2
+MC3_ENERGY_EXACT, MC3_ENERGY_SCORED = 0, 1
 
 PRECISIONS = {"fp64": MC3_FP64, "split_bf16": MC3_SPLIT_BF16}
 RULES = {"mcmcmc": MC3_RULE_MCMCMC, "metropolis": MC3_RULE_METROPOLIS}
 SCORERS = {"gemm": MC3_SCORER_GEMM, "delta": MC3_SCORER_DELTA, "auto": MC3_SCORER_AUTO}
 LAWS = {"uniform": MC3_LAW_UNIFORM, "line": MC3_LAW_LINE, "table": MC3_LAW_TABLE}
+ENERGY_UPDATES = {"exact": MC3_ENERGY_EXACT, "scored": MC3_ENERGY_SCORED}
 
 STATUS_NAMES = {0: "MC3_OK", -1: "MC3_E_ARG", -3: "MC3_E_DEVICE", -4: "MC3_E_STATE",
                 -5: "MC3_E_UNSUPPORTED", -6: "MC3_E_NUMERIC", -7: "MC3_E_WORKSPACE"}
@@ -40,7 +42,7 @@ EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_coupling
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
            "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
            "mc3_init_couplings_instance", "mc3_generate_couplings", "mc3_step_n_per_instance", "mc3_step_n_graph", "mc3_checkpoint_save",
-           "mc3_checkpoint_load", "mc3_set_generation"]
+           "mc3_checkpoint_load", "mc3_set_generation", "mc3_select_betas", "mc3_step_n_schedules"]
 
 
 class Config(ctypes.Structure):
@@ -50,7 +52,8 @@ class Config(ctypes.Structure):
                 ("chain_base", ctypes.c_uint32), ("mean_steps", ctypes.c_int32),
                 ("near_tie_tol", ctypes.c_double), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
                 ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double)),
-                ("tile_cols", ctypes.c_int32)]
+                ("tile_cols", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
+                ("energy_update", ctypes.c_int32), ("drift_tol", ctypes.c_double)]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -64,12 +67,18 @@ class BatchConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("near_tie_tol", ctypes.c_double),
                 ("instances", ctypes.POINTER(InstanceDesc)), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
                 ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double)),
-                ("tile_cols", ctypes.c_int32)]
+                ("tile_cols", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
+                ("energy_update", ctypes.c_int32), ("drift_tol", ctypes.c_double)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("beta0", ctypes.c_double), ("beta1", ctypes.c_double), ("total", ctypes.c_int64)]
 
 
 class Summary(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int64), ("moves", ctypes.c_int64), ("near_ties", ctypes.c_int64),
-                ("min_margin", ctypes.c_double), ("max_drift", ctypes.c_double)]
+                ("min_margin", ctypes.c_double), ("max_drift", ctypes.c_double),
+                ("recomputes", ctypes.c_int64), ("drift_events", ctypes.c_int64)]
 
 
 RECORD_DTYPE = np.dtype([("r", np.int32), ("vstar", np.int32), ("e_cur", np.float64), ("e_bar", np.float64),
@@ -122,6 +131,8 @@ def lib() -> ctypes.CDLL:
     L.mc3_checkpoint_save.argtypes = [vp, vp, P(c.c_size_t)]
     L.mc3_checkpoint_load.argtypes = [vp, vp, c.c_size_t]
     L.mc3_set_generation.argtypes = [vp, c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
+    L.mc3_select_betas.argtypes = [vp, c.c_uint32, P(c.c_double)]
+    L.mc3_step_n_schedules.argtypes = [vp, c.c_uint32, c.c_int64, P(Schedule)]
     L.mc3_last_error.argtypes = [vp]
     L.mc3_last_error.restype = c.c_char_p
     L.mc3_version.restype = c.c_char_p
@@ -135,14 +146,18 @@ def lib() -> ctypes.CDLL:
 def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: str = "split_bf16",
                 rule: str = "mcmcmc", trace_steps: int = 0, seed: int = 0, chain_base: int = 0,
                 near_tie_tol: float = -1.0, mean_steps: int = 0, scorer: str = "gemm", arity: int = 0,
-                law: str = "uniform", law_table=None, tile_cols: int = 0) -> Config:
+                law: str = "uniform", law_table=None, tile_cols: int = 0, recompute_every: int = 0,
+                energy_update: str = "exact", drift_tol: float = -1.0) -> Config:
     """arity 0: the M-ary star; law "line" (arity 1): the line-graph addition process;
     law "table": root weights law_table[0..M]; tile_cols 0: the split scoring tile width
-    by column count, else 128, 256 or 512."""
+    by column count, else 128, 256 or 512; recompute_every K > 0: FP64 recompute of the
+    carried energies after every step t with (t+1) % K == 0; energy_update "exact" or
+    "scored"."""
     tab = _table(law_table)
     cfg = Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base,
                  mean_steps, near_tie_tol, SCORERS[scorer], arity, LAWS[law],
-                 None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols)
+                 None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols,
+                 recompute_every, ENERGY_UPDATES[energy_update], drift_tol)
     cfg._keep_table = tab   # the table lives as long as the config
     return cfg
 
@@ -156,7 +171,8 @@ def _table(law_table):
 def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcmcmc", trace_steps: int = 0,
                       seed: int = 0, chain_base: int = 0, near_tie_tol: float = -1.0,
                       mean_steps: int = 0, scorer: str = "gemm", arity: int = 0, law: str = "uniform",
-                      law_table=None, tile_cols: int = 0) -> BatchConfig:
+                      law_table=None, tile_cols: int = 0, recompute_every: int = 0, energy_update: str = "exact",
+                      drift_tol: float = -1.0) -> BatchConfig:
     """instances: sequence of (N, M, chains, kmin, kmax); law "table": law_table holds
     the root weights of every instance, M_i+1 values each, in instance order;
     tile_cols as in make_config."""
@@ -164,7 +180,8 @@ def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcm
     tab = _table(law_table)
     cfg = BatchConfig(len(instances), PRECISIONS[precision], RULES[rule], trace_steps, mean_steps, chain_base, seed,
                       near_tie_tol, ctypes.cast(arr, ctypes.POINTER(InstanceDesc)), SCORERS[scorer], arity, LAWS[law],
-                      None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols)
+                      None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols,
+                      recompute_every, ENERGY_UPDATES[energy_update], drift_tol)
     cfg._keep = arr   # the descriptor array lives as long as the config
     cfg._keep_table = tab
     return cfg
@@ -257,6 +274,20 @@ class Context:
 
     def select(self, step: int, beta: float):
         self._check(lib().mc3_select(self.h, step, float(beta)), "mc3_select")
+
+    def select_betas(self, step: int, betas):
+        """mc3_select with one inverse temperature per instance."""
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        assert b.shape == (len(self.instances),)
+        self._check(lib().mc3_select_betas(self.h, step, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "mc3_select_betas")
+
+    def step_n_schedules(self, step0: int, n: int, schedules):
+        """mc3_step_n with one (beta0, beta1, total) schedule per instance."""
+        assert len(schedules) == len(self.instances)
+        arr = (Schedule * len(schedules))(*[Schedule(float(a), float(b), int(t)) for a, b, t in schedules])
+        self._check(lib().mc3_step_n_schedules(self.h, step0, n, ctypes.cast(arr, ctypes.POINTER(Schedule))),
+                    "mc3_step_n_schedules")
 
     def step_n(self, step0: int, n: int, beta0: float, beta1: float, total: int):
         self._check(lib().mc3_step_n(self.h, step0, n, float(beta0), float(beta1), total), "mc3_step_n")

@@ -66,6 +66,11 @@ int main(void) {
          offsetof(mc3_batch_config, arity), offsetof(mc3_batch_config, law));
   printf("%zu %zu\n", offsetof(mc3_config, law_table), offsetof(mc3_batch_config, law_table));
   printf("%zu %zu\n", offsetof(mc3_config, tile_cols), offsetof(mc3_batch_config, tile_cols));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(mc3_config, recompute_every), offsetof(mc3_config, energy_update),
+         offsetof(mc3_config, drift_tol), offsetof(mc3_batch_config, recompute_every),
+         offsetof(mc3_batch_config, energy_update), offsetof(mc3_batch_config, drift_tol));
+  printf("%zu %zu %zu\n", offsetof(mc3_summary, recomputes), offsetof(mc3_summary, drift_events),
+         sizeof(mc3_schedule));
   return 0;
 }
 '''
@@ -84,7 +89,12 @@ int main(void) {
                     native.Config.scorer.offset, native.Config.arity.offset, native.Config.law.offset,
                     native.BatchConfig.arity.offset, native.BatchConfig.law.offset,
                     native.Config.law_table.offset, native.BatchConfig.law_table.offset,
-                    native.Config.tile_cols.offset, native.BatchConfig.tile_cols.offset]
+                    native.Config.tile_cols.offset, native.BatchConfig.tile_cols.offset,
+                    native.Config.recompute_every.offset, native.Config.energy_update.offset,
+                    native.Config.drift_tol.offset, native.BatchConfig.recompute_every.offset,
+                    native.BatchConfig.energy_update.offset, native.BatchConfig.drift_tol.offset,
+                    native.Summary.recomputes.offset, native.Summary.drift_events.offset,
+                    ctypes.sizeof(native.Schedule)]
 
 
 def test_version(lib):

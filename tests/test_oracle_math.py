@@ -150,3 +150,42 @@ def test_select_margin_and_ebar():
     w = np.exp(-(E - E.min()))
     assert ebar == pytest.approx((w * E).sum() / w.sum(), rel=1e-15)
     assert 0.0 <= margin <= 0.5
+
+
+@pytest.mark.parametrize("beta", [0.3, 1.7, 9.0])
+def test_select_margin_is_the_integer_distance(beta):
+    """The selected node and its margin, rebuilt in Python integers from the definition:
+    fixed-point weights q_v = floor(2^52 exp(l_v - max l)) with l_v = -(beta (E_v - Emin))
+    (the oracle's own exp, pinned to libm above), Q_v their running sums, W = Q_M,
+    t = floor(u W / 2^53), v* = the first v with Q_v > t, and margin
+    min(t - Q_{v*-1}, Q_{v*} - t) / W.  An off-by-one in either distance, a wrong
+    interval edge or a threshold taken in floating point fails."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    hit_lo = hit_hi = 0
+    for trial in range(400):
+        nodes = int(rng.integers(2, 40))
+        E = rng.normal(size=nodes) * 3.0
+        emin = float(E.min())
+        ls = [-(beta * (float(e) - emin)) for e in E]
+        lmax = max(ls)
+        q = [math.floor(oracle.exp(l - lmax) * 2.0 ** 52) for l in ls]
+        Q = list(np.cumsum(np.array(q, dtype=object)))
+        W = Q[-1]
+        # draws near interval edges as well as anywhere
+        if trial % 2:
+            v = int(rng.integers(0, nodes))
+            edge = Q[v - 1] if v else 0
+            u = max(0, min(2 ** 53 - 1, -(-edge * 2 ** 53 // W) + int(rng.integers(-3, 4))))
+        else:
+            u = int(rng.integers(0, 2 ** 53))
+        t = (u * W) >> 53
+        vs = next(v for v in range(nodes) if Q[v] > t)
+        lo = Q[vs - 1] if vs else 0
+        d1, d2 = t - lo, Q[vs] - t
+        hit_lo += d1 < d2
+        hit_hi += d2 < d1
+        margin = float(min(d1, d2)) / float(W)
+        v_o, _, m_o, W_o = oracle.select_mcmcmc(E, beta, u)
+        assert (v_o, W_o) == (vs, W)
+        assert m_o == margin, (trial, m_o, margin)
+    assert hit_lo > 20 and hit_hi > 20   # both distances decided some margins
