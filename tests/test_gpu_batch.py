@@ -9,12 +9,11 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import announce, compare_trajectory, oracle_candidates
+from gpu_helpers import announce, compare_trajectory, eps_energy, oracle_candidates
 from paper_2102_05613_amd import inputs, native
 
 pytestmark = pytest.mark.gpu
 
-RTOL = {"fp64": 1e-6, "split_bf16": 1e-4}
 # (N, M, chains, kmin, kmax): ragged sizes, a one-block instance, M = 1, one chain
 DESCS = [(32, 4, 2, 1, 1), (200, 9, 3, 1, 5), (129, 16, 1, 1, 3), (64, 1, 4, 1, 2), (300, 70, 2, 2, 19)]
 SEED, BASE = 9, 5
@@ -130,7 +129,7 @@ def _sampled_energy_check(ctx, descs, prec, step, instances, chains_per, seed, b
             _, cols = oracle_candidates(seed, base + g, step, N, M, kmin, kmax, s)
             Eo = np.array([oracle.energy(J, scale, x) for x in cols])
             Ec = Eg[int(col0[i]) + c * M:int(col0[i]) + (c + 1) * M]
-            np.testing.assert_allclose(Ec, Eo, rtol=RTOL[prec], atol=RTOL[prec])
+            np.testing.assert_allclose(Ec, Eo, rtol=0, atol=eps_energy(prec, N))
             worst = max(worst, float(np.max(np.abs(Ec - Eo) / np.maximum(np.abs(Eo), 1e-300))))
     return worst
 

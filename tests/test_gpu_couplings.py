@@ -7,12 +7,11 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import announce, compare_trajectory, gpu_spins, oracle_candidates
+from gpu_helpers import announce, compare_trajectory, eps_energy, gpu_spins, oracle_candidates
 from paper_2102_05613_amd import native
 
 pytestmark = pytest.mark.gpu
 
-RTOL = {"fp64": 1e-6, "split_bf16": 1e-4}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -60,7 +59,7 @@ def test_gauss_generated_energies_match_oracle(prec, N, M, chains, kmax):
     for c in range(chains):
         _, cols = oracle_candidates(6, c, 7, N, M, 1, kmax, s[c])
         Eo = np.array([oracle.energy(J, scale, x) for x in cols])
-        np.testing.assert_allclose(Eg[c], Eo, rtol=RTOL[prec], atol=RTOL[prec])
+        np.testing.assert_allclose(Eg[c], Eo, rtol=0, atol=eps_energy(prec, N))
 
 
 def test_generated_couplings_reject_bad_arguments():
