@@ -265,6 +265,25 @@ mc3_status mc3_workspace_size(const mc3_config* cfg, size_t* bytes);
  * Validates the configuration before any HIP call. */
 mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out);
 
+/* Largest workspace a context from mc3_create_noalloc can have: 16 MiB. */
+#define MC3_NOALLOC_BYTES (16u << 20)
+
+/* mc3_create for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the workspace is a
+ * fixed array of MC3_NOALLOC_BYTES in the library's device code, one per GPU, held
+ * until the process ends; no hipMalloc, hipFree or other allocating call is made.
+ * Every other call works on the context as on one from mc3_create.  The array is
+ * shared by every context of this kind on a device: one such context per device at a
+ * time (MC3_E_STATE while another one lives; mc3_destroy waits for its stream and
+ * frees the array for the next).  Calls from several threads that overlap on one
+ * device's array race.  The array keeps what the last context left in it; the calls
+ * that set a context up (mc3_init_couplings, mc3_init_chains, mc3_checkpoint_load)
+ * clear or write everything a step reads first, as they do for a fresh workspace.
+ * Errors: MC3_E_ARG / MC3_E_UNSUPPORTED as mc3_create; MC3_E_WORKSPACE when
+ * mc3_workspace_size(cfg) exceeds MC3_NOALLOC_BYTES; MC3_E_DEVICE when the array's
+ * address cannot be obtained. */
+mc3_status mc3_create_noalloc(const mc3_config* cfg, void* stream, mc3_ctx** out);
+
 /* Batch forms of mc3_workspace_size and mc3_create (same contracts).  Every call
  * below works on a batch context: per-chain arrays span the global chains, the
  * energies of mc3_score_candidates are the instances' [chains][M] blocks one after

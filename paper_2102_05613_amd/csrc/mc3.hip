@@ -9,11 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -31,6 +33,45 @@ constexpr int kMaxAhead = 16;    // steps of flip sets drawn per proposal launch
 constexpr size_t kFlipBudget = size_t(512) << 20;  // bytes of flip-set ring, about
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// The workspace of contexts made by mc3_create_noalloc: a fixed device array, one copy
+// per GPU the library runs on, held until the process ends.  Host code never passes
+// this name to a kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[MC3_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};     // the array's device address, per device
+bool g_scratch_busy[kMaxDevices] = {};     // a live context holds that device's array
+
+// Reserve the current device's array: its address (looked up once per device, with the
+// device current) in *ptr.  MC3_E_STATE if a context already holds it.
+mc3_status reserve_scratch(int dev, void** ptr) {
+  if (dev < 0 || dev >= kMaxDevices) return MC3_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_busy[dev]) return MC3_E_STATE;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return MC3_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  g_scratch_busy[dev] = true;
+  *ptr = g_scratch_ptr[dev];
+  return MC3_OK;
+}
+
+void release_scratch(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
+}
 
 struct InstH {
   mc3_instance_desc desc;
@@ -388,6 +429,7 @@ struct mc3_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   bool have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
+  bool noalloc = false;      // the workspace is the device's fixed array (mc3_create_noalloc)
   uint32_t proposal_step = 0;
   double tol = 0.0;          // fixed part of the near-tie threshold (plus beta * tie_coef per instance)
   double drift_tol = 1e-9;   // relative drift counted as an event by the periodic recompute
@@ -879,7 +921,10 @@ mc3_status do_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double 
   return MC3_OK;
 }
 
-mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out) {
+// fixed_ws: the workspace is the library's own fixed array (its address is known to be
+// device memory).
+mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t bytes, void* stream, mc3_ctx** out,
+                       bool fixed_ws = false) {
   if (!out) return MC3_E_ARG;
   *out = nullptr;
   if (validate_batch(cfg)) return MC3_E_ARG;
@@ -890,7 +935,7 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MC3_E_DEVICE;
   hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+  if (!fixed_ws && (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice)) {
     (void)hipGetLastError();
     return MC3_E_WORKSPACE;
   }
@@ -1099,8 +1144,34 @@ mc3_status mc3_create(const mc3_config* cfg, void* workspace, size_t bytes, void
   return create_impl(&b, workspace, bytes, stream, out);
 }
 
+mc3_status mc3_create_noalloc(const mc3_config* cfg, void* stream, mc3_ctx** out) {
+  if (out) *out = nullptr;
+  if (!cfg || !out) return MC3_E_ARG;
+  mc3_instance_desc one;
+  const mc3_batch_config b = single_to_batch(cfg, &one);
+  if (validate_batch(&b)) return MC3_E_ARG;
+  size_t lds = 0;
+  if (resolve_delta(b, &lds) < 0) return MC3_E_UNSUPPORTED;
+  if (make_plan(b).total > (size_t)MC3_NOALLOC_BYTES) return MC3_E_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MC3_E_DEVICE;
+  void* ws = nullptr;
+  MC3_TRY(reserve_scratch(dev, &ws));
+  const mc3_status st = create_impl(&b, ws, (size_t)MC3_NOALLOC_BYTES, stream, out, true);
+  if (st != MC3_OK) {
+    release_scratch(dev);
+    return st;
+  }
+  (*out)->noalloc = true;
+  return MC3_OK;
+}
+
 mc3_status mc3_destroy(mc3_ctx* ctx) {
   if (!ctx) return MC3_E_ARG;
+  if (ctx->noalloc) {
+    (void)hipStreamSynchronize(ctx->stream);   // the array is free once its last kernel ends
+    release_scratch(ctx->device);
+  }
   for (hipEvent_t e : ctx->t_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);

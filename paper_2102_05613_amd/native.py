@@ -42,7 +42,8 @@ EXPORTS = ["mc3_workspace_size", "mc3_create", "mc3_destroy", "mc3_init_coupling
            "mc3_read_records", "mc3_read_candidates", "mc3_read_means", "mc3_timing_enable", "mc3_timing_read",
            "mc3_sync", "mc3_last_error", "mc3_version", "mc3_batch_workspace_size", "mc3_batch_create",
            "mc3_init_couplings_instance", "mc3_generate_couplings", "mc3_step_n_per_instance", "mc3_step_n_graph", "mc3_checkpoint_save",
-           "mc3_checkpoint_load", "mc3_set_generation", "mc3_select_betas", "mc3_step_n_schedules"]
+           "mc3_checkpoint_load", "mc3_set_generation", "mc3_select_betas", "mc3_step_n_schedules", "mc3_create_noalloc"]
+NOALLOC_BYTES = 16 << 20   # MC3_NOALLOC_BYTES
 
 
 class Config(ctypes.Structure):
@@ -107,6 +108,7 @@ def lib() -> ctypes.CDLL:
     vp = c.c_void_p
     L.mc3_workspace_size.argtypes = [P(Config), P(c.c_size_t)]
     L.mc3_create.argtypes = [P(Config), vp, c.c_size_t, vp, P(vp)]
+    L.mc3_create_noalloc.argtypes = [P(Config), vp, P(vp)]
     L.mc3_destroy.argtypes = [vp]
     L.mc3_init_couplings.argtypes = [vp, P(c.c_double), c.c_int64, c.c_double]
     L.mc3_init_chains.argtypes = [vp, vp]
@@ -200,9 +202,10 @@ def workspace_size(cfg) -> int:
 
 class Context:
     """One SK instance (Config) or a batch of instances (BatchConfig) with their
-    chains on the current GPU."""
+    chains on the current GPU.  noalloc (a Config only): mc3_create_noalloc, the
+    library's fixed device array as the workspace instead of a torch allocation."""
 
-    def __init__(self, cfg, device=None):
+    def __init__(self, cfg, device=None, noalloc: bool = False):
         import torch
         self.cfg = cfg
         if isinstance(cfg, BatchConfig):
@@ -212,10 +215,20 @@ class Context:
         self.N, self.M = self.instances[0][0], self.instances[0][1]
         self.chains = sum(d[2] for d in self.instances)
         self.words = max((d[0] + 31) // 32 for d in self.instances)
+        h = ctypes.c_void_p()
+        if noalloc:
+            if isinstance(cfg, BatchConfig):
+                raise ValueError("mc3_create_noalloc takes a single-instance Config")
+            self.workspace = None
+            self.stream = torch.cuda.current_stream(device)
+            st = lib().mc3_create_noalloc(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+            if st != MC3_OK:
+                raise MC3Error(st, "mc3_create_noalloc")
+            self.h = h
+            return
         nbytes = workspace_size(cfg)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
         self.stream = torch.cuda.current_stream(self.workspace.device)
-        h = ctypes.c_void_p()
         create = lib().mc3_batch_create if isinstance(cfg, BatchConfig) else lib().mc3_create
         st = create(ctypes.byref(cfg), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
