@@ -220,22 +220,24 @@ def _ratios_vs(study, base):
 
 def _thermalize(w, J, scale, T, T_long):
     """The paper's SK comparison (Fig. fig_sk) on this instance and the benchmark
-    workload's own setting.  T: steps of the graph runs; T_long: steps of the
-    single-update Metropolis runs (field-update scorer, microseconds a step), long
-    enough for them to converge too."""
+    workload's own setting.  T: the window's scale (window = T / 100); the graph runs
+    take 2 T steps (the line graph 3 T, the FP64 pair-sum star T, slower per step);
+    T_long: steps of the single-update Metropolis runs (field-update scorer,
+    microseconds a step), long enough for them to converge too."""
     window = max(10, T // 100)
+    T2, T3 = 2 * T, 3 * T
     paper = _thermalize_study(
         w, J, scale, 1.0,
         "the paper's SK comparison (Fig. fig_sk) on this instance: L = 1024, T = 1, single-spin-flip edges; "
         "line-graph addition process of 2^7 nodes, binary tree of depth 7, ternary of depth 5, 16-ary of "
         "depth 3 (uniform root), the 129-node star, against single-update Metropolis",
-        [("line_2e7", "split_bf16", "mcmcmc", 127, 1, 1, "gemm", 1, "line", T),
-         ("binary_depth7", "fp64", "mcmcmc", 126, 1, 1, "delta", 2, "uniform", T),
-         ("ternary_depth5", "fp64", "mcmcmc", 120, 1, 1, "delta", 3, "uniform", T),
-         ("16ary_depth3", "fp64", "mcmcmc", 272, 1, 1, "delta", 16, "uniform", T),
-         ("star_129_split_bf16", "split_bf16", "mcmcmc", 128, 1, 1, "gemm", 0, "uniform", T),
-         ("star_129_fp64", "fp64", "mcmcmc", 128, 1, 1, "gemm", 0, "uniform", max(10 * window, T // 10)),
-         ("star_129_field_update", "fp64", "mcmcmc", 128, 1, 1, "delta", 0, "uniform", T),
+        [("line_2e7", "split_bf16", "mcmcmc", 127, 1, 1, "gemm", 1, "line", T3),
+         ("binary_depth7", "fp64", "mcmcmc", 126, 1, 1, "delta", 2, "uniform", T2),
+         ("ternary_depth5", "fp64", "mcmcmc", 120, 1, 1, "delta", 3, "uniform", T2),
+         ("16ary_depth3", "fp64", "mcmcmc", 272, 1, 1, "delta", 16, "uniform", T2),
+         ("star_129_split_bf16", "split_bf16", "mcmcmc", 128, 1, 1, "gemm", 0, "uniform", T2),
+         ("star_129_fp64", "fp64", "mcmcmc", 128, 1, 1, "gemm", 0, "uniform", T),
+         ("star_129_field_update", "fp64", "mcmcmc", 128, 1, 1, "delta", 0, "uniform", T2),
          ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform", T_long)],
         window)
     paper["t1pct_ratio_metropolis_over_graph"] = _ratios_vs(paper, "metropolis_m1_single_flip")
@@ -243,8 +245,8 @@ def _thermalize(w, J, scale, T, T_long):
                             "Metropolis (Sec. 'Numerical results', Fig. fig_sk; hardware and precision not stated)")
     own = _thermalize_study(
         w, J, scale, w.beta0, "the benchmark workload's own flip sets (1..128 sites) and beta = 2",
-        [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax, "gemm", 0, "uniform", T),
-         ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, w.kmin, w.kmax, "gemm", 0, "uniform", max(10 * window, T // 10)),
+        [("mcmcmc_split_bf16", "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax, "gemm", 0, "uniform", T2),
+         ("mcmcmc_fp64", "fp64", "mcmcmc", w.M, w.kmin, w.kmax, "gemm", 0, "uniform", max(10 * window, T // 5)),
          ("metropolis_m1_single_flip", "fp64", "metropolis", 1, 1, 1, "delta", 0, "uniform", T_long)],
         window)
     own["t1pct_ratio_metropolis_over_graph"] = _ratios_vs(own, "metropolis_m1_single_flip")
@@ -552,6 +554,34 @@ def _set_variant(reps=20):
     return out
 
 
+def _scorer_comparison(w, J, scale, steps=10):
+    """The headline workload (N = 1024, 256 chains x M = 128, flip sets 1..128, beta = 2)
+    stepped with each scorer: split-BF16 and FP64 pair sums on the matrix cores, and the
+    FP64 field update (energies as differences: |F| field reads and |F|^2/2 coupling
+    gathers per candidate, the algorithmic minimum); then the autotuner's timed choice."""
+    import torch
+    from paper_2102_05613_amd import autotune, native
+    out = {"steps": steps}
+    for name, prec, scorer in (("pair_sum_split_bf16", "split_bf16", "gemm"), ("pair_sum_fp64", "fp64", "gemm"),
+                               ("field_update_fp64", "fp64", "delta")):
+        ctx = _context(w, prec, "mcmcmc", w.M, w.kmin, w.kmax, J, scale, scorer=scorer)
+        ctx.step_n(0, 3, w.beta0, w.beta0, 1)
+        ms = _timed_steps(ctx, 3, steps, w.beta0, w.beta0, 1)
+        ctx.close()
+        out[name] = {"ms_per_step": ms / steps, "candidates_per_s": w.chains * w.M * steps / (ms / 1e3)}
+    make = lambda scorer, width: native.make_config(w.N, w.M, w.chains, w.kmin, w.kmax, precision="split_bf16",
+                                                    seed=w.seed, scorer=scorer, tile_cols=width)
+
+    def init(ctx):
+        ctx.init_couplings(J, scale)
+        ctx.init_chains()
+
+    r = autotune.tune_scorer(make, init, beta=w.beta0, steps=steps)
+    out["autotuner"] = {"choice": f"{r['scorer']}:{r['tile_cols']}", "ms_per_step": r["ms"]}
+    torch.cuda.synchronize()
+    return out
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -608,6 +638,7 @@ def main():
     ap.add_argument("--ceiling-iters", type=int, default=12500,
                     help="rounds of the matrix-core ceiling loop (0 skips it)")
     ap.add_argument("--set-variant", type=int, default=1, help="0 skips the set-variant timing")
+    ap.add_argument("--scorers", type=int, default=1, help="0 skips the scorer comparison at the headline shape")
     ap.add_argument("--small-steps", type=int, default=10000,
                     help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
     ap.add_argument("--batch-instances", type=int, default=2000, help="0 skips the batched workload")
@@ -733,6 +764,9 @@ def main():
         Jl, sl = wl.couplings_matrix()
         out["precision_split_vs_fp64"]["sk_n8192_m1024"] = _precision_report(wl, Jl, sl)
         _log("large workload precision done")
+    if args.scorers:
+        other["scorers_at_headline_flip_sizes"] = _scorer_comparison(w, J, scale)
+        _log("scorer comparison done")
     if args.set_variant:
         other["root_law_table_biased_line"] = _table_law_workload()
         _log("root-law table workload done")

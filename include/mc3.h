@@ -117,11 +117,28 @@ typedef enum {
  *            general p (Sec. "Generalization to three configurations per Monte Carlo
  *            step") is arity 1, M = 2, weights (q/2, p, q/2), q = 1 - p; the line-graph
  *            addition process with probability p of adding at node 0's end is arity 1
- *            with weights C(M, v) p^v q^(M-v). */
+ *            with weights C(M, v) p^v q^(M-v).
+ *   BIASED:  a two-body proposal that depends on the state (Sec. "Problem statement"
+ *            allows any ergodic proposal): on the star (arity 0 or >= M) with
+ *            single-site edges (kmin = kmax = 1) and a uniform root, the site of an
+ *            edge is drawn from the state it is generated from with probability
+ *            proportional to exp(-bias dE_i), dE_i = 2 scale s_i h_i the energy change
+ *            of flipping site i (fixed point: q_i = floor(exp(a_i - max a) 2^52),
+ *            a_i = -(bias ((2 scale) (s_i h_i))), drawn with u53 of words 0, 1 of the
+ *            edge's stream).  r = 0: the hub is the current state; r >= 1: the hub is
+ *            the current state with site i_r ~ p(.|current) flipped; the other leaves
+ *            flip sites ~ p(.|hub).  Node weights exp(-beta E_v) rho_v with
+ *            rho_v = P_gen(T|c_v) / P_gen(T|hub) = p_{i_v}(c_v) / p_{i_v}(hub) (taken as
+ *            (q_{i_v}(c_v) W(hub)) / (q_{i_v}(hub) W(c_v))), rho_hub = 1; if the hub
+ *            cannot generate leaf r the chain stays.  Runs on the field-update scorer
+ *            (scorer DELTA or AUTO; GEMM is MC3_E_ARG), N <= 1024, M <= 512
+ *            (MC3_E_UNSUPPORTED beyond); rule MCMCMC.  These proposals depend on the
+ *            state, so they are drawn within each step, never ahead. */
 typedef enum {
     MC3_LAW_UNIFORM = 0,
     MC3_LAW_LINE = 1,
-    MC3_LAW_TABLE = 2
+    MC3_LAW_TABLE = 2,
+    MC3_LAW_BIASED = 3
 } mc3_graph_law;
 
 typedef enum {
@@ -184,6 +201,7 @@ typedef struct {
     double drift_tol;        /* a recompute whose |E_carried - E_recomputed| exceeds
                                 drift_tol (|E_recomputed| + 1) counts as a drift event;
                                 < 0 => 1e-9 */
+    double bias;             /* law BIASED: the proposal's bias (alpha); otherwise ignored */
 } mc3_config;
 
 /* One instance of a batch: its size, graph size, chains and flip-set range, with the
@@ -218,6 +236,7 @@ typedef struct {
     int32_t recompute_every; /* as in mc3_config */
     int32_t energy_update;   /* as in mc3_config */
     double drift_tol;        /* as in mc3_config */
+    double bias;             /* as in mc3_config */
 } mc3_batch_config;
 
 /* Per-step, per-chain record (40 bytes). */

@@ -35,7 +35,7 @@ _LIB = os.path.join(_HERE, "libmc3_oracle.so")
 
 TAG_INIT, TAG_ROOT, TAG_EDGE, TAG_SELECT = 1, 2, 3, 4
 RULE_MCMCMC, RULE_METROPOLIS = 0, 1
-LAW_UNIFORM, LAW_LINE, LAW_TABLE = 0, 1, 2
+LAW_UNIFORM, LAW_LINE, LAW_TABLE, LAW_BIASED = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -58,7 +58,8 @@ class Cfg(ctypes.Structure):
                 ("kmin", ctypes.c_int32), ("kmax", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("chain_base", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("scale", ctypes.c_double), ("arity", ctypes.c_int32),
-                ("law", ctypes.c_int32), ("pad2", ctypes.c_int32), ("table", ctypes.POINTER(ctypes.c_double))]
+                ("law", ctypes.c_int32), ("pad2", ctypes.c_int32), ("table", ctypes.POINTER(ctypes.c_double)),
+                ("alpha", ctypes.c_double)]
 
 
 REC_DTYPE = np.dtype([("r", np.int32), ("vstar", np.int32), ("e_cur", np.float64),
@@ -107,6 +108,15 @@ def lib():
         L.mc3o_select_mcmcmc.restype = i32
         L.mc3o_accept_metropolis.argtypes = [dbl, dbl, dbl, u64, P(dbl)]
         L.mc3o_accept_metropolis.restype = i32
+        L.mc3o_site_weights.argtypes = [i32, P(dbl), dbl, dbl, P(ctypes.c_int8), P(u64)]
+        L.mc3o_site_weights.restype = u64
+        L.mc3o_draw_site.argtypes = [i32, P(u64), u64, u64]
+        L.mc3o_draw_site.restype = i32
+        L.mc3o_select_ratio.argtypes = [i32, P(dbl), P(dbl), dbl, u64, P(dbl), P(dbl), P(u64)]
+        L.mc3o_select_ratio.restype = i32
+        L.mc3o_biased_step.argtypes = [i32, i32, P(dbl), dbl, dbl, dbl, u64, u32, u32, P(ctypes.c_int8),
+                                       P(ctypes.c_int8), P(dbl), P(dbl), P(i32), P(dbl), P(dbl)]
+        L.mc3o_biased_step.restype = i32
         L.mc3o_run.argtypes = [P(Cfg), P(dbl), P(ctypes.c_int8), P(dbl), u64, ctypes.c_int64,
                                P(dbl), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.mc3o_run.restype = i32
@@ -248,10 +258,53 @@ def accept_metropolis(e_cur: float, e_new: float, beta: float, u53_value: int):
     return bool(a), mg.value
 
 
+def site_weights(J: np.ndarray, scale: float, alpha: float, s: np.ndarray):
+    """Fixed-point site weights q [N] (uint64) and their total W of the biased
+    single-site proposal from state s."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    q = np.zeros(J.shape[0], dtype=np.uint64)
+    W = lib().mc3o_site_weights(J.shape[0], _ptr(J, ctypes.c_double), scale, alpha, _ptr(s, ctypes.c_int8),
+                                _ptr(q, ctypes.c_uint64))
+    return q, int(W)
+
+
+def draw_site(q: np.ndarray, W: int, u53_value: int) -> int:
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    return int(lib().mc3o_draw_site(len(q), _ptr(q, ctypes.c_uint64), W, u53_value))
+
+
+def select_ratio(E, rho, beta: float, u53_value: int):
+    """Node rule with generation-probability ratios rho; returns (vstar, e_bar, margin, W)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    eb, mg, ws = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64()
+    v = lib().mc3o_select_ratio(len(E), _ptr(E, ctypes.c_double), _ptr(rho, ctypes.c_double), beta, u53_value,
+                                ctypes.byref(eb), ctypes.byref(mg), ctypes.byref(ws))
+    return int(v), eb.value, mg.value, int(ws.value)
+
+
+def biased_step(J, scale, alpha, beta, seed, chain, step, s, M):
+    """One step of the biased single-site star from state s: dict(r, vstar, nodes
+    [(M+1), N], E, rho, e_bar, margin)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    N = J.shape[0]
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    nodes = np.zeros((M + 1, N), dtype=np.int8)
+    E = np.zeros(M + 1)
+    rho = np.zeros(M + 1)
+    r, eb, mg = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    v = lib().mc3o_biased_step(N, M, _ptr(J, ctypes.c_double), scale, alpha, beta, seed, chain, step,
+                               _ptr(s, ctypes.c_int8), _ptr(nodes, ctypes.c_int8), _ptr(E, ctypes.c_double),
+                               _ptr(rho, ctypes.c_double), ctypes.byref(r), ctypes.byref(eb), ctypes.byref(mg))
+    return {"r": r.value, "vstar": int(v), "nodes": nodes, "E": E, "rho": rho, "e_bar": eb.value,
+            "margin": mg.value}
+
+
 def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kmax: int, seed: int,
         betas, spins: Optional[np.ndarray] = None, step0: int = 0, rule: int = RULE_MCMCMC,
         chain_base: int = 0, want_node_e: bool = False, forced: Optional[np.ndarray] = None,
-        arity: Optional[int] = None, law: int = LAW_UNIFORM, table=None):
+        arity: Optional[int] = None, law: int = LAW_UNIFORM, table=None, alpha: float = 0.0):
     """Run len(betas) steps.  Returns dict(spins, e_cur, rec[, node_e]).
 
     Initial spins default to the INIT stream of each chain; energies are recomputed
@@ -274,7 +327,7 @@ def run(J: np.ndarray, scale: float, N: int, M: int, chains: int, kmin: int, kma
         tab = np.ascontiguousarray(table, dtype=np.float64)
         assert tab.shape == (M + 1,)
     cfg = Cfg(N, M, chains, kmin, kmax, rule, chain_base, 0, seed, scale, M if arity is None else arity, law, 0,
-              None if tab is None else _ptr(tab, ctypes.c_double))
+              None if tab is None else _ptr(tab, ctypes.c_double), alpha)
     rc = lib().mc3o_run(ctypes.byref(cfg), _ptr(J, ctypes.c_double), _ptr(spins, ctypes.c_int8),
                         _ptr(e_cur, ctypes.c_double), step0, nsteps, _ptr(betas, ctypes.c_double),
                         rec.ctypes.data, None if node_e is None else node_e.ctypes.data,

@@ -41,6 +41,11 @@
  *    Monte Carlo step" with a general p is the line of three nodes with root weights
  *    (q/2, p, q/2), q = 1 - p, and the line-graph addition process with a bias p
  *    toward node 0 is the line with weights C(M, v) p^v q^(M-v).
+ *  - A state-dependent two-body proposal (Sec. "Problem statement": any ergodic
+ *    proposal; the paper's motivation for graphs includes biased proposals): single
+ *    sites drawn with probability proportional to exp(-alpha dE_i) from the state the
+ *    edge is generated from, on the star with a uniform root; the node rule carries
+ *    P_gen(T|c_v) / P_gen(T|hub) (mc3o_biased_step).
  *  - Standard MCMC with the Metropolis rate min(1, ratio), Sec. "Problem statement",
  *    for the single-update baseline (rule METROPOLIS, M = 1).
  *  - Observables as node-weighted averages over the graph, Eq. eq_monte_carlo_graph.
@@ -416,6 +421,154 @@ int mc3o_accept_metropolis(double e_cur, double e_new, double beta, uint64_t u53
     return u < w;
 }
 
+/* ------------------------------------------------- state-dependent proposals */
+
+/* Site weights of the biased single-site proposal from state s (Sec. "Problem
+ * statement": the two-body proposal may be any ergodic law; here it depends on the
+ * state).  Site i is proposed with probability proportional to exp(-alpha dE_i), dE_i
+ * = E(s with i flipped) - E(s) = 2 scale s_i h_i, h_i = sum_j J_ij s_j (plain sum).  In
+ * fixed point: a_i = -(alpha ((2 scale) (s_i h_i))), amax = max a, q_i =
+ * floor(exp(a_i - amax) 2^52) (every q_i of the largest a_i is 2^52), written to q;
+ * returns W = sum q_i in site order. */
+uint64_t mc3o_site_weights(int N, const double* J, double scale, double alpha, const int8_t* s, uint64_t* q)
+{
+    double* a = (double*)malloc(sizeof(double) * (size_t)N);
+    double amax = -INFINITY;
+    for (int i = 0; i < N; ++i) {
+        double h = 0.0;
+        for (int j = 0; j < N; ++j) h += J[(size_t)i * N + j] * (double)s[j];
+        double x = (double)s[i] * h;
+        a[i] = -(alpha * ((2.0 * scale) * x));
+        if (a[i] > amax) amax = a[i];
+    }
+    uint64_t W = 0;
+    for (int i = 0; i < N; ++i) {
+        q[i] = (uint64_t)floor(mc3o_exp(a[i] - amax) * 0x1.0p52);
+        W += q[i];
+    }
+    free(a);
+    return W;
+}
+
+/* The site drawn from weights q (total W) by the 53-bit uniform u53:
+ * t = floor(u53 W / 2^53), site = min { i : q_0 + .. + q_i > t }. */
+int mc3o_draw_site(int N, const uint64_t* q, uint64_t W, uint64_t u53)
+{
+    unsigned __int128 prod = (unsigned __int128)u53 * (unsigned __int128)W;
+    uint64_t t = (uint64_t)(prod >> 53);
+    uint64_t Q = 0;
+    for (int i = 0; i < N; ++i) {
+        Q += q[i];
+        if (Q > t) return i;
+    }
+    return N - 1;
+}
+
+/* Node rule with generation-probability ratios (App. "Markov chain of graphs of
+ * configurations", Eq. eq_det_balance_graph_solution): P_node(v) proportional to
+ * exp(-beta E_v) rho_v, rho_v = P_gen(T|c_v) / P_gen(T|c_0).  Fixed point:
+ * y_v = exp(-(beta (E_v - Emin))) rho_v, w_v = y_v / max y, q_v = floor(w_v 2^52),
+ * Q_v inclusive sums in node order, t = floor(u53 W / 2^53), v* = min{v : Q_v > t};
+ * margin and node-weighted energy as mc3o_select_mcmcmc. */
+int mc3o_select_ratio(int nodes, const double* E, const double* rho, double beta, uint64_t u53,
+                      double* e_bar, double* margin, uint64_t* wsum)
+{
+    double emin = E[0];
+    for (int v = 1; v < nodes; ++v) if (E[v] < emin) emin = E[v];
+    double* w = (double*)malloc(sizeof(double) * (size_t)nodes);
+    double ymax = 0.0;
+    for (int v = 0; v < nodes; ++v) {
+        w[v] = mc3o_exp(-(beta * (E[v] - emin))) * rho[v];
+        if (w[v] > ymax) ymax = w[v];
+    }
+    for (int v = 0; v < nodes; ++v) w[v] = w[v] / ymax;
+    uint64_t Wq = 0;
+    uint64_t* Q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nodes);
+    for (int v = 0; v < nodes; ++v) {
+        Wq += (uint64_t)floor(w[v] * 0x1.0p52);
+        Q[v] = Wq;
+    }
+    unsigned __int128 prod = (unsigned __int128)u53 * (unsigned __int128)Wq;
+    uint64_t t = (uint64_t)(prod >> 53);
+    int vs = 0;
+    while (Q[vs] <= t) ++vs;
+    uint64_t lo = vs ? Q[vs - 1] : 0u;
+    uint64_t d1 = t - lo, d2 = Q[vs] - t;
+    *margin = (double)(d1 < d2 ? d1 : d2) / (double)Wq;
+    double num = 0.0, den = 0.0;
+    for (int v = 0; v < nodes; ++v) { num += w[v] * E[v]; den += w[v]; }
+    *e_bar = num / den;
+    *wsum = Wq;
+    free(w);
+    free(Q);
+    return vs;
+}
+
+/* One step of one chain with the biased single-site proposal on the star (uniform root
+ * r ~ U{0..M}, App. "General graph populating process"): r = 0: the hub is the current
+ * state s; r >= 1: s is leaf r and the hub is s with site i_r flipped, i_r drawn from
+ * the weights of s; every other leaf e is the hub with site i_e flipped, i_e drawn from
+ * the weights of the hub.  The site of edge e is drawn with u53 of words 0, 1 of the
+ * edge stream (tag 3, edge e).  With a uniform root, P_gen(T|c_v) relative to the hub
+ * is rho_v = p_{i_v}(c_v) / p_{i_v}(hub) for leaf v (c_v generates the hub through
+ * site i_v; every other edge is generated from the hub either way), taken in fixed
+ * point as ((q_{i_v}(c_v) W(hub)) / (q_{i_v}(hub) W(c_v))), rho_hub = 1.  When the hub
+ * cannot generate leaf r (q_{i_r}(hub) = 0) only node r has a nonzero generation
+ * probability: the chain stays (v* = r, margin infinite, e_bar = E_r).
+ * nodes: [(M+1) x N] out; E: [M+1] out (plain pair sums); rho [M+1] out. */
+int mc3o_biased_step(int N, int M, const double* J, double scale, double alpha, double beta, uint64_t seed,
+                     uint32_t chain, uint32_t step, const int8_t* s, int8_t* nodes, double* E, double* rho,
+                     int* r_out, double* e_bar, double* margin)
+{
+    uint64_t* qs = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
+    uint64_t* qh = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
+    uint64_t* qv = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
+    int* site = (int*)malloc(sizeof(int) * (size_t)(M + 1));
+    const int r = mc3o_root(seed, chain, step, M);
+    int8_t* hub = nodes;
+    memcpy(hub, s, (size_t)N);
+    if (r >= 1) {
+        uint64_t Ws = mc3o_site_weights(N, J, scale, alpha, s, qs);
+        uint64_t u = mc3o_u53(mc3o_word(seed, TAG_EDGE, chain, step, (uint32_t)r, 0u),
+                              mc3o_word(seed, TAG_EDGE, chain, step, (uint32_t)r, 1u));
+        site[r] = mc3o_draw_site(N, qs, Ws, u);
+        hub[site[r]] = (int8_t)-hub[site[r]];
+    }
+    uint64_t Wh = mc3o_site_weights(N, J, scale, alpha, hub, qh);
+    for (int e = 1; e <= M; ++e) {
+        if (e != r) {
+            uint64_t u = mc3o_u53(mc3o_word(seed, TAG_EDGE, chain, step, (uint32_t)e, 0u),
+                                  mc3o_word(seed, TAG_EDGE, chain, step, (uint32_t)e, 1u));
+            site[e] = mc3o_draw_site(N, qh, Wh, u);
+        }
+        int8_t* leaf = nodes + (size_t)e * N;
+        memcpy(leaf, hub, (size_t)N);
+        leaf[site[e]] = (int8_t)-leaf[site[e]];
+    }
+    for (int v = 0; v <= M; ++v) E[v] = mc3o_energy(N, J, scale, nodes + (size_t)v * N);
+    rho[0] = 1.0;
+    for (int v = 1; v <= M; ++v) {
+        uint64_t Wv = mc3o_site_weights(N, J, scale, alpha, nodes + (size_t)v * N, qv);
+        double num = (double)qv[site[v]] * (double)Wh;
+        double den = (double)qh[site[v]] * (double)Wv;
+        rho[v] = num / den;   /* den = 0 only at v = r: handled below */
+    }
+    uint32_t w0 = mc3o_word(seed, TAG_SELECT, chain, step, 0u, 0u);
+    uint32_t w1 = mc3o_word(seed, TAG_SELECT, chain, step, 0u, 1u);
+    int vs;
+    uint64_t wsum;
+    if (r >= 1 && qh[site[r]] == 0) {
+        vs = r;
+        *margin = INFINITY;
+        *e_bar = E[r];
+    } else {
+        vs = mc3o_select_ratio(M + 1, E, rho, beta, mc3o_u53(w0, w1), e_bar, margin, &wsum);
+    }
+    *r_out = r;
+    free(qs); free(qh); free(qv); free(site);
+    return vs;
+}
+
 /* ------------------------------------------------------------------------ run */
 
 typedef struct {
@@ -426,9 +579,11 @@ typedef struct {
     uint64_t seed;
     double scale;          /* energy scale: E = -scale * sum_{i<j} J_ij s_i s_j */
     int32_t arity;         /* tree arity (parent of v is (v-1)/arity); 0 = M (the star) */
-    int32_t law;           /* 0 = uniform root, 1 = line-graph addition process (arity 1), 2 = table */
+    int32_t law;           /* 0 = uniform root, 1 = line-graph addition process (arity 1), 2 = table,
+                              3 = star with the state-dependent single-site proposal (mc3o_biased_step) */
     int32_t pad2;
     const double* table;   /* law 2: root weights g_0..g_M */
+    double alpha;          /* law 3: bias of the state-dependent single-site proposal */
 } mc3o_cfg;
 
 /* Run nsteps steps starting at global step step0 for every chain.
@@ -449,7 +604,8 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
     if (N < 2 || M < 1 || cfg->chains < 1 || cfg->kmin < 1 || cfg->kmax < cfg->kmin || cfg->kmax > N) return -1;
     if (cfg->rule == 1 && M != 1) return -1;
     const int arity = cfg->arity > 0 ? cfg->arity : M;
-    if (arity > M || cfg->law < 0 || cfg->law > 2 || (cfg->law == 1 && arity != 1)) return -1;
+    if (arity > M || cfg->law < 0 || cfg->law > 3 || (cfg->law == 1 && arity != 1)) return -1;
+    if (cfg->law == 3 && (arity != M || cfg->kmin != 1 || cfg->kmax != 1 || cfg->rule != 0)) return -1;
     if (cfg->law == 2 && !cfg->table) return -1;
     double* log_prior = NULL;
     uint64_t* Qcum = NULL;
@@ -469,11 +625,27 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
     uint8_t* flips = (uint8_t*)malloc((size_t)(M + 1) * N);
     int8_t* nodes = (int8_t*)malloc((size_t)(M + 1) * N);
     double* E = (double*)malloc(sizeof(double) * (size_t)(M + 1));
+    double* rho_buf = (double*)malloc(sizeof(double) * (size_t)(M + 1));   /* law 3: rho per node */
     for (int64_t ts = 0; ts < nsteps; ++ts) {
         uint32_t step = (uint32_t)(step0 + (uint64_t)ts);
         for (int c = 0; c < cfg->chains; ++c) {
             uint32_t gc = cfg->chain_base + (uint32_t)c;
             int8_t* s = spins + (size_t)c * N;
+            if (cfg->law == 3) {
+                int r3, vs3;
+                double eb3, mg3;
+                vs3 = mc3o_biased_step(N, M, J, cfg->scale, cfg->alpha, beta[ts], cfg->seed, gc, step, s, nodes, E,
+                                       rho_buf, &r3, &eb3, &mg3);
+                if (forced && forced[(size_t)ts * cfg->chains + c] >= 0) vs3 = forced[(size_t)ts * cfg->chains + c];
+                if (node_e) memcpy(node_e + ((size_t)ts * cfg->chains + c) * (M + 1), E, sizeof(double) * (size_t)(M + 1));
+                memcpy(s, nodes + (size_t)vs3 * N, (size_t)N);
+                e_cur[c] = E[vs3];
+                if (rec) {
+                    mc3o_rec* o = rec + (size_t)ts * cfg->chains + c;
+                    o->r = r3; o->vstar = vs3; o->e_cur = E[vs3]; o->e_bar = eb3; o->margin = mg3; o->wsum = 0;
+                }
+                continue;
+            }
             int r = 0;
             if (cfg->rule != 1) {
                 if (cfg->law == 1)
@@ -513,7 +685,7 @@ int mc3o_run(const mc3o_cfg* cfg, const double* J, int8_t* spins, double* e_cur,
             }
         }
     }
-    free(flips); free(nodes); free(E); free(log_prior); free(Qcum);
+    free(flips); free(nodes); free(E); free(rho_buf); free(log_prior); free(Qcum);
     return 0;
 }
 

@@ -1,4 +1,4 @@
-"""Tile-width autotuner for the split-BF16 scoring launch.
+"""Autotuner: the split-BF16 scoring launch's tile width, and the scorer of a step.
 
 A scoring work unit is a row-block pair of J times a tile of 128, 256 or 512
 candidate columns, run by 2, 4 or 8 waves of 64 columns that share the pair's J
@@ -11,6 +11,13 @@ in a JSON file keyed by the device and the configuration.
 
 The choice changes time only, never a result: every column's partial sums run over
 the same k order at every width.
+
+`tune_scorer` times whole steps (mc3_step_n: proposal, scoring, selection, move) of
+the caller's configuration with every scorer the library accepts for it -- the pair
+sums on the matrix cores at each tile width, and the FP64 field update (energies as
+differences, where its limits hold) -- and returns the fastest.  This is the measured
+counterpart of the library's static MC3_SCORER_AUTO rule.  The scorers' results agree
+within their precisions (bit for bit on +-1 couplings), not bit for bit in general.
 """
 import hashlib
 import json
@@ -97,3 +104,66 @@ def tune_tile_cols(make_cfg: Callable[[int], object], init: Callable[[object], N
     table[key] = {"tile_cols": best, "ms": {str(w): v for w, v in ms.items()}}
     _store(cache_path, table)
     return {"tile_cols": best, "ms": ms, "key": key, "cached": False}
+
+
+# (scorer, tile_cols) options of tune_scorer; tile widths apply to the split pair sums
+SCORER_OPTIONS = tuple(("gemm", w) for w in WIDTHS) + (("delta", 0),)
+
+
+def time_steps(make_cfg: Callable[[str, int], object], init: Callable[[object], None], scorer: str, width: int,
+               steps: int, warmup: int, beta: float) -> float:
+    """Mean wall time (ms) of one step of mc3_step_n for make_cfg(scorer, width) on the
+    current GPU: `warmup` untimed steps, then `steps` steps between HIP events on the
+    context's stream."""
+    import torch
+    ctx = native.Context(make_cfg(scorer, width))
+    try:
+        init(ctx)
+        ctx.step_n(0, warmup, beta, beta, 1)
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        ctx.step_n(warmup, steps, beta, beta, 1)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+    finally:
+        ctx.close()
+
+
+def tune_scorer(make_cfg: Callable[[str, int], object], init: Callable[[object], None], beta: float = 1.0,
+                steps: int = 20, warmup: int = 3, options: Sequence = SCORER_OPTIONS,
+                cache_path: Optional[str] = None, device: Optional[str] = None, timer=time_steps,
+                retune: bool = False) -> Dict:
+    """The fastest (scorer, tile width) for make_cfg (a function of (scorer, tile_cols)
+    returning a Config or BatchConfig), over the options the library accepts for it
+    (tile widths only for split-BF16 pair sums).
+
+    Returns {"scorer", "tile_cols", "ms" (per "scorer:width"), "key", "cached"}."""
+    if device is None:
+        import torch
+        device = torch.cuda.get_device_name(0)
+    base = make_cfg("gemm", 0)
+    key = "scorer|" + config_key(base, device) + f"|beta={beta!r}"
+    table = _load(cache_path)
+    if not retune and key in table:
+        hit = table[key]
+        return {"scorer": hit["scorer"], "tile_cols": int(hit["tile_cols"]), "ms": dict(hit["ms"]), "key": key,
+                "cached": True}
+    ms = {}
+    for scorer, width in options:
+        if width and base.precision != native.MC3_SPLIT_BF16:
+            continue
+        try:
+            native.workspace_size(make_cfg(scorer, width))
+        except native.MC3Error:
+            continue   # outside this scorer's limits
+        ms[f"{scorer}:{width}"] = float(timer(make_cfg, init, scorer, width, steps, warmup, beta))
+    if not ms:
+        raise ValueError("no scorer accepts this configuration")
+    best = min(ms, key=lambda k: (ms[k], k))
+    scorer, width = best.split(":")
+    table[key] = {"scorer": scorer, "tile_cols": int(width), "ms": ms}
+    _store(cache_path, table)
+    return {"scorer": scorer, "tile_cols": int(width), "ms": ms, "key": key, "cached": False}

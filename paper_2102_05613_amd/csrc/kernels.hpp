@@ -6,6 +6,7 @@
 #include "score_f64.hpp"
 #include "select.hpp"
 #include "delta.hpp"
+#include "biased.hpp"
 #include "sets.hpp"
 #include "couplings.hpp"
 #include "recompute.hpp"

@@ -31,6 +31,7 @@ constexpr int kTileF64 = 128;    // columns per FP64-scoring unit
 constexpr int kClasses = 3;      // split-scoring tile widths: 128, 256, 512 columns (2, 4, 8 waves)
 constexpr int kMaxAhead = 16;    // steps of flip sets drawn per proposal launch, at most
 constexpr size_t kFlipBudget = size_t(512) << 20;  // bytes of flip-set ring, about
+constexpr int kMoveSlices = 64;  // most blocks per chain of the exact energy update
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -94,6 +95,8 @@ struct InstH {
 struct Plan {
   std::vector<InstH> inst;
   bool delta = false;   // field-update scorer (else the matrix-core pair sum)
+  bool delta_star = false;   // ... the kernel for stars with flip sets of any size
+  int Kmax = 0;
   size_t delta_lds = 0;
   int total_chains = 0, total_cols = 0, Wmax = 0, Wn_max = 0, Mmax = 0;
   int prop_T = 256, prop_stride = 1, prop_rows = 1;
@@ -107,6 +110,7 @@ struct Plan {
          rec_units_off = 0;
   size_t sched = 0;   // [instances][3] per-instance beta schedules (beta0, beta1, total)
   size_t drift_ev = 0;   // [chains] drift events of the periodic recompute
+  size_t moveD = 0, mflag = 0, xpart = 0;   // the exact energy update's per-chain move buffers
   size_t clock = 0;   // the step clock of replayed graphs (one uint32)
   size_t e_cur = 0, e_bar = 0, roots = 0, candT = 0, ring = 0, means = 0, moves = 0, near = 0, minm = 0, drift = 0,
          u_cur = 0, vals = 0, total = 0;
@@ -149,7 +153,13 @@ const char* validate_batch(const mc3_batch_config* c) {
   if (c->scorer != MC3_SCORER_GEMM && c->scorer != MC3_SCORER_DELTA && c->scorer != MC3_SCORER_AUTO)
     return "unknown scorer";
   if (c->arity < 0) return "arity must be >= 0";
-  if (c->law != MC3_LAW_UNIFORM && c->law != MC3_LAW_LINE && c->law != MC3_LAW_TABLE) return "unknown graph law";
+  if (c->law != MC3_LAW_UNIFORM && c->law != MC3_LAW_LINE && c->law != MC3_LAW_TABLE && c->law != MC3_LAW_BIASED)
+    return "unknown graph law";
+  if (c->law == MC3_LAW_BIASED) {
+    if (c->rule != MC3_RULE_MCMCMC) return "the biased proposal needs rule MCMCMC";
+    if (c->scorer == MC3_SCORER_GEMM) return "the biased proposal runs on the field-update scorer";
+    if (!std::isfinite(c->bias)) return "bias must be finite";
+  }
   if (c->law == MC3_LAW_TABLE && !c->law_table) return "law TABLE needs law_table";
   if (c->trace_steps < 0) return "trace_steps must be >= 0";
   if (c->mean_steps < 0) return "mean_steps must be >= 0";
@@ -166,6 +176,8 @@ const char* validate_batch(const mc3_batch_config* c) {
     const int M = c->instances[i].M;
     const int a = (c->arity == 0 || c->arity > M) ? M : c->arity;
     if (c->law == MC3_LAW_LINE && a != 1) return "the line law needs arity 1";
+    if (c->law == MC3_LAW_BIASED && (a != M || c->instances[i].kmin != 1 || c->instances[i].kmax != 1))
+      return "the biased proposal needs the star and single-site edges (kmin = kmax = 1)";
     if (c->law == MC3_LAW_TABLE && !root_table(c->law_table + table_at, M, nullptr))
       return "law_table: weights must be finite and >= 0 with a positive fixed-point total per instance";
     table_at += M + 1;
@@ -206,11 +218,42 @@ bool delta_fits(const mc3_batch_config& c, size_t* lds, int path_limit) {
   return *lds <= 65536;
 }
 
-// Resolve the scorer: 1 = field update, 0 = pair sum, -1 = field update requested but
-// outside its limits.
+// The field-update scorer for stars with flip sets of any size (k_step_delta_star):
+// whether its LDS fits, and how much.
+bool delta_star_fits(const mc3_batch_config& c, size_t* lds) {
+  int Nmax = 0, Mmax = 0, Wmax = 0, Kmax = 0;
+  for (int i = 0; i < c.n_instances; ++i) {
+    const mc3_instance_desc& d = c.instances[i];
+    if (resolved_arity(c, d.M) != d.M) return false;
+    Nmax = std::max(Nmax, d.N);
+    Mmax = std::max(Mmax, d.M);
+    Kmax = std::max(Kmax, d.kmax);
+    Wmax = std::max(Wmax, (d.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock / 32);
+  }
+  *lds = mc3::delta_star_lds_bytes(Nmax, Mmax, Wmax, Kmax);
+  return *lds <= 65536;
+}
+
+// Resolve the scorer: 1 = field update, 2 = field update for stars with flip sets of any
+// size, 0 = pair sum, -1 = field update requested but outside both kernels' limits.
 int resolve_delta(const mc3_batch_config& c, size_t* lds) {
+  if (c.law == MC3_LAW_BIASED) {   // its own persistent kernel (field update, state-dependent draws)
+    int Nmax = 0, Mmax = 0, Wmax = 0;
+    for (int i = 0; i < c.n_instances; ++i) {
+      const mc3_instance_desc& d = c.instances[i];
+      if (d.N > mc3::kBiasedMaxN || d.M > mc3::kBiasedMaxM) return -1;
+      Nmax = std::max(Nmax, d.N);
+      Mmax = std::max(Mmax, d.M);
+      Wmax = std::max(Wmax, (d.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock / 32);
+    }
+    *lds = mc3::biased_lds_bytes(Nmax, Mmax, Wmax);
+    return *lds <= 65536 ? 1 : -1;
+  }
   if (c.scorer == MC3_SCORER_GEMM) return 0;
-  if (c.scorer == MC3_SCORER_DELTA) return delta_fits(c, lds, 2 * mc3::kDeltaMaxK) ? 1 : -1;
+  if (c.scorer == MC3_SCORER_DELTA) {
+    if (delta_fits(c, lds, 2 * mc3::kDeltaMaxK)) return 1;
+    return delta_star_fits(c, lds) ? 2 : -1;
+  }
   return delta_fits(c, lds, 16) ? 1 : 0;
 }
 
@@ -229,7 +272,10 @@ int unit_cost(int NB, int p) { return p == NB - 1 - p ? NB - p : NB + 1; }
 Plan make_plan(const mc3_batch_config& cfg) {
   Plan pl;
   const int n = cfg.n_instances;
-  pl.delta = resolve_delta(cfg, &pl.delta_lds) == 1;
+  const int scorer = resolve_delta(cfg, &pl.delta_lds);
+  pl.delta = scorer >= 1;
+  pl.delta_star = scorer == 2;
+  for (int i = 0; i < n; ++i) pl.Kmax = std::max(pl.Kmax, cfg.instances[i].kmax);
   pl.inst.resize(n);
   for (int i = 0; i < n; ++i) {
     InstH& h = pl.inst[i];
@@ -366,6 +412,11 @@ Plan make_plan(const mc3_batch_config& cfg) {
   pl.drift = take(C * 8);
   pl.drift_ev = take(C * 8);
   pl.u_cur = take(C * 8);
+  if (!pl.delta) {
+    pl.moveD = take(C * 2 * (size_t)pl.Wmax * 4);
+    pl.mflag = take(C * 4);
+    pl.xpart = take(C * (size_t)kMoveSlices * 8);
+  }
   pl.ring = take((size_t)cfg.trace_steps * C * sizeof(mc3::Record));
   pl.means = take((size_t)cfg.mean_steps * 3 * sizeof(double));
   if (pl.delta) pl.vals = take((size_t)cfg.mean_steps * C * 2 * sizeof(double));
@@ -416,6 +467,7 @@ mc3_batch_config single_to_batch(const mc3_config* c, mc3_instance_desc* one) {
   b.recompute_every = c->recompute_every;
   b.energy_update = c->energy_update;
   b.drift_tol = c->drift_tol;
+  b.bias = c->bias;
   return b;
 }
 
@@ -430,6 +482,11 @@ struct mc3_ctx {
   int device = 0;
   bool have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
   bool noalloc = false;      // the workspace is the device's fixed array (mc3_create_noalloc)
+  // the exact energy update's second stream (step runs): the bookkeeping after each
+  // selection overlaps the next step's scoring
+  hipStream_t side = nullptr;
+  hipEvent_t ev_sel = nullptr, ev_post = nullptr;
+  bool side_pending = false, defer_moves = false;
   uint32_t proposal_step = 0;
   double tol = 0.0;          // fixed part of the near-tie threshold (plus beta * tie_coef per instance)
   double drift_tol = 1e-9;   // relative drift counted as an event by the periodic recompute
@@ -598,6 +655,32 @@ mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, 
       const int64_t t0 = (int64_t)step0 + done;
       chunk = (int)std::min<int64_t>(chunk, K - t0 % K);
     }
+    if (c->cfg.law == MC3_LAW_BIASED) {
+      hipLaunchKernelGGL(mc3::k_step_biased, dim3(pl.total_chains), dim3(256), pl.delta_lds, c->stream, c->ws,
+                         c->insts(), c->chain_inst(), pl.total_chains, Nmax, pl.Mmax, pl.Wmax,
+                         c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->at<mc3::Record>(pl.ring),
+                         c->at<unsigned long long>(pl.moves), c->at<unsigned long long>(pl.near),
+                         c->at<double>(pl.minm), c->at<double>(pl.e_bar), c->at<double>(pl.vals), c->cfg.mean_steps,
+                         c->cfg.bias, beta0, beta1, (long long)total, c->tol, c->key(), c->cfg.chain_base,
+                         step0 + (uint32_t)done, chunk, c->cfg.trace_steps, sched);
+      MC3_TRY(check_launch(c, "biased step kernel"));
+      done += chunk;
+      MC3_TRY(maybe_recompute(c, step0 + (uint32_t)(done - 1)));
+      continue;
+    }
+    if (pl.delta_star) {
+      hipLaunchKernelGGL(mc3::k_step_delta_star, dim3(pl.total_chains), dim3(256), pl.delta_lds, c->stream, c->ws,
+                         c->insts(), c->chain_inst(), pl.total_chains, Nmax, pl.Mmax, pl.Wmax, pl.Kmax,
+                         c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->at<mc3::Record>(pl.ring),
+                         c->at<unsigned long long>(pl.moves), c->at<unsigned long long>(pl.near),
+                         c->at<double>(pl.minm), c->at<double>(pl.e_bar), c->at<double>(pl.vals), c->cfg.mean_steps,
+                         c->metropolis() ? 1 : 0, beta0, beta1, (long long)total, c->tol, c->key(),
+                         c->cfg.chain_base, step0 + (uint32_t)done, chunk, c->cfg.trace_steps, sched);
+      MC3_TRY(check_launch(c, "field-update star kernel"));
+      done += chunk;
+      MC3_TRY(maybe_recompute(c, step0 + (uint32_t)(done - 1)));
+      continue;
+    }
     hipLaunchKernelGGL(mc3::k_step_delta, dim3(pl.total_chains), dim3(256), pl.delta_lds, c->stream, c->ws,
                        c->insts(), c->chain_inst(), pl.total_chains, Nmax, pl.Mmax, pl.Wmax,
                        c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->at<mc3::Record>(pl.ring),
@@ -723,12 +806,16 @@ struct ClockArg {
 // Selection of global chains [g0, g0 + n) at `step`; with next_base, also the base
 // words of step+1 (whose flip sets and roots must already be proposed).  Ring slots are
 // those of `step` itself; with a clock the kernel takes step - base.
+mc3_status launch_moves(mc3_ctx* c, uint32_t step, int g0, int n, const ClockArg& ck);
+
 mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n,
                          const ClockArg& ck = ClockArg{}, const double* sched = nullptr) {
   const Plan& pl = c->pl;
   int Nmax = 0;
   for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
-  const size_t lds = std::max((size_t)(pl.Mmax + 1) * 16, (size_t)8 * pl.Wmax + (size_t)2 * Nmax);
+  const size_t lds = (size_t)(pl.Mmax + 1) * 16;
+  const bool exact = c->cfg.energy_update == MC3_ENERGY_EXACT;
+  (void)Nmax;
   hipLaunchKernelGGL(mc3::k_select, dim3(n), dim3(256), lds, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
                      pl.total_chains, c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->roots(step),
                      c->roots(step + 1u),
@@ -736,9 +823,30 @@ mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base,
                      c->at<unsigned long long>(pl.near), c->at<double>(pl.minm), c->at<double>(pl.e_bar),
                      c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base,
                      ck.clk ? step - ck.base : step, c->slot(step), c->slot(step + 1u), c->cfg.trace_steps,
-                     next_base ? 1 : 0, ck.clk, ck.beta0, ck.beta1, (long long)ck.total, sched,
-                     c->cfg.energy_update == MC3_ENERGY_EXACT ? 1 : 0);
-  return check_launch(c, "select kernel");
+                     next_base ? 1 : 0, ck.clk, ck.beta0, ck.beta1, (long long)ck.total, sched, exact ? 1 : 0,
+                     c->at<uint32_t>(pl.moveD), pl.Wmax, c->at<int32_t>(pl.mflag));
+  MC3_TRY(check_launch(c, "select kernel"));
+  if (!exact || c->defer_moves) return MC3_OK;
+  return launch_moves(c, step, g0, n, ck);
+}
+
+// The exact energy update of the chains [g0, g0 + n) that moved at `step`: their
+// difference from the rows of the flipped sites, S blocks per chain (about 2048 blocks
+// in all), then the sums into the carried energies and the step's records.
+mc3_status launch_moves(mc3_ctx* c, uint32_t step, int g0, int n, const ClockArg& ck) {
+  const Plan& pl = c->pl;
+  int Nmax = 0;
+  for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
+  const int S = std::max(1, std::min(kMoveSlices, 2048 / std::max(1, n)));
+  hipLaunchKernelGGL(mc3::k_move_delta, dim3(n, S), dim3(256), (size_t)8 * pl.Wmax + (size_t)2 * Nmax, c->stream,
+                     c->ws, c->insts(), c->chain_inst(), g0, c->at<const uint32_t>(pl.moveD), pl.Wmax,
+                     c->at<const int32_t>(pl.mflag), c->at<double>(pl.xpart), S);
+  MC3_TRY(check_launch(c, "move kernel"));
+  hipLaunchKernelGGL(mc3::k_move_finish, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->insts(), c->chain_inst(),
+                     g0, n, pl.total_chains, c->at<const int32_t>(pl.mflag), c->at<const double>(pl.xpart), S,
+                     c->at<double>(pl.u_cur), c->at<double>(pl.e_cur), c->at<mc3::Record>(pl.ring),
+                     c->cfg.trace_steps, ck.clk ? step - ck.base : step, ck.clk);
+  return check_launch(c, "move finish kernel");
 }
 
 mc3_status launch_means(mc3_ctx* c, uint32_t step, const ClockArg& ck = ClockArg{}) {
@@ -749,6 +857,13 @@ mc3_status launch_means(mc3_ctx* c, uint32_t step, const ClockArg& ck = ClockArg
                      step % (uint32_t)c->cfg.mean_steps, ck.clk ? step - ck.base : step, ck.clk,
                      (uint32_t)c->cfg.mean_steps);
   return check_launch(c, "means kernel");
+}
+
+// The context's stream waits for what the second stream still has in flight.
+mc3_status join_side(mc3_ctx* c) {
+  if (!c->side_pending) return MC3_OK;
+  c->side_pending = false;
+  return hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_post, 0), "side join");
 }
 
 mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
@@ -765,6 +880,46 @@ mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = fa
                      const double* sched = nullptr) {
   MC3_TRY(launch_select(c, step, beta, next_base, 0, c->pl.total_chains, ClockArg{}, sched));
   return after_select(c, step, next_base);
+}
+
+// The selection of step t inside a run of steps with the exact energy update: the
+// selection on the context's stream; the moves' energy update, the means and the
+// periodic recompute on a second stream of the context's own (default priority), after
+// the selection and overlapping the next step's scoring, which reads none of what they
+// write; the next selection, which reads the carried energies, waits for them.
+mc3_status do_select_overlapped(mc3_ctx* c, uint32_t t, double beta, bool next_base, const double* sched) {
+  if (!c->side) {
+    MC3_TRY(hip_ok(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream"));
+    MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming), "side event"));
+    MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->ev_post, hipEventDisableTiming), "side event"));
+  }
+  MC3_TRY(join_side(c));
+  c->defer_moves = true;
+  const mc3_status st = launch_select(c, t, beta, next_base, 0, c->pl.total_chains, ClockArg{}, sched);
+  c->defer_moves = false;
+  MC3_TRY(st);
+  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel, c->stream), "side event"));
+  MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->side, c->ev_sel, 0), "side wait"));
+  hipStream_t main = c->stream;
+  c->stream = c->side;
+  mc3_status s2 = launch_moves(c, t, 0, c->pl.total_chains, ClockArg{});
+  if (s2 == MC3_OK) s2 = launch_means(c, t);
+  if (s2 == MC3_OK) s2 = maybe_recompute(c, t);
+  c->stream = main;
+  MC3_TRY(s2);
+  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_post, c->side), "side event"));
+  c->side_pending = true;
+  c->have_proposal = next_base;
+  c->have_scores = false;
+  if (next_base) c->proposal_step = t + 1u;
+  c->steps_done += 1;
+  return MC3_OK;
+}
+
+// Step-loop selection: overlapped with the exact energy update, else as do_select.
+mc3_status select_in_run(mc3_ctx* c, uint32_t t, double beta, bool next_base, const double* sched) {
+  if (c->cfg.energy_update == MC3_ENERGY_EXACT) return do_select_overlapped(c, t, beta, next_base, sched);
+  return do_select(c, t, beta, next_base, sched);
 }
 
 double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
@@ -790,8 +945,9 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
     const bool last = i + 1 == n;
     MC3_TRY(do_score(c, nullptr));
     if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
-    MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last, sched));
+    MC3_TRY(select_in_run(c, t, beta_at(t, beta0, beta1, total), !last, sched));
   }
+  MC3_TRY(join_side(c));
   c->have_proposal = false;
   return MC3_OK;
 }
@@ -804,9 +960,9 @@ mc3_status step_groups(mc3_ctx* c, uint32_t t0, int64_t n, double beta0, double 
     const bool last = i + 1 == n;
     MC3_TRY(do_score(c, nullptr));
     if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
-    MC3_TRY(do_select(c, t, beta_at(t, beta0, beta1, total), !last));
+    MC3_TRY(select_in_run(c, t, beta_at(t, beta0, beta1, total), !last, nullptr));
   }
-  return MC3_OK;
+  return join_side(c);
 }
 
 int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
@@ -1176,6 +1332,12 @@ mc3_status mc3_destroy(mc3_ctx* ctx) {
   for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_sel) (void)hipEventDestroy(ctx->ev_sel);
+  if (ctx->ev_post) (void)hipEventDestroy(ctx->ev_post);
   delete ctx;
   return MC3_OK;
 }

@@ -114,6 +114,71 @@ __device__ __forceinline__ RuleOut apply_rule(const double* En, unsigned long lo
   return o;
 }
 
+// The node rule with generation-probability ratios rho_v = P_gen(T|c_v) / P_gen(T|c_0)
+// (App. "Markov chain of graphs of configurations", Eq. eq_det_balance_graph_solution),
+// computed by one whole wave: y_v = exp(-(beta (E_v - Emin))) rho_v, w_v = y_v / max y,
+// then the fixed-point draw of apply_rule; the node-weighted energy with the weights w.
+__device__ __forceinline__ RuleOut apply_rule_ratio(const double* En, const double* rho, unsigned long long* Qn, int M,
+                                                    int r, double beta, uint64_t u53, int lane) {
+  RuleOut o;
+  const int nodes = M + 1;
+  const int K = (nodes + 63) >> 6;
+  const int v0 = lane * K, v1 = min(v0 + K, nodes);
+  double emin = __longlong_as_double(0x7FF0000000000000ll);
+  for (int v = v0; v < v1; ++v) emin = En[v] < emin ? En[v] : emin;
+  emin = wave_min(emin);
+  double ymax = 0.0;
+  for (int v = v0; v < v1; ++v) {
+    const double y = exp_weight(-(beta * (En[v] - emin))) * rho[v];
+    ymax = y > ymax ? y : ymax;
+  }
+  ymax = wave_max(ymax);
+  unsigned long long wq = 0ull;
+  double num = 0.0, den = 0.0;
+  for (int v = v0; v < v1; ++v) {
+    const double E = En[v];
+    const double w = (exp_weight(-(beta * (E - emin))) * rho[v]) / ymax;
+    const unsigned long long q = (unsigned long long)(w * 0x1.0p52);
+    Qn[v] = q;
+    wq += q;
+    num += w * E;
+    den += w;
+  }
+  const unsigned long long S = wave_scan_u64(wq, lane);
+  const unsigned long long Wq = readlane_u64(S, 63);
+  num = wave_sum(num);
+  den = wave_sum(den);
+  o.ebar = num / den;
+  const unsigned long long lo = (unsigned long long)u53 * Wq;
+  const unsigned long long hi = __umul64hi((unsigned long long)u53, Wq);
+  const unsigned long long t = (hi << 11) | (lo >> 53);
+  unsigned long long Q = S - wq;
+  int vhit = -1;
+  unsigned long long qh = 0ull, Qh = 0ull;
+  for (int v = v0; v < v1; ++v) {
+    const unsigned long long q = Qn[v];
+    Q += q;
+    if (vhit < 0 && Q > t) {
+      vhit = v;
+      qh = q;
+      Qh = Q;
+    }
+  }
+  const unsigned long long hit = __ballot(vhit >= 0);
+  if (hit == 0ull) {
+    o.vstar = r;
+    o.margin = 0.0;
+  } else {
+    const int first = __ffsll((long long)hit) - 1;
+    o.vstar = __builtin_amdgcn_readlane(vhit, first);
+    const unsigned long long qv = readlane_u64(qh, first), Qv = readlane_u64(Qh, first);
+    const unsigned long long d1 = t - (Qv - qv), d2 = Qv - t;
+    o.margin = (double)(d1 < d2 ? d1 : d2) / (double)Wq;
+  }
+  o.e_new = En[o.vstar];
+  return o;
+}
+
 // Per-chain bookkeeping of a selected step (one lane): carried energy e_new,
 // node-weighted energy, counters and, with a ring, the step's record.  tau is the
 // near-tie threshold of this step.
@@ -227,15 +292,16 @@ __device__ __forceinline__ double block_sum256(double x, double* red4, int tid) 
 
 // The exact change of the pair sum U = sum_{i<j} J_ij s_i s_j when the sites of D flip
 // (s the old state): the pairs with one site in D change sign, so
-//   dU = -2 sum_{i in D} s_i sum_{j not in D} J_ij s_j,
-// |D| rows of the symmetric J64 in FP64 (exact integers for +-1 couplings).  Called
-// by all 256 threads; dW, sW: the words of D and of the old state in LDS; Dl: LDS for
-// |D| site entries (site | sign << 15).  Wave 0 lists the sites in word order (lane l
+//   dU = -2 sum_{i in D} s_i sum_{j not in D} J_ij s_j = -2 cross,
+// |D| rows of the symmetric J64 in FP64 (exact integers for +-1 couplings).  This
+// returns slice sl of S of the cross sum: the listed sites a with a % S == sl.  Called by
+// all 256 threads; dW, sW: the words of D and of the old state in LDS; Dl: LDS for |D|
+// site entries (site | sign << 15).  Wave 0 lists the sites in word order (lane l
 // takes words 4l .. 4l+3, W <= 256); then thread t takes columns j = t, t+256, ..
-// outside D and sums s_i J_ij over the listed rows, eight rows of loads at a time.
-__device__ __forceinline__ double flip_delta_u(const double* __restrict__ J64, int N, int Np, int W,
-                                               const uint32_t* dW, const uint32_t* sW, uint16_t* Dl, int* sh_nd,
-                                               double* red4, int tid) {
+// outside D and sums s_i J_ij over its rows, eight rows of loads at a time.
+__device__ __forceinline__ double flip_cross(const double* __restrict__ J64, int N, int Np, int W,
+                                             const uint32_t* dW, const uint32_t* sW, uint16_t* Dl, int* sh_nd,
+                                             double* red4, int tid, int sl, int S) {
   const int lane = tid & 63;
   if (tid < 64) {
     uint32_t wd[4];
@@ -270,21 +336,72 @@ __device__ __forceinline__ double flip_delta_u(const double* __restrict__ J64, i
     if ((dW[wj] >> bj) & 1u) continue;
     const double* __restrict__ col = J64 + j;
     double gsum = 0.0;
-    int a = 0;
-    for (; a + 8 <= nd; a += 8) {
+    int a = sl;
+    for (; a + 7 * S < nd; a += 8 * S) {
       double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = col[(size_t)(Dl[a + q] & 0x7FFF) * Np];
+      for (int q = 0; q < 8; ++q) v[q] = col[(size_t)(Dl[a + q * S] & 0x7FFF) * Np];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) gsum = gsum + ((Dl[a + q] >> 15) ? -v[q] : v[q]);
+      for (int q = 0; q < 8; ++q) gsum = gsum + ((Dl[a + q * S] >> 15) ? -v[q] : v[q]);
     }
-    for (; a < nd; ++a) {
+    for (; a < nd; a += S) {
       const double v = col[(size_t)(Dl[a] & 0x7FFF) * Np];
       gsum = gsum + ((Dl[a] >> 15) ? -v : v);
     }
     cross = cross + (((sW[wj] >> bj) & 1u) ? -gsum : gsum);
   }
-  return -2.0 * block_sum256(cross, red4, tid);
+  return block_sum256(cross, red4, tid);
+}
+
+// Slice blockIdx.y of S of the cross sum of every global chain blockIdx.x +
+// chain_off that moved (mflag), from the chain's words of D and of its old state
+// (moveD [chains][2 Wmax]: D, then old spins) written by the selection.
+// Dynamic LDS: 8 Wmax + 2 Nmax bytes.
+__global__ __launch_bounds__(256) void k_move_delta(char* __restrict__ ws, const Inst* __restrict__ insts,
+                                                    const int32_t* __restrict__ chain_inst, int chain_off,
+                                                    const uint32_t* __restrict__ moveD, int Wmax,
+                                                    const int32_t* __restrict__ mflag, double* __restrict__ xpart,
+                                                    int S) {
+  extern __shared__ uint32_t mv_lds[];
+  __shared__ int sh_nd;
+  __shared__ double sh_red[4];
+  const int g = chain_off + blockIdx.x, sl = blockIdx.y, tid = threadIdx.x;
+  if (!mflag[g]) return;
+  const Inst& in = insts[chain_inst[g]];
+  const int W = in.W;
+  uint32_t* dW = mv_lds;
+  uint32_t* sW = dW + Wmax;
+  const uint32_t* src = moveD + (size_t)g * 2 * Wmax;
+  for (int w = tid; w < W; w += 256) {
+    dW[w] = src[w];
+    sW[w] = src[Wmax + w];
+  }
+  __syncthreads();
+  const double x = flip_cross(ws_at<const double>(ws, in.J64), in.N, in.Np, W, dW, sW,
+                              reinterpret_cast<uint16_t*>(sW + Wmax), &sh_nd, sh_red, tid, sl, S);
+  if (tid == 0) xpart[(size_t)g * S + sl] = x;
+}
+
+// The carried pair sum of every chain that moved: U += -2 (sum of the S slices, in
+// order); E = -(scale U) into e_cur and into the step's record.  With a step clock the
+// step is *clk + step.
+__global__ void k_move_finish(const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
+                              int n, int total_chains, const int32_t* __restrict__ mflag,
+                              const double* __restrict__ xpart, int S, double* __restrict__ u_cur,
+                              double* __restrict__ e_cur, Record* __restrict__ ring, int trace_steps, uint32_t step,
+                              const uint32_t* __restrict__ clk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int g = chain_off + i;
+  if (!mflag[g]) return;
+  if (clk) step += *clk;
+  double cross = 0.0;
+  for (int sl = 0; sl < S; ++sl) cross += xpart[(size_t)g * S + sl];
+  const double U = u_cur[g] + (-2.0 * cross);
+  const double E = -(insts[chain_inst[g]].scale * U);
+  u_cur[g] = U;
+  e_cur[g] = E;
+  if (trace_steps > 0) ring[(size_t)(step % (uint32_t)trace_steps) * total_chains + g].e_cur = E;
 }
 
 // One block of 256 threads per chain: node rule (MCMCMC) or Metropolis rate, move,
@@ -299,11 +416,13 @@ __device__ __forceinline__ double flip_delta_u(const double* __restrict__ J64, i
 //   2. wave 0: the rule (apply_rule);
 //   3. thread w: the new state's word and the next step's base word (ChainWords),
 //      loaded before step 1;
-//   4. the new U: exact = 1: U + dU(D*) in FP64 from the rows of the path set D*
-//      between the old and the new state (flip_delta_u); exact = 0: the chosen
-//      column's pair sum as scored;
+//   4. the new U: exact = 0: the chosen column's pair sum as scored; exact = 1: the
+//      words of the set D* of flipped sites and of the old state go to moveD and the
+//      chain's mflag is set, and k_move_delta / k_move_finish add the exact FP64
+//      difference dU(D*) from the rows of D* (spread over many blocks) after this
+//      launch, rewriting the carried energy and the record's;
 //   5. thread 0: the bookkeeping and the record.
-// Dynamic LDS: max(16 (M+1), 8 W + 2 N) bytes.
+// Dynamic LDS: 16 (M+1) bytes.
 __global__ __launch_bounds__(256) void k_select(
     char* __restrict__ ws, const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
     int total_chains, double* __restrict__ e_cur, double* __restrict__ u_cur, const int32_t* __restrict__ roots_all,
@@ -311,10 +430,10 @@ __global__ __launch_bounds__(256) void k_select(
     unsigned long long* __restrict__ near_ties, double* __restrict__ min_margin, double* __restrict__ e_bar_out,
     int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, uint32_t slot,
     uint32_t slot_next, int trace_steps, int next_base, const uint32_t* __restrict__ clk, double beta0,
-    double beta1, long long total, const double* __restrict__ sched, int exact) {
+    double beta1, long long total, const double* __restrict__ sched, int exact, uint32_t* __restrict__ moveD,
+    int Wmax, int32_t* __restrict__ mflag) {
   extern __shared__ double sel_lds[];
-  __shared__ int sh_vstar, sh_nd;
-  __shared__ double sh_red[4];
+  __shared__ int sh_vstar;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = chain_off + blockIdx.x;   // global chain
   if (g >= total_chains) return;
@@ -365,18 +484,14 @@ __global__ __launch_bounds__(256) void k_select(
   x[0] = cw.new_word(flipsT, Bp, col0, vstar, r, W, tid, 0);
   cw.store(spins, base_next, x, moved, next_base != 0, W, tid);
   double u_new = U;
-  if (moved) {
-    if (exact) {
-      uint32_t* dW = reinterpret_cast<uint32_t*>(sel_lds);   // En and Qn are no longer read
-      uint32_t* sW = dW + W;
-      if (tid < W) {
-        dW[tid] = cw.s_old[0] ^ x[0];
-        sW[tid] = cw.s_old[0];
-      }
-      __syncthreads();
-      u_new = U + flip_delta_u(ws_at<const double>(ws, in.J64), in.N, in.Np, W, dW, sW,
-                               reinterpret_cast<uint16_t*>(sW + W), &sh_nd, sh_red, tid);
-    } else if (tid == 0) {
+  if (exact) {
+    if (tid == 0) mflag[g] = moved ? 1 : 0;
+    if (moved && tid < W) {
+      moveD[(size_t)g * 2 * Wmax + tid] = cw.s_old[0] ^ x[0];
+      moveD[(size_t)g * 2 * Wmax + Wmax + tid] = cw.s_old[0];
+    }
+  } else if (moved) {
+    if (tid == 0) {
       // the chosen node's column: node v >= 1 is column v-1, the hub (r >= 1) column r-1
       const size_t col = col0 + (size_t)(vstar >= 1 ? vstar - 1 : r - 1);
       double acc = 0.0;
@@ -385,7 +500,8 @@ __global__ __launch_bounds__(256) void k_select(
     }
   }
   if (tid == 0) {
-    u_cur[g] = u_new;
+    // exact, moved: k_move_finish replaces the energy recorded here
+    if (!(exact && moved)) u_cur[g] = u_new;
     record_outcome(o, -(in.scale * u_new), g, r, tol + beta * in.tie_coef, step, trace_steps, total_chains, e_cur,
                    e_bar_out, moves, near_ties, min_margin, ring);
   }

@@ -24,13 +24,13 @@ MC3_E_UNSUPPORTED, MC3_E_NUMERIC, MC3_E_WORKSPACE = -5, -6, -7
 MC3_FP64, MC3_SPLIT_BF16 = 0, 1
 MC3_RULE_MCMCMC, MC3_RULE_METROPOLIS = 0, 1
 MC3_SCORER_GEMM, MC3_SCORER_DELTA, MC3_SCORER_AUTO = 0, 1, 2
-MC3_LAW_UNIFORM, MC3_LAW_LINE, MC3_LAW_TABLE = 0, 1, 2
+MC3_LAW_UNIFORM, MC3_LAW_LINE, MC3_LAW_TABLE, MC3_LAW_BIASED = 0, 1, 2, 3
 MC3_ENERGY_EXACT, MC3_ENERGY_SCORED = 0, 1
 
 PRECISIONS = {"fp64": MC3_FP64, "split_bf16": MC3_SPLIT_BF16}
 RULES = {"mcmcmc": MC3_RULE_MCMCMC, "metropolis": MC3_RULE_METROPOLIS}
 SCORERS = {"gemm": MC3_SCORER_GEMM, "delta": MC3_SCORER_DELTA, "auto": MC3_SCORER_AUTO}
-LAWS = {"uniform": MC3_LAW_UNIFORM, "line": MC3_LAW_LINE, "table": MC3_LAW_TABLE}
+LAWS = {"uniform": MC3_LAW_UNIFORM, "line": MC3_LAW_LINE, "table": MC3_LAW_TABLE, "biased": MC3_LAW_BIASED}
 ENERGY_UPDATES = {"exact": MC3_ENERGY_EXACT, "scored": MC3_ENERGY_SCORED}
 
 STATUS_NAMES = {0: "MC3_OK", -1: "MC3_E_ARG", -3: "MC3_E_DEVICE", -4: "MC3_E_STATE",
@@ -54,7 +54,7 @@ class Config(ctypes.Structure):
                 ("near_tie_tol", ctypes.c_double), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
                 ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double)),
                 ("tile_cols", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
-                ("energy_update", ctypes.c_int32), ("drift_tol", ctypes.c_double)]
+                ("energy_update", ctypes.c_int32), ("drift_tol", ctypes.c_double), ("bias", ctypes.c_double)]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -69,7 +69,7 @@ class BatchConfig(ctypes.Structure):
                 ("instances", ctypes.POINTER(InstanceDesc)), ("scorer", ctypes.c_int32), ("arity", ctypes.c_int32),
                 ("law", ctypes.c_int32), ("law_table", ctypes.POINTER(ctypes.c_double)),
                 ("tile_cols", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
-                ("energy_update", ctypes.c_int32), ("drift_tol", ctypes.c_double)]
+                ("energy_update", ctypes.c_int32), ("drift_tol", ctypes.c_double), ("bias", ctypes.c_double)]
 
 
 class Schedule(ctypes.Structure):
@@ -149,7 +149,7 @@ def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: st
                 rule: str = "mcmcmc", trace_steps: int = 0, seed: int = 0, chain_base: int = 0,
                 near_tie_tol: float = -1.0, mean_steps: int = 0, scorer: str = "gemm", arity: int = 0,
                 law: str = "uniform", law_table=None, tile_cols: int = 0, recompute_every: int = 0,
-                energy_update: str = "exact", drift_tol: float = -1.0) -> Config:
+                energy_update: str = "exact", drift_tol: float = -1.0, bias: float = 0.0) -> Config:
     """arity 0: the M-ary star; law "line" (arity 1): the line-graph addition process;
     law "table": root weights law_table[0..M]; tile_cols 0: the split scoring tile width
     by column count, else 128, 256 or 512; recompute_every K > 0: FP64 recompute of the
@@ -159,7 +159,7 @@ def make_config(N: int, M: int, chains: int, kmin: int, kmax: int, precision: st
     cfg = Config(N, M, chains, kmin, kmax, PRECISIONS[precision], RULES[rule], trace_steps, seed, chain_base,
                  mean_steps, near_tie_tol, SCORERS[scorer], arity, LAWS[law],
                  None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols,
-                 recompute_every, ENERGY_UPDATES[energy_update], drift_tol)
+                 recompute_every, ENERGY_UPDATES[energy_update], drift_tol, bias)
     cfg._keep_table = tab   # the table lives as long as the config
     return cfg
 
@@ -174,7 +174,7 @@ def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcm
                       seed: int = 0, chain_base: int = 0, near_tie_tol: float = -1.0,
                       mean_steps: int = 0, scorer: str = "gemm", arity: int = 0, law: str = "uniform",
                       law_table=None, tile_cols: int = 0, recompute_every: int = 0, energy_update: str = "exact",
-                      drift_tol: float = -1.0) -> BatchConfig:
+                      drift_tol: float = -1.0, bias: float = 0.0) -> BatchConfig:
     """instances: sequence of (N, M, chains, kmin, kmax); law "table": law_table holds
     the root weights of every instance, M_i+1 values each, in instance order;
     tile_cols as in make_config."""
@@ -183,7 +183,7 @@ def make_batch_config(instances, precision: str = "split_bf16", rule: str = "mcm
     cfg = BatchConfig(len(instances), PRECISIONS[precision], RULES[rule], trace_steps, mean_steps, chain_base, seed,
                       near_tie_tol, ctypes.cast(arr, ctypes.POINTER(InstanceDesc)), SCORERS[scorer], arity, LAWS[law],
                       None if tab is None else tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tile_cols,
-                      recompute_every, ENERGY_UPDATES[energy_update], drift_tol)
+                      recompute_every, ENERGY_UPDATES[energy_update], drift_tol, bias)
     cfg._keep = arr   # the descriptor array lives as long as the config
     cfg._keep_table = tab
     return cfg

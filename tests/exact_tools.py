@@ -211,3 +211,45 @@ def tree_kernel(E: np.ndarray, beta: float, N: int, M: int, arity: int, kmin: in
             pn = w / w.sum(axis=1, keepdims=True)
             np.add.at(P, (np.full(nodes.shape, s), nodes), pr * cprob[:, None] * pn)
     return P
+
+
+# ---------------------------------------------------------------- state-dependent proposals
+
+def site_probs(E: np.ndarray, N: int, c: int, alpha: float) -> np.ndarray:
+    """p_i(c) proportional to exp(-alpha (E(c with site i flipped) - E(c))), i = 0..N-1."""
+    dE = np.array([E[c ^ (1 << i)] - E[c] for i in range(N)])
+    w = np.exp(-alpha * (dE - dE.min()))
+    return w / w.sum()
+
+
+def biased_star_kernel(E: np.ndarray, beta: float, N: int, M: int, alpha: float, ratio: bool = True) -> np.ndarray:
+    """Exact transition matrix of one step on the M-ary star with the state-dependent
+    single-site proposal: the current state sits at r ~ U{0..M}; r = 0: the hub is the
+    current state; r >= 1: the hub is the current state with site i_r flipped,
+    i_r ~ p(.|current); every other leaf e is the hub with site i_e ~ p(.|hub)
+    flipped.  Node weights exp(-beta E_v) G_v with G_hub = 1 and, for leaf v,
+    G_v = p_{i_v}(c_v) / p_{i_v}(hub) -- the graph's generation probability from c_v
+    relative to the hub's (ratio=False drops it: the negative control)."""
+    S = 2 ** N
+    P = np.zeros((S, S))
+    probs = {c: site_probs(E, N, c, alpha) for c in range(S)}
+    combos = list(itertools.product(range(N), repeat=M))
+    for s in range(S):
+        for r in range(M + 1):
+            for sites in combos:   # sites[e-1] = i_e
+                if r == 0:
+                    hub = s
+                    pr = np.prod([probs[hub][i] for i in sites])
+                else:
+                    hub = s ^ (1 << sites[r - 1])
+                    pr = probs[s][sites[r - 1]] * np.prod([probs[hub][i] for e, i in enumerate(sites, 1) if e != r])
+                nodes = [hub] + [hub ^ (1 << i) for i in sites]
+                G = [1.0] + [probs[nodes[v]][sites[v - 1]] / probs[hub][sites[v - 1]] for v in range(1, M + 1)]
+                if not ratio:
+                    G = [1.0] * (M + 1)
+                En = E[nodes]
+                w = np.exp(-beta * (En - En.min())) * np.array(G)
+                pn = w / w.sum()
+                for v in range(M + 1):
+                    P[s, nodes[v]] += pr / (M + 1) * pn[v]
+    return P

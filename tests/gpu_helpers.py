@@ -35,7 +35,8 @@ def column_nodes(M, r):
     return [0 if (r >= 1 and m == r - 1) else m + 1 for m in range(M)]
 
 
-LAW_CODES = {"uniform": oracle.LAW_UNIFORM, "line": oracle.LAW_LINE, "table": oracle.LAW_TABLE}
+LAW_CODES = {"uniform": oracle.LAW_UNIFORM, "line": oracle.LAW_LINE, "table": oracle.LAW_TABLE,
+             "biased": oracle.LAW_BIASED}
 
 
 def oracle_candidates(seed, chain, step, N, M, kmin, kmax, s, rule="mcmcmc", arity=None, law="uniform",
@@ -56,7 +57,7 @@ def eps_energy(precision: str, N: int) -> float:
 
 def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas, rule, energy_rtol,
                        exact=False, chain_base=0, arity=None, law="uniform", table=None, eps_e=None, tau=None,
-                       max_forced=None, ecur_rtol=None):
+                       max_forced=None, ecur_rtol=None, alpha=0.0):
     """Run the oracle over the same steps, taking the GPU's pick at the steps the GPU
     flagged as near ties (guided replay), and compare every record.
 
@@ -81,7 +82,7 @@ def compare_trajectory(gpu_rec, J, scale, N, M, chains, kmin, kmax, seed, betas,
         assert eps_e is not None and max_forced is not None, "guided comparison needs eps_e and max_forced"
     ro = oracle.run(J, scale, N, M, chains, kmin, kmax, seed, betas,
                     rule=oracle.RULE_METROPOLIS if rule == "metropolis" else oracle.RULE_MCMCMC,
-                    forced=forced, chain_base=chain_base, arity=arity, law=LAW_CODES[law], table=table)
+                    forced=forced, chain_base=chain_base, arity=arity, law=LAW_CODES[law], table=table, alpha=alpha)
     orec = ro["rec"]
     assert np.array_equal(gpu_rec["r"], orec["r"]), "roots differ"
     bad = np.argwhere(gpu_rec["vstar"] != orec["vstar"])

@@ -196,13 +196,17 @@ def test_batch_rejects_bad_header_fields(lib):
     assert lib.mc3_step_n_per_instance(None, 0, 1, 1.0, 1.0, 1) == native.MC3_E_ARG
 
 
-@pytest.mark.parametrize("shape,scorer,expect", [
-    ((64, 4, 2, 1, 16), "delta", native.MC3_OK), ((64, 4, 2, 1, 17), "delta", native.MC3_E_UNSUPPORTED),
-    ((4097, 4, 2, 1, 2), "delta", native.MC3_E_UNSUPPORTED), ((64, 513, 2, 1, 2), "delta", native.MC3_E_UNSUPPORTED),
-    ((4096, 512, 2, 1, 16), "delta", native.MC3_E_UNSUPPORTED),   # LDS beyond 64 KiB
-    ((64, 4, 2, 1, 17), "auto", native.MC3_OK), ((64, 4, 2, 1, 16), "gemm", native.MC3_OK)])
-def test_field_update_scorer_limits(lib, shape, scorer, expect):
-    cfg = native.make_config(*shape, precision="fp64", scorer=scorer)
+@pytest.mark.parametrize("shape,scorer,arity,expect", [
+    ((64, 4, 2, 1, 16), "delta", 0, native.MC3_OK),
+    # beyond the small-flip kernel: stars go to the kernel for flip sets of any size
+    ((64, 4, 2, 1, 17), "delta", 0, native.MC3_OK), ((4097, 4, 2, 1, 2), "delta", 0, native.MC3_E_UNSUPPORTED),
+    ((3000, 4, 2, 1, 2), "delta", 0, native.MC3_OK),
+    ((64, 513, 2, 1, 2), "delta", 0, native.MC3_OK), ((1024, 128, 4, 1, 128), "delta", 0, native.MC3_OK),
+    ((4096, 512, 2, 1, 16), "delta", 0, native.MC3_E_UNSUPPORTED),   # LDS beyond 64 KiB in both kernels
+    ((64, 14, 2, 1, 17), "delta", 2, native.MC3_E_UNSUPPORTED),      # a tree with large flip sets
+    ((64, 4, 2, 1, 17), "auto", 0, native.MC3_OK), ((64, 4, 2, 1, 16), "gemm", 0, native.MC3_OK)])
+def test_field_update_scorer_limits(lib, shape, scorer, arity, expect):
+    cfg = native.make_config(*shape, precision="fp64", scorer=scorer, arity=arity)
     n = ctypes.c_size_t()
     assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == expect
     if expect == native.MC3_E_UNSUPPORTED:

@@ -73,3 +73,41 @@ def test_library_rejects_other_tile_widths(width):
     assert e.value.status == native.MC3_E_ARG
     with pytest.raises(native.MC3Error):
         native.workspace_size(native.make_batch_config([(64, 8, 4, 1, 4)], tile_cols=width))
+
+
+def _make2(N=128, M=16, chains=4, kmax=4, precision="split_bf16"):
+    return lambda scorer, w: native.make_config(N, M, chains, 1, kmax, precision=precision, scorer=scorer,
+                                                tile_cols=w)
+
+
+def _step_timer(times, calls):
+    def t(make_cfg, init, scorer, width, steps, warmup, beta):
+        cfg = make_cfg(scorer, width)
+        assert cfg.tile_cols == width and cfg.scorer == native.SCORERS[scorer]
+        calls.append((scorer, width))
+        return times[(scorer, width)]
+    return t
+
+
+def test_scorer_choice_times_every_accepted_option(tmp_path):
+    calls = []
+    times = {("gemm", 0): 0.05, ("gemm", 128): 0.06, ("gemm", 256): 0.04, ("gemm", 512): 0.07, ("delta", 0): 0.01}
+    path = str(tmp_path / "sc.json")
+    r = autotune.tune_scorer(_make2(), None, cache_path=path, device="dev", timer=_step_timer(times, calls))
+    assert (r["scorer"], r["tile_cols"]) == ("delta", 0) and len(calls) == 5
+    again = autotune.tune_scorer(_make2(), None, cache_path=path, device="dev", timer=_step_timer(times, calls))
+    assert again["cached"] and again["scorer"] == "delta" and len(calls) == 5
+    # FP64 pair sums have no tile widths to time
+    calls.clear()
+    r = autotune.tune_scorer(_make2(precision="fp64"), None, device="dev", timer=_step_timer(times, calls))
+    assert sorted(calls) == [("delta", 0), ("gemm", 0)] and r["scorer"] == "delta"
+
+
+def test_scorer_choice_skips_what_the_library_refuses():
+    # a tree with large flip sets: the field-update scorers refuse it
+    make = lambda scorer, w: native.make_config(64, 14, 2, 1, 17, precision="split_bf16", scorer=scorer, tile_cols=w,
+                                                arity=2)
+    calls = []
+    times = {("gemm", 0): 0.05, ("gemm", 128): 0.06, ("gemm", 256): 0.04, ("gemm", 512): 0.07, ("delta", 0): 0.0}
+    r = autotune.tune_scorer(make, None, device="dev", timer=_step_timer(times, calls))
+    assert ("delta", 0) not in calls and (r["scorer"], r["tile_cols"]) == ("gemm", 256)

@@ -124,3 +124,47 @@ def test_delta_rejects_stepwise_calls():
         assert ei.value.status == native.MC3_E_UNSUPPORTED
     ctx.step_n(0, 5, 1.0, 1.0, 1)
     assert ctx.measure()[2]["steps_done"] == 5
+
+
+# ---------------------------------------------------------------- flip sets of any size (stars)
+
+@pytest.mark.parametrize("N,M,chains,kmin,kmax", [(64, 8, 3, 1, 32), (256, 32, 2, 1, 64), (300, 5, 2, 40, 120)])
+def test_star_any_flip_size_pm1_bit_exact(N, M, chains, kmin, kmax):
+    """Stars whose flip sets are beyond the small-flip kernel: +-1 trajectories equal the
+    oracle's and the matrix-core scorer's bit for bit."""
+    steps = 400
+    announce(f"delta star pm1 N={N} M={M} k={kmin}..{kmax}")
+    J, scale = inputs.couplings_pm1(N, 1300 + N)
+    recs = {}
+    for scorer in ("delta", "gemm"):
+        cfg = native.make_config(N, M, chains, kmin, kmax, precision="fp64", trace_steps=steps, seed=6,
+                                 scorer=scorer)
+        ctx = native.Context(cfg)
+        ctx.init_couplings(J, scale)
+        ctx.init_chains()
+        ctx.step_n(0, steps, 0.9, 0.9, 1)
+        recs[scorer] = (ctx.read_records(0, steps), ctx.measure()[1])
+        ctx.close()
+    for f in ("r", "vstar", "e_cur", "margin", "flags"):
+        assert np.array_equal(recs["delta"][0][f], recs["gemm"][0][f]), f
+    assert np.array_equal(recs["delta"][1], recs["gemm"][1])
+    compare_trajectory(recs["delta"][0], J, scale, N, M, chains, kmin, kmax, 6, np.full(steps, 0.9), "mcmcmc", 0.0,
+                       exact=True)
+
+
+def test_star_headline_flip_sizes_gauss_guided():
+    """The headline's shape of graph (N = 1024, M = 128, flip sets of 1..128 sites) with
+    the field-update scorer: 20 steps of 4 chains match the oracle, guided at flagged
+    near ties, energies within 1e-9."""
+    N, M, chains, steps = 1024, 128, 4, 20
+    announce("delta star headline flip sizes")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0003)
+    cfg = native.make_config(N, M, chains, 1, 128, precision="fp64", trace_steps=steps, seed=3, scorer="delta")
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    ctx.step_n(0, steps, 1.0, 1.0, 1)
+    rec = ctx.read_records(0, steps)
+    assert (rec["flags"] & 2).any()
+    compare_trajectory(rec, J, scale, N, M, chains, 1, 128, 3, np.ones(steps), "mcmcmc", 1e-9,
+                       eps_e=eps_energy("fp64", N), max_forced=2, ecur_rtol=1e-9)

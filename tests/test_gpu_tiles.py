@@ -82,3 +82,24 @@ def test_autotuner_on_the_device(tmp_path):
     assert set(r["ms"]) == set(autotune.WIDTHS) and all(v > 0 for v in r["ms"].values())
     assert r["ms"][r["tile_cols"]] == min(r["ms"].values())
     assert autotune.tune_tile_cols(make, init, cache_path=path)["cached"]
+
+
+def test_scorer_tuner_on_the_device(tmp_path):
+    """tune_scorer times every scorer the library accepts (split pair sums at each width,
+    the field update) and picks one whose timing it reports."""
+    N, M, chains = 256, 16, 32
+    announce("scorer tuner N=256 M=16")
+    J, scale = inputs.couplings_gauss(N, 71)
+    make = lambda scorer, w: native.make_config(N, M, chains, 1, 4, precision="split_bf16", seed=2, scorer=scorer,
+                                                tile_cols=w)
+
+    def init(ctx):
+        ctx.init_couplings(J, scale)
+        ctx.init_chains()
+
+    path = str(tmp_path / "scorers.json")
+    r = autotune.tune_scorer(make, init, beta=1.0, steps=10, warmup=2, cache_path=path)
+    assert set(r["ms"]) == {"gemm:0", "gemm:128", "gemm:256", "gemm:512", "delta:0"}
+    assert all(v > 0 for v in r["ms"].values())
+    assert r["ms"][f"{r['scorer']}:{r['tile_cols']}"] == min(r["ms"].values())
+    assert autotune.tune_scorer(make, init, beta=1.0, cache_path=path)["cached"]
