@@ -267,3 +267,37 @@ def test_table_law_batch_validation(lib):
     bad = native.make_batch_config(descs, precision="fp64", law="table",
                                    law_table=[1.0, 2.0, 3.0, 4.0, 0.0, 0.0, 0.0])
     assert lib.mc3_batch_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == native.MC3_E_ARG
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(recompute_every=-1), native.MC3_E_ARG), (dict(drift_tol=float("nan")), native.MC3_E_ARG),
+    (dict(recompute_every=100, drift_tol=1e-6), native.MC3_OK),
+    (dict(law="biased", scorer="delta", bias=0.5), native.MC3_OK),
+    (dict(law="biased", scorer="auto", bias=0.5), native.MC3_OK),
+    (dict(law="biased", scorer="gemm", bias=0.5), native.MC3_E_ARG),
+    (dict(law="biased", scorer="delta", bias=float("inf")), native.MC3_E_ARG),
+    (dict(law="biased", scorer="delta", kmax=2), native.MC3_E_ARG),
+    (dict(law="biased", scorer="delta", arity=2), native.MC3_E_ARG),
+    (dict(law="biased", scorer="delta", rule="metropolis", M=1), native.MC3_E_ARG),
+    (dict(law="biased", scorer="delta", N=1025), native.MC3_E_UNSUPPORTED),
+    (dict(law="biased", scorer="delta", M=513), native.MC3_E_UNSUPPORTED)])
+def test_energy_and_proposal_options_validated(lib, kw, expect):
+    args = dict(N=64, M=4, chains=2, kmin=1, kmax=1, precision="fp64")
+    args.update(kw)
+    cfg = native.make_config(**args)
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == expect
+
+
+def test_energy_update_field_validated(lib):
+    cfg = native.make_config(64, 4, 2, 1, 1)
+    cfg.energy_update = 7
+    n = ctypes.c_size_t()
+    assert lib.mc3_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == native.MC3_E_ARG
+
+
+def test_noalloc_and_schedule_calls_reject_null(lib):
+    h = ctypes.c_void_p()
+    assert lib.mc3_create_noalloc(None, None, ctypes.byref(h)) == native.MC3_E_ARG
+    assert lib.mc3_select_betas(None, 0, None) == native.MC3_E_ARG
+    assert lib.mc3_step_n_schedules(None, 0, 1, None) == native.MC3_E_ARG
