@@ -333,6 +333,15 @@ def _batched_workload(args):
     ctx.step_n_per_instance(3 + args.batch_steps, n_per, beta, beta, 1)
     torch.cuda.synchronize()
     per_ms = (time.perf_counter() - t0) * 1e3 / n_per
+    # the same steps replayed from a captured HIP graph: one replay launches a 272-step
+    # body; a run needs at least 288 steps to replay once.  The capture (outside the
+    # timing) is reused by a run starting at the same step modulo 272.
+    graph = None
+    if args.batch_graph_steps >= 288:
+        t1 = 3 + args.batch_steps + n_per
+        ctx.step_n_graph(t1, 288, beta, beta, 1)
+        gms = _timed_steps(ctx, t1 + 2 * 272, args.batch_graph_steps, beta, beta, 1, graph=True)
+        graph = {"ms_per_step": gms / args.batch_graph_steps, "steps": args.batch_graph_steps}
     ctx.close()
     Ns = np.array([d[0] for d in descs], dtype=np.float64)
     Ms = np.array([d[1] for d in descs], dtype=np.float64)
@@ -352,6 +361,8 @@ def _batched_workload(args):
             "per_instance_launches": {"ms_per_step": per_ms, "candidates_per_s": cand / (per_ms / 1e3),
                                       "steps": n_per, "launches_per_step": 3 * len(descs)},
             "speedup_batched": per_ms / ms_step,
+            "batched_graph_replay": None if graph is None else {
+                **graph, "candidates_per_s": cand / (graph["ms_per_step"] / 1e3)},
             "score_roofline": {"flops_per_launch": flops, "achieved_tflops": flops / score_s / 1e12,
                                "frac_mfma_bf16": flops / score_s / 1e12 / PEAK_BF16_TFLOPS,
                                "j_bytes_per_launch": jbytes, "achieved_gbs_j_once": jbytes / score_s / 1e9,
@@ -643,6 +654,8 @@ def main():
                     help="steps timed on the latency-bound N=32 and N=256 workloads (0 skips them)")
     ap.add_argument("--batch-instances", type=int, default=2000, help="0 skips the batched workload")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-graph-steps", type=int, default=560,
+                    help="steps of the batch replayed from a captured HIP graph (0 skips; at least 288 to replay)")
     ap.add_argument("--large-steps", type=int, default=16, help="0 skips the N=8192 workload")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection run: one plain 512 MiB device copy (calibrates FETCH_SIZE/WRITE_SIZE), "

@@ -101,31 +101,30 @@ __device__ __forceinline__ void copy_a(SplitStage<WAVES>& st, const uint4* src, 
 // One 32-k chunk: DMA of the next chunk's A fragments into `nxt`; this chunk's flip
 // and base words (loaded into registers two chunks ago) combined into the columns'
 // spin words `w`; the loads of the words two chunks ahead issued into the same
-// registers (pf/pb: the CF columns' flip and base words of that chunk); then 2 k-steps
-// x 12 A fragments x CF column fragments of MFMAs from `cur`.  The closing wait lets the
-// 2 CF word loads stay in flight (they were issued after the copies; loads complete in
-// order), so global latency of the words is hidden behind two chunks.
-template <int WAVES, int CF, int RF_LAST = 3>
-__device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitStage<WAVES>& cur,
+// registers; then 2 k-steps x 12 A fragments x 2 column fragments of MFMAs from
+// `cur`.  The closing wait lets the four word loads stay in flight (they were issued
+// after the copies; loads complete in order), so global latency of the words is hidden
+// behind two chunks.
+template <int WAVES, int RF_LAST = 3>
+__device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][2], const SplitStage<WAVES>& cur,
                                             SplitStage<WAVES>& nxt, const uint4* next_a, size_t row_stride,
-                                            uint32_t (&rawf)[CF], uint32_t (&rawb)[CF], const uint32_t* const (&pf)[CF],
-                                            const uint32_t* const (&pb)[CF], uint32_t rootmask, int lane, int wave,
-                                            uint32_t (&w)[CF]) {
-  static_assert(CF == 2 || CF == 4, "2 or 4 column fragments per wave");
+                                            uint32_t (&rawf)[2], uint32_t (&rawb)[2], const uint32_t* pf0,
+                                            const uint32_t* pf1, const uint32_t* pb0, const uint32_t* pb1,
+                                            uint32_t rootmask, int lane, int wave, uint32_t (&w)[2]) {
   copy_a<WAVES>(nxt, next_a, row_stride, wave);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) w[cf] = rawb[cf] ^ (((rootmask >> cf) & 1u) ? 0u : rawf[cf]);
-#pragma unroll
-  for (int cf = 0; cf < CF; ++cf) rawf[cf] = *pf[cf];
-#pragma unroll
-  for (int cf = 0; cf < CF; ++cf) rawb[cf] = *pb[cf];
+  for (int cf = 0; cf < 2; ++cf) w[cf] = rawb[cf] ^ (((rootmask >> cf) & 1u) ? 0u : rawf[cf]);
+  rawf[0] = *pf0;
+  rawf[1] = *pf1;
+  rawb[0] = *pb0;
+  rawb[1] = *pb1;
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    bf16x8 b[CF];
+    bf16x8 b[2];
 #pragma unroll
-    for (int cf = 0; cf < CF; ++cf) b[cf] = spins_to_bf16(w[cf], 8 * s + 4 * (lane >> 5));
+    for (int cf = 0; cf < 2; ++cf) b[cf] = spins_to_bf16(w[cf], 8 * s + 4 * (lane >> 5));
     bf16x8 a[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
@@ -138,38 +137,36 @@ __device__ __forceinline__ void split_chunk(f32x16 (&acc)[4][CF], const SplitSta
     for (int i = 0; i < 12; ++i) {
       if (i % 4 > RF_LAST) continue;
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf)
+      for (int cf = 0; cf < 2; ++cf)
         acc[i % 4][cf] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[cf], acc[i % 4][cf], 0, 0, 0);
     }
   }
-  // vmcnt(2 CF), no wait on the other counters
-  __builtin_amdgcn_s_waitcnt((2 * CF) | (7 << 4) | (15 << 8));
+  // vmcnt(4), no wait on the other counters
+  __builtin_amdgcn_s_waitcnt(4 | (7 << 4) | (15 << 8));
   __builtin_amdgcn_s_barrier();
 }
 
 // Energies of candidate columns on the BF16 matrix cores.
 //
 // E(c) = -scale * sum_i c_i h_i with h_i = sum_{j>i} J_ij c_j (strict upper triangle),
-// J = hi + mid + lo.  A work unit is (row-block pair p, column tile of 32 CF WAVES
-// columns; WAVES waves of 32 CF columns each: 2, 4 or 8 waves of 64, or 4 waves of 128,
-// chosen per instance so that small instances waste few padding columns): row blocks p
-// and NB-1-p (128 rows each; their K ranges start at the block's first row, so the pair
-// costs NB+1 blocks of K whatever p is), taken in an order that alternates between
-// units.  The waves share the A fragments through LDS, filled by direct global->LDS
-// copies one 32-k chunk ahead (two stages, the copy running on from one row block into
-// the next); each wave owns its columns, whose flip-set and base words each lane loads
-// into registers two chunks ahead, combines and expands to +-1 BF16; every A fragment
-// read from LDS feeds CF MFMAs.  The epilogue multiplies h by the column's spins (the
-// words of the block's first four chunks, kept in registers) and sums over rows in
-// FP64; the unit writes one FP64 value per column.  Each block takes its unit from a
-// table built by the host (the order of the table decides which XCD runs which unit).
-// Per column the k order of the FP32 accumulation is the same for every shape, so the
-// results do not depend on the shape.
-template <int WAVES, int CF = 2>
-__global__ __launch_bounds__(64 * WAVES, CF == 4 ? 1 : 2) void k_score_split(
+// J = hi + mid + lo.  A work unit is (row-block pair p, column tile of 64 WAVES
+// columns; 2, 4 or 8 waves, chosen per instance so that small instances waste few
+// padding columns): row blocks p and NB-1-p (128 rows each; their K ranges start at the
+// block's first row, so the pair costs NB+1 blocks of K whatever p is), taken in an
+// order that alternates between units.  The waves share the A fragments through LDS,
+// filled by direct global->LDS copies one 32-k chunk ahead (two stages, the copy
+// running on from one row block into the next); each wave owns 64 columns, whose
+// flip-set and base words each lane loads into registers two chunks ahead, combines
+// and expands to +-1 BF16.  The epilogue multiplies h by the column's spins (the words
+// of the block's first four chunks, kept in registers) and sums over rows in FP64; the
+// unit writes one FP64 value per column.  Each block takes its
+// unit from a table built by the host (the order of the table decides which XCD runs
+// which unit).
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 2) void k_score_split(
     char* __restrict__ ws, const Inst* __restrict__ insts, const Unit* __restrict__ units,
     const int32_t* __restrict__ roots_all, uint32_t slot, uint32_t parity) {
-  constexpr int TN = 32 * CF * WAVES;
+  constexpr int TN = 64 * WAVES;
   constexpr int PER = 24 / WAVES;
   static_assert(WAVES == 2 || WAVES == 4 || WAVES == 8, "2, 4 or 8 waves");
   __shared__ SplitStage<WAVES> st0;
@@ -186,30 +183,27 @@ __global__ __launch_bounds__(64 * WAVES, CF == 4 ? 1 : 2) void k_score_split(
   const int p = un.p, ct = un.ct;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int col_w = ct * TN + wave * 32 * CF;   // first column of this wave
+  const int col_w = ct * TN + wave * 64;   // first column of this wave
   const int KS = Np / 16;
   const int W = Np / 32;
   const int B = chains * M;
   const int rf_w = (wave * PER) / 6, f_w = (wave * PER) % 6;
   const size_t row_stride = (size_t)KS * 3 * 64;
 
-  // this lane's CF columns: flip-word columns, base rows, root-column mask
-  int colv[CF];
-  const uint32_t* brow[CF];
+  // this lane's two columns: flip-word columns, base rows, root-column mask
+  const int col0 = col_w + (lane & 31), col1 = col0 + 32;
+  const uint32_t* brow0 = base + (size_t)(col0 < B ? col0 / M : chains) * W;
+  const uint32_t* brow1 = base + (size_t)(col1 < B ? col1 / M : chains) * W;
   uint32_t rootmask = 0u;
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) {
+  for (int cf = 0; cf < 2; ++cf) {
     const int col = col_w + cf * 32 + (lane & 31);
-    colv[cf] = col;
-    brow[cf] = base + (size_t)(col < B ? col / M : chains) * W;
     if (col < B) {
       const int c = col / M, r = roots[c];
       if (r >= 1 && col - c * M == r - 1) rootmask |= 1u << cf;
     }
   }
-  double part[CF];
-#pragma unroll
-  for (int cf = 0; cf < CF; ++cf) part[cf] = 0.0;
+  double part[2] = {0.0, 0.0};
 
   const int nblk = (p == NB - 1 - p) ? 1 : 2;
   const int first = un.swap ? NB - 1 - p : p;
@@ -224,41 +218,31 @@ __global__ __launch_bounds__(64 * WAVES, CF == 4 ? 1 : 2) void k_score_split(
   auto a_src = [&](int I) {
     return Apack + (((size_t)(4 * I + rf_w) * KS + 8 * I) * 3 + f_w) * 64 + lane;
   };
-  uint32_t rfE[CF], rbE[CF], rfO[CF], rbO[CF];   // raw words of even and odd chunks
+  uint32_t rfE[2], rbE[2], rfO[2], rbO[2];   // raw words of even and odd chunks
   {
     const int k0w = kw_of(0), k1w = kw_of(1);
-#pragma unroll
-    for (int cf = 0; cf < CF; ++cf) {
-      rfE[cf] = flipsT[(size_t)k0w * Bp + colv[cf]];
-      rbE[cf] = brow[cf][k0w];
-      rfO[cf] = flipsT[(size_t)k1w * Bp + colv[cf]];
-      rbO[cf] = brow[cf][k1w];
-    }
+    rfE[0] = flipsT[(size_t)k0w * Bp + col0];
+    rfE[1] = flipsT[(size_t)k0w * Bp + col1];
+    rbE[0] = brow0[k0w];
+    rbE[1] = brow1[k0w];
+    rfO[0] = flipsT[(size_t)k1w * Bp + col0];
+    rfO[1] = flipsT[(size_t)k1w * Bp + col1];
+    rbO[0] = brow0[k1w];
+    rbO[1] = brow1[k1w];
     copy_a<WAVES>(st0, a_src(first), row_stride, wave);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  // the word pointers of chunk gg
-  const uint32_t* pf[CF];
-  const uint32_t* pb[CF];
-  auto words_of = [&](int gg) {
-    const int kw = kw_of(gg);
-#pragma unroll
-    for (int cf = 0; cf < CF; ++cf) {
-      pf[cf] = flipsT + (size_t)kw * Bp + colv[cf];
-      pb[cf] = brow[cf] + kw;
-    }
-  };
 
   int g = 0;   // the unit's chunk index
   for (int bi = 0; bi < nblk; ++bi) {
     const int I = bi == 0 ? first : second;
     const int nchunk = (Np - I * kRowBlock) / 32;   // a multiple of 4
-    f32x16 acc[4][CF];
+    f32x16 acc[4][2];
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf)
+      for (int cf = 0; cf < 2; ++cf)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[rf][cf][e] = 0.0f;
     const uint4* src = a_src(I);
@@ -266,24 +250,27 @@ __global__ __launch_bounds__(64 * WAVES, CF == 4 ? 1 : 2) void k_score_split(
     const uint4* src_n = more ? a_src(second) : src + (size_t)(nchunk - 1) * 6 * 64;
     // A of the chunk after local chunk c (the next block's first after the last)
 #define MC3_A(cn) (((cn) >= nchunk) ? src_n : src + (size_t)(cn) * 6 * 64)
+#define MC3_W(gg) flipsT + (size_t)kw_of(gg) * Bp + col0, flipsT + (size_t)kw_of(gg) * Bp + col1, \
+                  brow0 + kw_of(gg), brow1 + kw_of(gg)
     // the spin words of the block's own rows are those of its first four chunks (its
     // K range starts at its first row): kept for the epilogue
-    uint32_t wblk[4][CF], wsv[CF];
-    words_of(g + 2);
-    split_chunk<WAVES, CF, 0>(acc, st0, st1, MC3_A(1), row_stride, rfE, rbE, pf, pb, rootmask, lane, wave, wblk[0]);
-    words_of(g + 3);
-    split_chunk<WAVES, CF, 1>(acc, st1, st0, MC3_A(2), row_stride, rfO, rbO, pf, pb, rootmask, lane, wave, wblk[1]);
-    words_of(g + 4);
-    split_chunk<WAVES, CF, 2>(acc, st0, st1, MC3_A(3), row_stride, rfE, rbE, pf, pb, rootmask, lane, wave, wblk[2]);
-    words_of(g + 5);
-    split_chunk<WAVES, CF, 3>(acc, st1, st0, MC3_A(4), row_stride, rfO, rbO, pf, pb, rootmask, lane, wave, wblk[3]);
+    uint32_t wblk[4][2], wsv[2];
+    split_chunk<WAVES, 0>(acc, st0, st1, MC3_A(1), row_stride, rfE, rbE, MC3_W(g + 2), rootmask, lane, wave,
+                          wblk[0]);
+    split_chunk<WAVES, 1>(acc, st1, st0, MC3_A(2), row_stride, rfO, rbO, MC3_W(g + 3), rootmask, lane, wave,
+                          wblk[1]);
+    split_chunk<WAVES, 2>(acc, st0, st1, MC3_A(3), row_stride, rfE, rbE, MC3_W(g + 4), rootmask, lane, wave,
+                          wblk[2]);
+    split_chunk<WAVES, 3>(acc, st1, st0, MC3_A(4), row_stride, rfO, rbO, MC3_W(g + 5), rootmask, lane, wave,
+                          wblk[3]);
     for (int c = 4; c < nchunk; c += 2) {
-      words_of(g + c + 2);
-      split_chunk<WAVES, CF>(acc, st0, st1, MC3_A(c + 1), row_stride, rfE, rbE, pf, pb, rootmask, lane, wave, wsv);
-      words_of(g + c + 3);
-      split_chunk<WAVES, CF>(acc, st1, st0, MC3_A(c + 2), row_stride, rfO, rbO, pf, pb, rootmask, lane, wave, wsv);
+      split_chunk<WAVES>(acc, st0, st1, MC3_A(c + 1), row_stride, rfE, rbE, MC3_W(g + c + 2), rootmask, lane, wave,
+                         wsv);
+      split_chunk<WAVES>(acc, st1, st0, MC3_A(c + 2), row_stride, rfO, rbO, MC3_W(g + c + 3), rootmask, lane, wave,
+                         wsv);
     }
 #undef MC3_A
+#undef MC3_W
     g += nchunk;
     // epilogue: rows I*128 + 32 rf + 8(e/4) + 4(lane/32) + e%4 of column col_w + 32 cf +
     // lane%32, whose spins are bits site_bit(8(e/4) + 4(lane/32) + e%4) = 2(lane/32) +
@@ -291,7 +278,7 @@ __global__ __launch_bounds__(64 * WAVES, CF == 4 ? 1 : 2) void k_score_split(
 #pragma unroll
     for (int rf = 0; rf < 4; ++rf) {
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf) {
+      for (int cf = 0; cf < 2; ++cf) {
         const uint32_t sb = wblk[rf][cf] >> (2 * (lane >> 5));
         double sum = 0.0;
 #pragma unroll
@@ -305,7 +292,7 @@ __global__ __launch_bounds__(64 * WAVES, CF == 4 ? 1 : 2) void k_score_split(
     }
   }
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) {
+  for (int cf = 0; cf < 2; ++cf) {
     const double other = __shfl_xor(part[cf], 32);
     const double tot = part[cf] + other;
     if (lane < 32) partial[(size_t)p * Bp + col_w + cf * 32 + lane] = tot;
