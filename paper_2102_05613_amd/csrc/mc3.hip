@@ -29,9 +29,9 @@ constexpr size_t kAlign = 256;
 constexpr int kColPad = 512;     // candidate columns of an instance are padded to this
 constexpr int kTileF64 = 128;    // columns per FP64-scoring unit
 constexpr int kClasses = 3;      // split-scoring tile widths: 128, 256, 512 columns (2, 4, 8 waves)
+constexpr int kMoveRowsMax = 8;  // row parts per chain of the exact energy update, at most
 constexpr int kMaxAhead = 16;    // steps of flip sets drawn per proposal launch, at most
 constexpr size_t kFlipBudget = size_t(512) << 20;  // bytes of flip-set ring, about
-constexpr int kMoveSlices = 64;  // most blocks per chain of the exact energy update
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -44,6 +44,11 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 static __device__ __align__(256) unsigned char scratch[MC3_NOALLOC_BYTES];
 
 namespace {
+
+// Row parts of the exact energy update: enough blocks (about 2048) for a few chains.
+int move_row_parts(int total_chains) {
+  return std::max(1, std::min(kMoveRowsMax, 256 / std::max(1, total_chains)));
+}
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -415,7 +420,7 @@ Plan make_plan(const mc3_batch_config& cfg) {
   if (!pl.delta) {
     pl.moveD = take(C * 2 * (size_t)pl.Wmax * 4);
     pl.mflag = take(C * 4);
-    pl.xpart = take(C * (size_t)kMoveSlices * 8);
+    pl.xpart = take(C * (size_t)mc3::kMoveCols * kMoveRowsMax * 8);
   }
   pl.ring = take((size_t)cfg.trace_steps * C * sizeof(mc3::Record));
   pl.means = take((size_t)cfg.mean_steps * 3 * sizeof(double));
@@ -831,19 +836,22 @@ mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base,
 }
 
 // The exact energy update of the chains [g0, g0 + n) that moved at `step`: their
-// difference from the rows of the flipped sites, S blocks per chain (about 2048 blocks
-// in all), then the sums into the carried energies and the step's records.
+// difference from the rows of the flipped sites, kMoveCols x RS blocks per chain (a
+// column slice of J64 each, the rows split RS ways; RS depends on the plan alone, so a
+// chain's sum has the same order in every launch), then the sums into the carried
+// energies and the step's records.
 mc3_status launch_moves(mc3_ctx* c, uint32_t step, int g0, int n, const ClockArg& ck) {
   const Plan& pl = c->pl;
   int Nmax = 0;
   for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
-  const int S = std::max(1, std::min(kMoveSlices, 2048 / std::max(1, n)));
-  hipLaunchKernelGGL(mc3::k_move_delta, dim3(n, S), dim3(256), (size_t)8 * pl.Wmax + (size_t)2 * Nmax, c->stream,
-                     c->ws, c->insts(), c->chain_inst(), g0, c->at<const uint32_t>(pl.moveD), pl.Wmax,
-                     c->at<const int32_t>(pl.mflag), c->at<double>(pl.xpart), S);
+  const int RS = move_row_parts(pl.total_chains);
+  hipLaunchKernelGGL(mc3::k_move_delta, dim3(n * mc3::kMoveCols * RS), dim3(256),
+                     (size_t)8 * pl.Wmax + (size_t)2 * Nmax, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
+                     c->at<const uint32_t>(pl.moveD), pl.Wmax, c->at<const int32_t>(pl.mflag),
+                     c->at<double>(pl.xpart), RS);
   MC3_TRY(check_launch(c, "move kernel"));
   hipLaunchKernelGGL(mc3::k_move_finish, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->insts(), c->chain_inst(),
-                     g0, n, pl.total_chains, c->at<const int32_t>(pl.mflag), c->at<const double>(pl.xpart), S,
+                     g0, n, pl.total_chains, c->at<const int32_t>(pl.mflag), c->at<const double>(pl.xpart), RS,
                      c->at<double>(pl.u_cur), c->at<double>(pl.e_cur), c->at<mc3::Record>(pl.ring),
                      c->cfg.trace_steps, ck.clk ? step - ck.base : step, ck.clk);
   return check_launch(c, "move finish kernel");

@@ -294,14 +294,19 @@ __device__ __forceinline__ double block_sum256(double x, double* red4, int tid) 
 // (s the old state): the pairs with one site in D change sign, so
 //   dU = -2 sum_{i in D} s_i sum_{j not in D} J_ij s_j = -2 cross,
 // |D| rows of the symmetric J64 in FP64 (exact integers for +-1 couplings).  This
-// returns slice sl of S of the cross sum: the listed sites a with a % S == sl.  Called by
-// all 256 threads; dW, sW: the words of D and of the old state in LDS; Dl: LDS for |D|
-// site entries (site | sign << 15).  Wave 0 lists the sites in word order (lane l
-// takes words 4l .. 4l+3, W <= 256); then thread t takes columns j = t, t+256, ..
-// outside D and sums s_i J_ij over its rows, eight rows of loads at a time.
+// returns part (sl, rs) of the cross sum: the columns j outside D in column slice sl of
+// kMoveCols, [sl wc, (sl + 1) wc) with wc = ceil(N / kMoveCols), over the listed rows a
+// with a % RS == rs.  Called by all 256 threads; dW, sW: the words of D and of the old
+// state in LDS; Dl: LDS for |D| site entries (site | sign << 15).  Wave 0 lists the
+// sites in word order (lane l takes words 4l .. 4l+3, W <= 256); then the threads form
+// R groups of CW (CW a power of two >= wc up to 256, R = 256 / CW): thread t takes
+// columns j0 + t % CW, + CW, .. of the slice and the rows rs + RS (t / CW), + RS R, ..,
+// eight rows of loads at a time.
+constexpr int kMoveCols = 8;
+
 __device__ __forceinline__ double flip_cross(const double* __restrict__ J64, int N, int Np, int W,
                                              const uint32_t* dW, const uint32_t* sW, uint16_t* Dl, int* sh_nd,
-                                             double* red4, int tid, int sl, int S) {
+                                             double* red4, int tid, int sl, int rs, int RS) {
   const int lane = tid & 63;
   if (tid < 64) {
     uint32_t wd[4];
@@ -330,21 +335,26 @@ __device__ __forceinline__ double flip_cross(const double* __restrict__ J64, int
   }
   __syncthreads();
   const int nd = *sh_nd;
+  const int wc = (N + kMoveCols - 1) / kMoveCols;
+  int CW = 32;
+  while (CW < wc && CW < 256) CW <<= 1;
+  const int R = (256 / CW) * RS;
+  const int j0 = sl * wc, j1 = min(N, j0 + wc), rg = rs + RS * (tid / CW);
   double cross = 0.0;
-  for (int j = tid; j < N; j += 256) {
+  for (int j = j0 + tid % CW; j < j1; j += CW) {
     const uint32_t wj = (uint32_t)j >> 5, bj = site_bit((uint32_t)j & 31u);
     if ((dW[wj] >> bj) & 1u) continue;
     const double* __restrict__ col = J64 + j;
     double gsum = 0.0;
-    int a = sl;
-    for (; a + 7 * S < nd; a += 8 * S) {
+    int a = rg;
+    for (; a + 7 * R < nd; a += 8 * R) {
       double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = col[(size_t)(Dl[a + q * S] & 0x7FFF) * Np];
+      for (int q = 0; q < 8; ++q) v[q] = col[(size_t)(Dl[a + q * R] & 0x7FFF) * Np];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) gsum = gsum + ((Dl[a + q * S] >> 15) ? -v[q] : v[q]);
+      for (int q = 0; q < 8; ++q) gsum = gsum + ((Dl[a + q * R] >> 15) ? -v[q] : v[q]);
     }
-    for (; a < nd; a += S) {
+    for (; a < nd; a += R) {
       const double v = col[(size_t)(Dl[a] & 0x7FFF) * Np];
       gsum = gsum + ((Dl[a] >> 15) ? -v : v);
     }
@@ -353,19 +363,23 @@ __device__ __forceinline__ double flip_cross(const double* __restrict__ J64, int
   return block_sum256(cross, red4, tid);
 }
 
-// Slice blockIdx.y of S of the cross sum of every global chain blockIdx.x +
-// chain_off that moved (mflag), from the chain's words of D and of its old state
-// (moveD [chains][2 Wmax]: D, then old spins) written by the selection.
-// Dynamic LDS: 8 Wmax + 2 Nmax bytes.
+// Part (sl, rs) of the cross sum of every global chain that moved (mflag), from the
+// chain's words of D and of its old state (moveD [chains][2 Wmax]: D, then old spins)
+// written by the selection.  Block b takes slice sl = b % kMoveCols, q = b / kMoveCols,
+// chain chain_off + q / RS and row part rs = q % RS: workgroups go to the 8 XCDs in
+// turn, so each XCD reads one column slice of J64 (an eighth of it) and keeps it in
+// its own L2.  The part goes to xpart[g][rs kMoveCols + sl].  Dynamic LDS: 8 Wmax +
+// 2 Nmax bytes.
 __global__ __launch_bounds__(256) void k_move_delta(char* __restrict__ ws, const Inst* __restrict__ insts,
                                                     const int32_t* __restrict__ chain_inst, int chain_off,
                                                     const uint32_t* __restrict__ moveD, int Wmax,
                                                     const int32_t* __restrict__ mflag, double* __restrict__ xpart,
-                                                    int S) {
+                                                    int RS) {
   extern __shared__ uint32_t mv_lds[];
   __shared__ int sh_nd;
   __shared__ double sh_red[4];
-  const int g = chain_off + blockIdx.x, sl = blockIdx.y, tid = threadIdx.x;
+  const int q = (int)(blockIdx.x / kMoveCols), sl = (int)(blockIdx.x % kMoveCols), tid = threadIdx.x;
+  const int g = chain_off + q / RS, rs = q % RS;
   if (!mflag[g]) return;
   const Inst& in = insts[chain_inst[g]];
   const int W = in.W;
@@ -378,16 +392,16 @@ __global__ __launch_bounds__(256) void k_move_delta(char* __restrict__ ws, const
   }
   __syncthreads();
   const double x = flip_cross(ws_at<const double>(ws, in.J64), in.N, in.Np, W, dW, sW,
-                              reinterpret_cast<uint16_t*>(sW + Wmax), &sh_nd, sh_red, tid, sl, S);
-  if (tid == 0) xpart[(size_t)g * S + sl] = x;
+                              reinterpret_cast<uint16_t*>(sW + Wmax), &sh_nd, sh_red, tid, sl, rs, RS);
+  if (tid == 0) xpart[(size_t)g * kMoveCols * RS + (size_t)rs * kMoveCols + sl] = x;
 }
 
-// The carried pair sum of every chain that moved: U += -2 (sum of the S slices, in
-// order); E = -(scale U) into e_cur and into the step's record.  With a step clock the
-// step is *clk + step.
+// The carried pair sum of every chain that moved: U += -2 (sum of its kMoveCols RS
+// parts, in order); E = -(scale U) into e_cur and into the step's record.  With a step
+// clock the step is *clk + step.
 __global__ void k_move_finish(const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
                               int n, int total_chains, const int32_t* __restrict__ mflag,
-                              const double* __restrict__ xpart, int S, double* __restrict__ u_cur,
+                              const double* __restrict__ xpart, int RS, double* __restrict__ u_cur,
                               double* __restrict__ e_cur, Record* __restrict__ ring, int trace_steps, uint32_t step,
                               const uint32_t* __restrict__ clk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,7 +410,8 @@ __global__ void k_move_finish(const Inst* __restrict__ insts, const int32_t* __r
   if (!mflag[g]) return;
   if (clk) step += *clk;
   double cross = 0.0;
-  for (int sl = 0; sl < S; ++sl) cross += xpart[(size_t)g * S + sl];
+  const int P = kMoveCols * RS;
+  for (int p = 0; p < P; ++p) cross += xpart[(size_t)g * P + p];
   const double U = u_cur[g] + (-2.0 * cross);
   const double E = -(insts[chain_inst[g]].scale * U);
   u_cur[g] = U;
