@@ -487,11 +487,6 @@ struct mc3_ctx {
   int device = 0;
   bool have_chains = false, have_proposal = false, have_scores = false, poisoned = false;
   bool noalloc = false;      // the workspace is the device's fixed array (mc3_create_noalloc)
-  // the exact energy update's second stream (step runs): the bookkeeping after each
-  // selection overlaps the next step's scoring
-  hipStream_t side = nullptr;
-  hipEvent_t ev_sel = nullptr, ev_post = nullptr;
-  bool side_pending = false, defer_moves = false;
   uint32_t proposal_step = 0;
   double tol = 0.0;          // fixed part of the near-tie threshold (plus beta * tie_coef per instance)
   double drift_tol = 1e-9;   // relative drift counted as an event by the periodic recompute
@@ -635,9 +630,13 @@ mc3_status launch_recompute(mc3_ctx* c, int mode) {
 }
 
 // The periodic recompute after the selection of global step t.
-mc3_status maybe_recompute(mc3_ctx* c, uint32_t t) {
+bool recompute_due(const mc3_ctx* c, uint32_t t) {
   const int32_t K = c->cfg.recompute_every;
-  if (K <= 0 || ((uint64_t)t + 1u) % (uint64_t)K != 0u) return MC3_OK;
+  return K > 0 && ((uint64_t)t + 1u) % (uint64_t)K == 0u;
+}
+
+mc3_status maybe_recompute(mc3_ctx* c, uint32_t t) {
+  if (!recompute_due(c, t)) return MC3_OK;
   return launch_recompute(c, 1);
 }
 
@@ -829,31 +828,45 @@ mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base,
                      c->metropolis() ? 1 : 0, beta, c->tol, c->key(), c->cfg.chain_base,
                      ck.clk ? step - ck.base : step, c->slot(step), c->slot(step + 1u), c->cfg.trace_steps,
                      next_base ? 1 : 0, ck.clk, ck.beta0, ck.beta1, (long long)ck.total, sched, exact ? 1 : 0,
-                     c->at<uint32_t>(pl.moveD), pl.Wmax, c->at<int32_t>(pl.mflag));
+                     c->at<uint32_t>(pl.moveD), pl.Wmax, c->at<int32_t>(pl.mflag), c->at<const double>(pl.xpart),
+                     move_row_parts(pl.total_chains));
   MC3_TRY(check_launch(c, "select kernel"));
-  if (!exact || c->defer_moves) return MC3_OK;
+  if (!exact) return MC3_OK;
   return launch_moves(c, step, g0, n, ck);
 }
 
 // The exact energy update of the chains [g0, g0 + n) that moved at `step`: their
 // difference from the rows of the flipped sites, kMoveCols x RS blocks per chain (a
 // column slice of J64 each, the rows split RS ways; RS depends on the plan alone, so a
-// chain's sum has the same order in every launch), then the sums into the carried
-// energies and the step's records.
+// chain's sum has the same order in every launch).  The next selection adds it into
+// the carried energy and the step's record, or flush_moves does.
 mc3_status launch_moves(mc3_ctx* c, uint32_t step, int g0, int n, const ClockArg& ck) {
   const Plan& pl = c->pl;
   int Nmax = 0;
   for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
+  (void)step;
+  (void)ck;
   const int RS = move_row_parts(pl.total_chains);
   hipLaunchKernelGGL(mc3::k_move_delta, dim3(n * mc3::kMoveCols * RS), dim3(256),
                      (size_t)8 * pl.Wmax + (size_t)2 * Nmax, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
                      c->at<const uint32_t>(pl.moveD), pl.Wmax, c->at<const int32_t>(pl.mflag),
                      c->at<double>(pl.xpart), RS);
-  MC3_TRY(check_launch(c, "move kernel"));
+  return check_launch(c, "move kernel");
+}
+
+// With the exact energy update: the differences of the moves of `step` (the last
+// selection) that no selection has added yet, added into the carried energies and the
+// step's records (k_move_finish; chains whose flag is clear are left alone).  Run
+// before anything that reads the carried energies other than the next selection: the
+// means, the periodic recompute, and the end of every call that selects.
+mc3_status flush_moves(mc3_ctx* c, uint32_t step, const ClockArg& ck = ClockArg{}) {
+  const Plan& pl = c->pl;
+  if (c->cfg.energy_update != MC3_ENERGY_EXACT || pl.delta) return MC3_OK;
+  const int n = pl.total_chains;
   hipLaunchKernelGGL(mc3::k_move_finish, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->insts(), c->chain_inst(),
-                     g0, n, pl.total_chains, c->at<const int32_t>(pl.mflag), c->at<const double>(pl.xpart), RS,
-                     c->at<double>(pl.u_cur), c->at<double>(pl.e_cur), c->at<mc3::Record>(pl.ring),
-                     c->cfg.trace_steps, ck.clk ? step - ck.base : step, ck.clk);
+                     0, n, pl.total_chains, c->at<int32_t>(pl.mflag), c->at<const double>(pl.xpart),
+                     move_row_parts(pl.total_chains), c->at<double>(pl.u_cur), c->at<double>(pl.e_cur),
+                     c->at<mc3::Record>(pl.ring), c->cfg.trace_steps, ck.clk ? step - ck.base : step, ck.clk);
   return check_launch(c, "move finish kernel");
 }
 
@@ -867,14 +880,8 @@ mc3_status launch_means(mc3_ctx* c, uint32_t step, const ClockArg& ck = ClockArg
   return check_launch(c, "means kernel");
 }
 
-// The context's stream waits for what the second stream still has in flight.
-mc3_status join_side(mc3_ctx* c) {
-  if (!c->side_pending) return MC3_OK;
-  c->side_pending = false;
-  return hip_ok(c, hipStreamWaitEvent(c->stream, c->ev_post, 0), "side join");
-}
-
 mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
+  if (c->cfg.mean_steps > 0 || recompute_due(c, step)) MC3_TRY(flush_moves(c, step));
   MC3_TRY(launch_means(c, step));
   MC3_TRY(maybe_recompute(c, step));
   c->have_proposal = next_base;
@@ -884,50 +891,21 @@ mc3_status after_select(mc3_ctx* c, uint32_t step, bool next_base) {
   return MC3_OK;
 }
 
+// One selection as a call of its own (mc3_select): the carried energies are complete
+// when it returns.
 mc3_status do_select(mc3_ctx* c, uint32_t step, double beta, bool next_base = false,
                      const double* sched = nullptr) {
   MC3_TRY(launch_select(c, step, beta, next_base, 0, c->pl.total_chains, ClockArg{}, sched));
-  return after_select(c, step, next_base);
+  MC3_TRY(after_select(c, step, next_base));
+  return flush_moves(c, step);
 }
 
-// The selection of step t inside a run of steps with the exact energy update: the
-// selection on the context's stream; the moves' energy update, the means and the
-// periodic recompute on a second stream of the context's own (default priority), after
-// the selection and overlapping the next step's scoring, which reads none of what they
-// write; the next selection, which reads the carried energies, waits for them.
-mc3_status do_select_overlapped(mc3_ctx* c, uint32_t t, double beta, bool next_base, const double* sched) {
-  if (!c->side) {
-    MC3_TRY(hip_ok(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream"));
-    MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming), "side event"));
-    MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->ev_post, hipEventDisableTiming), "side event"));
-  }
-  MC3_TRY(join_side(c));
-  c->defer_moves = true;
-  const mc3_status st = launch_select(c, t, beta, next_base, 0, c->pl.total_chains, ClockArg{}, sched);
-  c->defer_moves = false;
-  MC3_TRY(st);
-  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_sel, c->stream), "side event"));
-  MC3_TRY(hip_ok(c, hipStreamWaitEvent(c->side, c->ev_sel, 0), "side wait"));
-  hipStream_t main = c->stream;
-  c->stream = c->side;
-  mc3_status s2 = launch_moves(c, t, 0, c->pl.total_chains, ClockArg{});
-  if (s2 == MC3_OK) s2 = launch_means(c, t);
-  if (s2 == MC3_OK) s2 = maybe_recompute(c, t);
-  c->stream = main;
-  MC3_TRY(s2);
-  MC3_TRY(hip_ok(c, hipEventRecord(c->ev_post, c->side), "side event"));
-  c->side_pending = true;
-  c->have_proposal = next_base;
-  c->have_scores = false;
-  if (next_base) c->proposal_step = t + 1u;
-  c->steps_done += 1;
-  return MC3_OK;
-}
-
-// Step-loop selection: overlapped with the exact energy update, else as do_select.
+// The selection of step t inside a run of steps: with the exact energy update the
+// moves' differences are summed after it (k_move_delta) and added by the next
+// selection, so the run's last step is flushed by its caller.
 mc3_status select_in_run(mc3_ctx* c, uint32_t t, double beta, bool next_base, const double* sched) {
-  if (c->cfg.energy_update == MC3_ENERGY_EXACT) return do_select_overlapped(c, t, beta, next_base, sched);
-  return do_select(c, t, beta, next_base, sched);
+  MC3_TRY(launch_select(c, t, beta, next_base, 0, c->pl.total_chains, ClockArg{}, sched));
+  return after_select(c, t, next_base);
 }
 
 double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
@@ -955,7 +933,7 @@ mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double
     if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
     MC3_TRY(select_in_run(c, t, beta_at(t, beta0, beta1, total), !last, sched));
   }
-  MC3_TRY(join_side(c));
+  MC3_TRY(flush_moves(c, step0 + (uint32_t)(n - 1)));
   c->have_proposal = false;
   return MC3_OK;
 }
@@ -970,7 +948,7 @@ mc3_status step_groups(mc3_ctx* c, uint32_t t0, int64_t n, double beta0, double 
     if (!last && (i + 1) % K == 0) MC3_TRY(propose_all(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false));
     MC3_TRY(select_in_run(c, t, beta_at(t, beta0, beta1, total), !last, nullptr));
   }
-  return join_side(c);
+  return n > 0 ? flush_moves(c, t0 + (uint32_t)(n - 1)) : MC3_OK;
 }
 
 int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
@@ -1003,6 +981,7 @@ mc3_status capture_body(mc3_ctx* c, uint32_t a, int64_t L, double beta0, double 
       st = do_score(c, nullptr);
       if (st == MC3_OK && (j + 1) % K == 0) st = propose_all(c, (uint32_t)(j + 1), (int)K, false, ck.clk);
       if (st == MC3_OK) st = launch_select(c, t, 0.0, true, 0, c->pl.total_chains, ck);
+      if (st == MC3_OK && c->cfg.mean_steps > 0) st = flush_moves(c, t, ck);
       if (st == MC3_OK) st = launch_means(c, t, ck);
     }
     if (st == MC3_OK) {
@@ -1081,6 +1060,7 @@ mc3_status do_step_n_per_instance(mc3_ctx* c, uint32_t step0, int64_t n, double 
     }
     MC3_TRY(after_select(c, t, false));
   }
+  if (n > 0) MC3_TRY(flush_moves(c, step0 + (uint32_t)(n - 1)));
   c->have_proposal = false;
   return MC3_OK;
 }
@@ -1215,7 +1195,8 @@ mc3_status pack_couplings(mc3_ctx* c, InstH& h, double scale) {
 }
 
 // Clear what a fresh chain state needs cleared: flip-set padding columns and the zero
-// base row (must read as zero), counters, margins, the record and means rings.
+// base row (must read as zero), counters, move flags, margins, the record and means
+// rings.
 mc3_status reset_buffers(mc3_ctx* c) {
   const Plan& pl = c->pl;
   const size_t C = (size_t)pl.total_chains;
@@ -1229,6 +1210,9 @@ mc3_status reset_buffers(mc3_ctx* c) {
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.near), 0, C * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift), 0, C * 8, c->stream), "clear"));
   MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.drift_ev), 0, C * 8, c->stream), "clear"));
+  // no move's difference is pending (the selection adds a flagged chain's first); the
+  // field-update path has no move buffers
+  if (!pl.delta) MC3_TRY(hip_ok(c, hipMemsetAsync(c->at<char>(pl.mflag), 0, C * 4, c->stream), "clear"));
   c->recomputes = 0;
   {
     std::vector<double> big(C, HUGE_VAL);
@@ -1340,12 +1324,6 @@ mc3_status mc3_destroy(mc3_ctx* ctx) {
   for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
-  if (ctx->side) {
-    (void)hipStreamSynchronize(ctx->side);
-    (void)hipStreamDestroy(ctx->side);
-  }
-  if (ctx->ev_sel) (void)hipEventDestroy(ctx->ev_sel);
-  if (ctx->ev_post) (void)hipEventDestroy(ctx->ev_post);
   delete ctx;
   return MC3_OK;
 }

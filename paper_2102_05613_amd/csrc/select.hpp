@@ -396,11 +396,12 @@ __global__ __launch_bounds__(256) void k_move_delta(char* __restrict__ ws, const
   if (tid == 0) xpart[(size_t)g * kMoveCols * RS + (size_t)rs * kMoveCols + sl] = x;
 }
 
-// The carried pair sum of every chain that moved: U += -2 (sum of its kMoveCols RS
-// parts, in order); E = -(scale U) into e_cur and into the step's record.  With a step
-// clock the step is *clk + step.
+// The carried pair sum of every chain that moved at `step` and whose difference is not
+// yet added (mflag): U += -2 (sum of its kMoveCols RS parts, in order); E = -(scale U)
+// into e_cur and into the step's record; the flag cleared.  With a step clock the step
+// is *clk + step.
 __global__ void k_move_finish(const Inst* __restrict__ insts, const int32_t* __restrict__ chain_inst, int chain_off,
-                              int n, int total_chains, const int32_t* __restrict__ mflag,
+                              int n, int total_chains, int32_t* __restrict__ mflag,
                               const double* __restrict__ xpart, int RS, double* __restrict__ u_cur,
                               double* __restrict__ e_cur, Record* __restrict__ ring, int trace_steps, uint32_t step,
                               const uint32_t* __restrict__ clk) {
@@ -416,6 +417,7 @@ __global__ void k_move_finish(const Inst* __restrict__ insts, const int32_t* __r
   const double E = -(insts[chain_inst[g]].scale * U);
   u_cur[g] = U;
   e_cur[g] = E;
+  mflag[g] = 0;
   if (trace_steps > 0) ring[(size_t)(step % (uint32_t)trace_steps) * total_chains + g].e_cur = E;
 }
 
@@ -433,9 +435,11 @@ __global__ void k_move_finish(const Inst* __restrict__ insts, const int32_t* __r
 //      loaded before step 1;
 //   4. the new U: exact = 0: the chosen column's pair sum as scored; exact = 1: the
 //      words of the set D* of flipped sites and of the old state go to moveD and the
-//      chain's mflag is set, and k_move_delta / k_move_finish add the exact FP64
-//      difference dU(D*) from the rows of D* (spread over many blocks) after this
-//      launch, rewriting the carried energy and the record's;
+//      chain's mflag is set; k_move_delta sums the exact FP64 difference dU(D*) from
+//      the rows of D* (spread over many blocks) after this launch, and the next
+//      selection (or k_move_finish) adds it, rewriting the carried energy and the
+//      record's.  A chain whose flag is still set on entry first adds the previous
+//      step's difference;
 //   5. thread 0: the bookkeeping and the record.
 // Dynamic LDS: 16 (M+1) bytes.
 __global__ __launch_bounds__(256) void k_select(
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(256) void k_select(
     int metropolis, double beta, double tol, Key key, uint32_t chain_base, uint32_t step, uint32_t slot,
     uint32_t slot_next, int trace_steps, int next_base, const uint32_t* __restrict__ clk, double beta0,
     double beta1, long long total, const double* __restrict__ sched, int exact, uint32_t* __restrict__ moveD,
-    int Wmax, int32_t* __restrict__ mflag) {
+    int Wmax, int32_t* __restrict__ mflag, const double* __restrict__ xpart, int move_rs) {
   extern __shared__ double sel_lds[];
   __shared__ int sh_vstar;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -473,7 +477,21 @@ __global__ __launch_bounds__(256) void k_select(
   double* En = sel_lds;                                                              // [nodes]
   unsigned long long* Qn = reinterpret_cast<unsigned long long*>(sel_lds + nodes);   // [nodes]
   const int r = metropolis ? 0 : roots_all[in.chain0 + c];
-  const double U = u_cur[g];
+  double U = u_cur[g];
+  if (exact && mflag[g]) {
+    // the move of step-1, whose difference k_move_delta has summed and no kernel has
+    // added yet: the same sum as k_move_finish's, in the same order
+    const int P = kMoveCols * move_rs;
+    double cross = 0.0;
+    for (int q = 0; q < P; ++q) cross += xpart[(size_t)g * P + q];
+    U = U + (-2.0 * cross);
+    if (tid == 0) {
+      const double E = -(in.scale * U);
+      u_cur[g] = U;
+      e_cur[g] = E;
+      if (trace_steps > 0) ring[(size_t)((step - 1u) % (uint32_t)trace_steps) * total_chains + g].e_cur = E;
+    }
+  }
   const double ecur = -(in.scale * U);
   long long col_next = -1;
   if (next_base) {
