@@ -623,7 +623,8 @@ def _cpu_baseline(w, J, scale, sample_chains, threads):
     dt = time.perf_counter() - t0
     return {"value": sample_chains * w.M / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
             "sample": f"1 step of {sample_chains} chains (x{w.M} candidates; plain pair-sum energies of all "
-                      f"{w.M + 1} nodes) of the same workload, {dt:.1f} s wall on {threads} threads",
+                      f"{w.M + 1} nodes) of the same workload, {dt:.1f} s wall on {threads} threads "
+                      f"(about {dt * threads:.0f} thread-seconds)",
             "cpu": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
@@ -639,7 +640,7 @@ def main():
     ap.add_argument("--thermalize-steps", type=int, default=20000)
     ap.add_argument("--metropolis-steps", type=int, default=2000000,
                     help="steps of the single-update Metropolis runs of the thermalization study")
-    ap.add_argument("--cpu-chains", type=int, default=320)
+    ap.add_argument("--cpu-chains", type=int, default=640)
     ap.add_argument("--cpu-threads", type=int, default=16,
                     help="oracle threads for the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--anneal-steps", type=int, default=100000)
