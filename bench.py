@@ -398,6 +398,52 @@ def _large_workload(args):
 SPLIT_RTOL = 1e-4   # split-BF16 energies against FP64: relative, with the same absolute floor
 
 
+def _large_cross_check(steps, every):
+    """The split path of the large workload run over the first `steps` steps of its
+    anneal; at every `every`-th step the candidates it scores are scored again by the
+    FP64 path from the same states (an FP64 context given the split chains' spins;
+    flip sets and roots are functions of seed, chain and step, so both score the same
+    candidates)."""
+    import torch
+    from paper_2102_05613_amd import inputs, native
+    w = inputs.workload("sk_n8192_m1024_split")
+    J, scale = w.couplings_matrix()
+    split = _context(w, "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax, J, scale)
+    cfg = native.make_config(w.N, w.M, w.chains, w.kmin, w.kmax, precision="fp64", seed=w.seed)
+    f64 = native.Context(cfg)
+    f64.init_couplings(J, scale)
+    Es = torch.zeros(w.chains * w.M, dtype=torch.float64, device="cuda")
+    Ed = torch.zeros_like(Es)
+    checks = []
+    t = 0
+    while t < steps:
+        f64.init_chains(native.bits_to_spins(split.measure()[1], w.N))
+        split.propose(t)
+        split.score_candidates(Es)
+        f64.propose(t)
+        f64.score_candidates(Ed)
+        es, ed = Es.cpu().numpy(), Ed.cpu().numpy()
+        d = np.abs(es - ed)
+        checks.append({"step": t, "abs_max": float(d.max()), "abs_mean": float(d.mean()),
+                       "max_err_over_tolerance": float((d / (SPLIT_RTOL * (np.abs(ed) + 1.0))).max()),
+                       "energy_abs_min": float(np.abs(ed).min())})
+        n = min(every, steps - t)
+        split.step_n(t, n, w.beta0, w.beta1, w.steps)
+        t += n
+    split.close()
+    f64.close()
+    worst = max(c["max_err_over_tolerance"] for c in checks)
+    eps = w.N * 2.0 ** -24
+    return {"every": every, "steps": steps, "candidates_per_check": w.chains * w.M,
+            "tolerance": "|E_split - E_fp64| <= 1e-4 (|E_fp64| + 1)", "checks": checks,
+            "max_err_over_tolerance": worst, "within_tolerance": bool(worst <= 1.0),
+            "eps_bound": eps, "within_eps_bound": bool(max(c["abs_max"] for c in checks) <= eps),
+            "note": "eps_bound = N 2^-24, the split path's bound on one energy's error (FP32 accumulation of N "
+                    "terms); the 1e-4 absolute floor is below it at N = 8192, so candidates with energies near "
+                    "zero (the random initial states) can exceed the relative tolerance while within the bound",
+            "reference": "FP64 matrix-core scoring of the same candidates from the split chains' states"}
+
+
 def _precision_report(w, J, scale, step=3):
     """Relative error of the split-BF16 energies of every candidate of one step against
     the FP64 scorer's energies of the same candidates (same seed and step; the FP64
@@ -425,6 +471,7 @@ def _precision_report(w, J, scale, step=3):
     over_tol = d / (SPLIT_RTOL * (np.abs(E["fp64"]) + 1.0))
     return {"candidates": int(rel.size), "tolerance": "|E_split - E_fp64| <= 1e-4 (|E_fp64| + 1)",
             "max_err_over_tolerance": float(over_tol.max()), "within_tolerance": bool(over_tol.max() <= 1.0),
+            "eps_bound": w.N * 2.0 ** -24, "within_eps_bound": bool(d.max() <= w.N * 2.0 ** -24),
             "rel_max": float(rel.max()), "rel_p9999": float(np.quantile(rel, 0.9999)),
             "rel_mean": float(rel.mean()), "abs_max": float(d.max()), "abs_p9999": float(np.quantile(d, 0.9999)),
             "abs_mean": float(d.mean()), "energy_abs_mean": float(np.abs(E["fp64"]).mean()),
@@ -644,8 +691,11 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=16,
                     help="oracle threads for the CPU baseline (capped by the host's CPUs)")
     ap.add_argument("--anneal-steps", type=int, default=100000)
-    ap.add_argument("--large-thermalize-steps", type=int, default=0,
-                    help="steps of the N=8192 anneal study (0 skips it; 20000 is the workload's schedule)")
+    ap.add_argument("--large-cross-check-steps", type=int, default=400,
+                    help="split steps of the large workload with an FP64 scoring cross-check every 100th step")
+    ap.add_argument("--large-thermalize-steps", type=int, default=20000,
+                    help="steps of the N=8192 anneal study (0, or --large-steps 0, skips it; 20000 is the "
+                         "workload's schedule)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ceiling-iters", type=int, default=12500,
                     help="rounds of the matrix-core ceiling loop (0 skips it)")
@@ -778,6 +828,9 @@ def main():
         Jl, sl = wl.couplings_matrix()
         out["precision_split_vs_fp64"]["sk_n8192_m1024"] = _precision_report(wl, Jl, sl)
         _log("large workload precision done")
+        if args.large_cross_check_steps > 0:
+            other["sk_n8192_m1024_split"]["fp64_cross_check"] = _large_cross_check(args.large_cross_check_steps, 100)
+            _log("large workload FP64 cross-check done")
     if args.scorers:
         other["scorers_at_headline_flip_sizes"] = _scorer_comparison(w, J, scale)
         _log("scorer comparison done")
@@ -786,7 +839,7 @@ def main():
         _log("root-law table workload done")
         other["set_variant_generation"] = _set_variant()
         _log("set variant done")
-    if args.large_thermalize_steps > 0:
+    if args.large_steps > 0 and args.large_thermalize_steps > 0:
         out.setdefault("steps_to_thermalize", {})["large_workload"] = _large_thermalize(args.large_thermalize_steps)
     if other:
         out["other_workloads"] = other
