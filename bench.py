@@ -323,19 +323,28 @@ def _batched_workload(args):
     _log(f"batch: {len(descs)} instances loaded in {load_s:.1f} s")
     ctx.step_n(0, 3, beta, beta, 1)
     # the steps as mc3_step_n runs them (each half of the instances on a stream of its
-    # own); then the same launches on one stream with every scoring launch timed
-    ms = _timed_steps(ctx, 3, args.batch_steps, beta, beta, 1)
-    t_one = 3 + args.batch_steps
-    n_one = max(2, args.batch_steps // 2)
-    ctx.timing_enable(True)
-    ms_one = _timed_steps(ctx, t_one, n_one, beta, beta, 1)
-    score_ms, launches = ctx.timing_read()
-    ctx.timing_enable(False)
+    # own), in four chunks, alternating with chunks of the same launches on one stream
+    # with every scoring launch timed, so that both see steps of the same stage
+    chunk = max(1, args.batch_steps // 4)
+    ms = ms_one = score_ms = 0.0
+    launches = 0
+    t = 3
+    for _ in range(4):
+        ms += _timed_steps(ctx, t, chunk, beta, beta, 1)
+        t += chunk
+        ctx.timing_enable(True)
+        ms_one += _timed_steps(ctx, t, chunk, beta, beta, 1)
+        sm, ln = ctx.timing_read()
+        score_ms += sm
+        launches += ln
+        ctx.timing_enable(False)
+        t += chunk
+    n_two = n_one = 4 * chunk
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n_per = max(1, args.batch_steps // 4)
-    ctx.step_n_per_instance(t_one + n_one, n_per, beta, beta, 1)
+    ctx.step_n_per_instance(t, n_per, beta, beta, 1)
     torch.cuda.synchronize()
     per_ms = (time.perf_counter() - t0) * 1e3 / n_per
     # the same steps replayed from a captured HIP graph: one replay launches a 272-step
@@ -343,7 +352,7 @@ def _batched_workload(args):
     # timing) is reused by a run starting at the same step modulo 272.
     graph = None
     if args.batch_graph_steps >= 288:
-        t1 = t_one + n_one + n_per
+        t1 = t + n_per
         ctx.step_n_graph(t1, 288, beta, beta, 1)
         gms = _timed_steps(ctx, t1 + 2 * 272, args.batch_graph_steps, beta, beta, 1, graph=True)
         graph = {"ms_per_step": gms / args.batch_graph_steps, "steps": args.batch_graph_steps}
@@ -355,10 +364,10 @@ def _batched_workload(args):
     flops = float(np.sum(3.0 * Ns * (Ns - 1) * Ms * inputs.BATCH_CHAINS))
     jbytes = float(np.sum(3.0 * Np * (Np + 128)))   # split triangle incl. diagonal blocks, read once
     score_s = score_ms / launches / 1e3
-    ms_step = ms / args.batch_steps
+    ms_step = ms / n_two
     return {"instances": len(descs), "chains_per_instance": inputs.BATCH_CHAINS, "beta": beta,
             "N_range": [int(Ns.min()), int(Ns.max())], "M_range": [int(Ms.min()), int(Ms.max())],
-            "candidates_per_step": cand, "steps": args.batch_steps,
+            "candidates_per_step": cand, "steps": n_two,
             "batched": {"ms_per_step": ms_step, "candidates_per_s": cand / (ms_step / 1e3),
                         "score_kernel_ms": score_s * 1e3,
                         "launches_per_step": "per half of the instances, on a stream of its own: one scoring "
@@ -366,7 +375,8 @@ def _batched_workload(args):
                                              "launch, one proposal per 16 steps",
                         "one_stream": {"ms_per_step": ms_one / n_one, "steps": n_one,
                                        "note": "the same launches on one stream, every scoring launch timed "
-                                               "(score_kernel_ms is theirs)"}},
+                                               "(score_kernel_ms is theirs); chunks of these steps alternate "
+                                               "with the two-stream chunks"}},
             "per_instance_launches": {"ms_per_step": per_ms, "candidates_per_s": cand / (per_ms / 1e3),
                                       "steps": n_per, "launches_per_step": 3 * len(descs)},
             "speedup_batched": per_ms / ms_step,
