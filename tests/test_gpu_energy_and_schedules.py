@@ -8,8 +8,9 @@ repaired by the next periodic recompute; per-instance schedules give, instance b
 instance, the single-instance contexts' records bit for bit; couplings given only
 above the diagonal (garbage below) give the trajectory of the full symmetric matrix bit
 for bit on every scorer; the automatic scorer equals the scorer its rule names bit for
-bit; graph replay on a batch equals mc3_step_n bit for bit; M = 1024 selections match
-the oracle (guided at flagged near ties)."""
+bit; graph replay on a batch equals mc3_step_n bit for bit; M = 1024 and M = 4000 (the
+largest) selections match the oracle (guided at flagged near ties); at N = 8192 the
+carried energy equals the oracle's pair sums to FP64 rounding."""
 import numpy as np
 import pytest
 
@@ -230,3 +231,39 @@ def test_selection_over_1025_nodes_guided(prec):
     compare_trajectory(rec, J, scale, N, M, chains, 1, 6, 31, np.full(steps, 0.8), "mcmcmc",
                        1e-4 if prec == "split_bf16" else 1e-6, eps_e=eps_energy(prec, N), max_forced=2,
                        ecur_rtol=1e-9)
+
+
+def test_selection_over_the_most_nodes_guided():
+    """M = 4000, the largest graph a context accepts, at small N: selections over 4001
+    nodes (64 KiB of node energies and weights in LDS) match the oracle, guided only
+    at flagged near ties."""
+    N, M, chains, steps = 64, 4000, 2, 10
+    announce("M=4000 guided")
+    J, scale = inputs.couplings_gauss(N, 4000)
+    ctx = make_ctx(N, M, chains, 1, 4, "split_bf16", J, scale, seed=37, trace_steps=steps)
+    ctx.step_n(0, steps, 0.9, 0.9, 1)
+    rec = ctx.read_records(0, steps)
+    assert (rec["flags"] & 2).any()
+    compare_trajectory(rec, J, scale, N, M, chains, 1, 4, 37, np.full(steps, 0.9), "mcmcmc", 1e-4,
+                       eps_e=eps_energy("split_bf16", N), max_forced=2, ecur_rtol=1e-9)
+
+
+def test_exact_update_at_the_largest_size():
+    """N = 8192 (the largest instance) with flip sets of up to 256 sites at a low beta,
+    where most chains move: the carried energy after 12 steps (each move's difference
+    summed from up to 512 coupling rows of 64 KiB) equals the oracle's pair sums of the
+    final states to FP64 rounding, and the FP64 recompute agrees."""
+    N, M, chains, steps = 8192, 16, 4, 12
+    announce("exact update N=8192")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0005)
+    ctx = make_ctx(N, M, chains, 1, 256, "split_bf16", J, scale, seed=5)
+    ctx.step_n(0, steps, 0.05, 0.05, 1)
+    e_carried, bits, summ = ctx.measure()
+    assert summ["moves"] >= chains * steps // 2
+    s = native.bits_to_spins(bits, N)
+    eo = np.array([oracle.energy(J, scale, s[c]) for c in range(chains)])
+    np.testing.assert_allclose(e_carried, eo, rtol=1e-10, atol=1e-10)
+    ctx.recompute()
+    e_rec, _, summ = ctx.measure()
+    np.testing.assert_allclose(e_rec, eo, rtol=1e-12, atol=1e-12)
+    assert summ["max_drift"] < 1e-9 * (np.abs(eo).max() + 1)
