@@ -322,24 +322,15 @@ def _batched_workload(args):
     ctx.init_chains()
     _log(f"batch: {len(descs)} instances loaded in {load_s:.1f} s")
     ctx.step_n(0, 3, beta, beta, 1)
-    # the steps as mc3_step_n runs them (each half of the instances on a stream of its
-    # own), in four chunks, alternating with chunks of the same launches on one stream
-    # with every scoring launch timed, so that both see steps of the same stage
-    chunk = max(1, args.batch_steps // 4)
-    ms = ms_one = score_ms = 0.0
-    launches = 0
-    t = 3
-    for _ in range(4):
-        ms += _timed_steps(ctx, t, chunk, beta, beta, 1)
-        t += chunk
-        ctx.timing_enable(True)
-        ms_one += _timed_steps(ctx, t, chunk, beta, beta, 1)
-        sm, ln = ctx.timing_read()
-        score_ms += sm
-        launches += ln
-        ctx.timing_enable(False)
-        t += chunk
-    n_two = n_one = 4 * chunk
+    ms = _timed_steps(ctx, 3, args.batch_steps, beta, beta, 1)
+    # the scoring launches timed one by one in a pass of their own
+    t = 3 + args.batch_steps
+    n_one = max(2, args.batch_steps // 2)
+    ctx.timing_enable(True)
+    _timed_steps(ctx, t, n_one, beta, beta, 1)
+    score_ms, launches = ctx.timing_read()
+    ctx.timing_enable(False)
+    t += n_one
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -357,6 +348,23 @@ def _batched_workload(args):
         gms = _timed_steps(ctx, t1 + 2 * 272, args.batch_graph_steps, beta, beta, 1, graph=True)
         graph = {"ms_per_step": gms / args.batch_graph_steps, "steps": args.batch_graph_steps}
     ctx.close()
+    # the same batch on the field-update scorer: every chain of every instance in one
+    # persistent launch that iterates the steps (score by differences, select, update
+    # the field), FP64; Gaussian couplings drawn on the device (same law)
+    pcfg = native.make_batch_config(descs, precision="fp64", seed=w.seed, scorer="delta")
+    pctx = native.Context(pcfg)
+    for i in range(len(descs)):
+        pctx.generate_couplings(native.MC3_J_GAUSS, (inputs.BATCH_SEED << 20) + i, instance=i)
+    pctx.init_chains()
+    pctx.step_n(0, 3, beta, beta, 1)
+    pms = _timed_steps(pctx, 3, args.batch_steps, beta, beta, 1)
+    psum = pctx.measure()[2]
+    pctx.close()
+    persistent = {"ms_per_step": pms / args.batch_steps, "steps": args.batch_steps,
+                  "moves_per_chain_step": psum["moves"] / (psum["steps_done"] * sum(d[2] for d in descs)),
+                  "kernel": "k_step_delta_star: one workgroup per chain, all 8000 chains in one launch per call, "
+                            "steps iterated inside the kernel",
+                  "precision": "fp64 (energy differences from the maintained fields)"}
     Ns = np.array([d[0] for d in descs], dtype=np.float64)
     Ms = np.array([d[1] for d in descs], dtype=np.float64)
     Np = np.ceil(Ns / 128) * 128
@@ -364,22 +372,21 @@ def _batched_workload(args):
     flops = float(np.sum(3.0 * Ns * (Ns - 1) * Ms * inputs.BATCH_CHAINS))
     jbytes = float(np.sum(3.0 * Np * (Np + 128)))   # split triangle incl. diagonal blocks, read once
     score_s = score_ms / launches / 1e3
-    ms_step = ms / n_two
+    ms_step = ms / args.batch_steps
     return {"instances": len(descs), "chains_per_instance": inputs.BATCH_CHAINS, "beta": beta,
             "N_range": [int(Ns.min()), int(Ns.max())], "M_range": [int(Ms.min()), int(Ms.max())],
-            "candidates_per_step": cand, "steps": n_two,
+            "candidates_per_step": cand, "steps": args.batch_steps,
             "batched": {"ms_per_step": ms_step, "candidates_per_s": cand / (ms_step / 1e3),
                         "score_kernel_ms": score_s * 1e3,
-                        "launches_per_step": "per half of the instances, on a stream of its own: one scoring "
-                                             "launch per tile width present, one selection, one exact-update "
-                                             "launch, one proposal per 16 steps",
-                        "one_stream": {"ms_per_step": ms_one / n_one, "steps": n_one,
-                                       "note": "the same launches on one stream, every scoring launch timed "
-                                               "(score_kernel_ms is theirs); chunks of these steps alternate "
-                                               "with the two-stream chunks"}},
+                        "launches_per_step": "one scoring launch per tile width present, one selection, one "
+                                             "exact-update launch, one proposal per 16 steps",
+                        "score_timing": f"HIP events around each scoring launch of {n_one} steps after the "
+                                        f"timed ones"},
             "per_instance_launches": {"ms_per_step": per_ms, "candidates_per_s": cand / (per_ms / 1e3),
                                       "steps": n_per, "launches_per_step": 3 * len(descs)},
             "speedup_batched": per_ms / ms_step,
+            "persistent_field_update": {**persistent,
+                                        "candidates_per_s": cand / (persistent["ms_per_step"] / 1e3)},
             "batched_graph_replay": None if graph is None else {
                 **graph, "candidates_per_s": cand / (graph["ms_per_step"] / 1e3)},
             "score_roofline": {"flops_per_launch": flops, "achieved_tflops": flops / score_s / 1e12,

@@ -81,9 +81,13 @@ typedef enum {
  *          differs from the current node by the path flip set D = F_r xor F_v, so
  *          dU = -2 sum_{i in D} s_i h_i + 4 sum_{i<j in D} J_ij s_i s_j (|D| + |D|^2/2
  *          couplings per candidate instead of N^2); a move updates h with the |D|
- *          rows of J.  All steps of a chain run in one persistent workgroup.  Limits:
- *          kmax <= 16, M <= 512, N <= 4096, kmax times the longest path between two
- *          nodes (in edges) <= 32 and the per-chain state within 64 KiB of LDS
+ *          rows of J.  All steps of a chain run in one persistent workgroup, every
+ *          chain of every instance of a batch in one launch.  Limits: either (small
+ *          flip sets, any tree) kmax <= 16, M <= 512, N <= 4096, kmax times the
+ *          longest path between two nodes (in edges) <= 32 and the per-chain state
+ *          within 64 KiB of LDS; or (the star, flip sets of any size) the per-chain
+ *          state within 160 KiB of LDS: 16 N + 24 (M+1) + 8 W + 4 M W + 8 kmax bytes
+ *          for the batch's largest N, M, kmax and W = ceil(N/128) 4
  *          (MC3_E_UNSUPPORTED otherwise); only mc3_step_n moves the chains
  *          (mc3_propose, mc3_score_candidates, mc3_select, mc3_read_candidates and
  *          mc3_step_n_per_instance return MC3_E_UNSUPPORTED).  `precision` is unused.

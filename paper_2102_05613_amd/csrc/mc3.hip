@@ -108,17 +108,6 @@ struct Plan {
   int ahead = 1;    // steps proposed per launch in mc3_step_n
   int nslots = 2;   // flip-set and root ring slots (ahead + 1)
   std::vector<mc3::Unit> units_global[kClasses], units_local;
-  // A batch's two halves (instances [inst0, inst1), their chains and proposal blocks,
-  // and unit tables laid out like the whole batch's): a run of steps gives each half a
-  // stream of its own, so one half's selection and energy update overlap the other
-  // half's scoring.  halves == 0: not split (one instance).
-  struct Half {
-    int inst0 = 0, inst1 = 0, chain0 = 0, chains = 0, pb0 = 0, pbn = 0;
-    std::vector<mc3::Unit> units[kClasses];
-    size_t units_off[kClasses] = {0, 0, 0};
-  };
-  int halves = 0;
-  Half half[2];
   std::vector<mc3::PBlock> pblocks;
   std::vector<mc3::RecUnit> rec_units;   // the FP64 recompute's units, every instance
   std::vector<int32_t> chain_inst;
@@ -234,6 +223,10 @@ bool delta_fits(const mc3_batch_config& c, size_t* lds, int path_limit) {
   return *lds <= 65536;
 }
 
+// LDS a workgroup may hold on gfx950 (160 KiB; kernels that take more than 64 KiB of
+// dynamic LDS raise their limit with hipFuncSetAttribute before the launch).
+constexpr size_t kLdsPerBlock = 160u << 10;
+
 // The field-update scorer for stars with flip sets of any size (k_step_delta_star):
 // whether its LDS fits, and how much.
 bool delta_star_fits(const mc3_batch_config& c, size_t* lds) {
@@ -247,7 +240,7 @@ bool delta_star_fits(const mc3_batch_config& c, size_t* lds) {
     Wmax = std::max(Wmax, (d.N + mc3::kRowBlock - 1) / mc3::kRowBlock * mc3::kRowBlock / 32);
   }
   *lds = mc3::delta_star_lds_bytes(Nmax, Mmax, Wmax, Kmax);
-  return *lds <= 65536;
+  return *lds <= kLdsPerBlock;
 }
 
 // Resolve the scorer: 1 = field update, 2 = field update for stars with flip sets of any
@@ -383,49 +376,23 @@ Plan make_plan(const mc3_batch_config& cfg) {
     }
     for (int p = 0; p < h.P; ++p) groups[h.cls].push_back(Group{i, p, CT, unit_cost(h.NB, p)});
   }
-  auto layout = [](std::vector<Group> gs, std::vector<mc3::Unit>& out) {
-    std::stable_sort(gs.begin(), gs.end(),
-                     [](const Group& a, const Group& b) { return a.cost != b.cost ? a.cost > b.cost : a.CT > b.CT; });
-    for (size_t g0 = 0; g0 < gs.size(); g0 += 8) {
-      const size_t ng = std::min<size_t>(8, gs.size() - g0);
-      int cmax = 0;
-      for (size_t x = 0; x < ng; ++x) cmax = std::max(cmax, gs[g0 + x].CT);
-      for (int j = 0; j < cmax; ++j)
-        for (size_t x = 0; x < 8; ++x) {
-          mc3::Unit un{-1, 0, 0, 0};
-          if (x < ng && j < gs[g0 + x].CT) un = mc3::Unit{gs[g0 + x].inst, gs[g0 + x].p, j, 0};
-          out.push_back(un);
-        }
-    }
-  };
   if (n == 1) {
     pl.units_global[pl.inst[0].cls] = pl.units_local;
   } else {
-    for (int k = 0; k < kClasses; ++k) layout(groups[k], pl.units_global[k]);
-    // the halves: instances split where the scoring work (chains M N^2) reaches half
-    double total = 0.0;
-    for (const InstH& h : pl.inst) total += (double)h.desc.chains * h.desc.M * h.desc.N * h.desc.N;
-    double acc = 0.0;
-    int split = 1;
-    for (int i = 0; i < n - 1; ++i) {
-      acc += (double)pl.inst[i].desc.chains * pl.inst[i].desc.M * pl.inst[i].desc.N * pl.inst[i].desc.N;
-      split = i + 1;
-      if (acc >= 0.5 * total) break;
-    }
-    pl.halves = 2;
-    for (int q = 0; q < 2; ++q) {
-      Plan::Half& H = pl.half[q];
-      H.inst0 = q == 0 ? 0 : split;
-      H.inst1 = q == 0 ? split : n;
-      H.chain0 = pl.inst[H.inst0].chain0;
-      H.chains = (H.inst1 < n ? pl.inst[H.inst1].chain0 : pl.total_chains) - H.chain0;
-      H.pb0 = pl.inst[H.inst0].pblock_off;
-      H.pbn = (H.inst1 < n ? pl.inst[H.inst1].pblock_off : (int)pl.pblocks.size()) - H.pb0;
-      for (int k = 0; k < kClasses; ++k) {
-        std::vector<Group> gs;
-        for (const Group& g : groups[k])
-          if (g.inst >= H.inst0 && g.inst < H.inst1) gs.push_back(g);
-        layout(gs, H.units[k]);
+    for (int k = 0; k < kClasses; ++k) {
+      std::vector<Group>& gs = groups[k];
+      std::stable_sort(gs.begin(), gs.end(),
+                       [](const Group& a, const Group& b) { return a.cost != b.cost ? a.cost > b.cost : a.CT > b.CT; });
+      for (size_t g0 = 0; g0 < gs.size(); g0 += 8) {
+        const size_t ng = std::min<size_t>(8, gs.size() - g0);
+        int cmax = 0;
+        for (size_t x = 0; x < ng; ++x) cmax = std::max(cmax, gs[g0 + x].CT);
+        for (int j = 0; j < cmax; ++j)
+          for (size_t x = 0; x < 8; ++x) {
+            mc3::Unit un{-1, 0, 0, 0};
+            if (x < ng && j < gs[g0 + x].CT) un = mc3::Unit{gs[g0 + x].inst, gs[g0 + x].p, j, 0};
+            pl.units_global[k].push_back(un);
+          }
       }
     }
   }
@@ -440,9 +407,6 @@ Plan make_plan(const mc3_batch_config& cfg) {
   pl.insts = take((size_t)n * sizeof(mc3::Inst));
   pl.chain_inst_off = take(C * 4);
   for (int k = 0; k < kClasses; ++k) pl.units_global_off[k] = take(pl.units_global[k].size() * sizeof(mc3::Unit));
-  for (int q = 0; q < pl.halves; ++q)
-    for (int k = 0; k < kClasses; ++k)
-      pl.half[q].units_off[k] = take(pl.half[q].units[k].size() * sizeof(mc3::Unit));
   pl.units_local_off = take(pl.units_local.size() * sizeof(mc3::Unit));
   pl.pblocks_off = take(pl.pblocks.size() * sizeof(mc3::PBlock));
   pl.rec_units_off = take(pl.rec_units.size() * sizeof(mc3::RecUnit));
@@ -542,14 +506,11 @@ struct mc3_ctx {
   size_t t_next = 0;
   double t_total_ms = 0.0;
   int64_t t_count = 0;
+  bool star_lds_set = false;   // k_step_delta_star's dynamic LDS limit raised past 64 KiB
   // mc3_step_n_graph: the captured body, the stream it is captured on, and what it was
   // captured for (schedule, and the first step's residue modulo the body length)
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
-  // the second half's stream of a batch's runs of steps (default priority), and the
-  // events that fork it from the caller's stream and join it back
-  hipStream_t half_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double g_beta0 = 0.0, g_beta1 = 0.0;
   int64_t g_total = 0, g_len = 0, g_phase = -1;
   std::string err;
@@ -717,6 +678,12 @@ mc3_status do_step_n_delta(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, 
       continue;
     }
     if (pl.delta_star) {
+      if (pl.delta_lds > 65536 && !c->star_lds_set) {
+        MC3_TRY(hip_ok(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&mc3::k_step_delta_star),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.delta_lds),
+                       "field-update star kernel LDS"));
+        c->star_lds_set = true;
+      }
       hipLaunchKernelGGL(mc3::k_step_delta_star, dim3(pl.total_chains), dim3(256), pl.delta_lds, c->stream, c->ws,
                          c->insts(), c->chain_inst(), pl.total_chains, Nmax, pl.Mmax, pl.Wmax, pl.Kmax,
                          c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->at<mc3::Record>(pl.ring),
@@ -963,16 +930,9 @@ double beta_at(uint32_t t, double beta0, double beta1, int64_t total) {
 // flip sets of step a for the base words a's scoring uses, and whose own slot is the
 // one slot the group does not touch.  Per step: one scoring launch and one selection
 // launch (which also forms the next step's base words).
-mc3_status do_step_n_halves(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total,
-                            const double* sched);
-
 mc3_status do_step_n(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total,
                      const double* sched = nullptr) {
   if (n <= 0) return MC3_OK;
-  // a batch runs its two halves on two streams, unless a step needs every chain at once
-  // (the means, the periodic recompute) or the scoring launches are being timed
-  if (c->pl.halves == 2 && !c->timing && c->cfg.mean_steps <= 0 && c->cfg.recompute_every <= 0)
-    return do_step_n_halves(c, step0, n, beta0, beta1, total, sched);
   const int64_t K = c->pl.ahead;
   MC3_TRY(propose_all(c, step0, (int)std::min<int64_t>(K, n), true));
   c->have_proposal = true;
@@ -1000,57 +960,6 @@ mc3_status step_groups(mc3_ctx* c, uint32_t t0, int64_t n, double beta0, double 
     MC3_TRY(select_in_run(c, t, beta_at(t, beta0, beta1, total), !last, nullptr));
   }
   return n > 0 ? flush_moves(c, t0 + (uint32_t)(n - 1)) : MC3_OK;
-}
-
-// n steps of a batch split in two halves: the same launches as do_step_n, each half's
-// on a stream of its own (the caller's stream and a second one, forked after what the
-// caller's stream already holds and joined back at the end), so that while one half
-// selects and updates its energies the other half's scoring runs.  The halves share no
-// data: instances, chains, proposal blocks and unit tables are each half's own.
-mc3_status do_step_n_halves(mc3_ctx* c, uint32_t step0, int64_t n, double beta0, double beta1, int64_t total,
-                            const double* sched) {
-  const Plan& pl = c->pl;
-  if (!c->half_stream) {
-    MC3_TRY(hip_ok(c, hipStreamCreateWithFlags(&c->half_stream, hipStreamNonBlocking), "half stream"));
-    MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "half event"));
-    MC3_TRY(hip_ok(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "half event"));
-  }
-  const int64_t K = pl.ahead;
-  hipStream_t main = c->stream;
-  mc3_status st = MC3_OK;
-  for (int64_t i = 0; i < n && st == MC3_OK; ++i) {
-    const uint32_t t = step0 + (uint32_t)i;
-    const bool last = i + 1 == n;
-    const double beta = beta_at(t, beta0, beta1, total);
-    for (int q = 0; q < 2 && st == MC3_OK; ++q) {
-      c->stream = q == 0 ? main : c->half_stream;
-      const Plan::Half& H = pl.half[q];
-      c->proposal_step = t;
-      if (i == 0 && q == 1) {
-        // the second half starts after the first half's first step (and everything
-        // before it on the caller's stream): the halves' selections and energy
-        // updates then fall beside the other half's scoring
-        st = hip_ok(c, hipEventRecord(c->ev_fork, main), "half fork");
-        if (st == MC3_OK) st = hip_ok(c, hipStreamWaitEvent(c->half_stream, c->ev_fork, 0), "half fork");
-        if (st != MC3_OK) break;
-      }
-      if (i == 0) st = launch_propose(c, step0, (int)std::min<int64_t>(K, n), true, H.pb0, H.pbn);
-      for (int k = 0; k < kClasses && st == MC3_OK; ++k)
-        if (!H.units[k].empty()) st = launch_score_units(c, H.units_off[k], (int)H.units[k].size(), k);
-      if (st == MC3_OK && !last && (i + 1) % K == 0)
-        st = launch_propose(c, t + 1u, (int)std::min<int64_t>(K, n - i - 1), false, H.pb0, H.pbn);
-      if (st == MC3_OK) st = launch_select(c, t, beta, !last, H.chain0, H.chains, ClockArg{}, sched);
-    }
-    c->steps_done += 1;
-  }
-  c->stream = main;
-  if (st == MC3_OK) st = hip_ok(c, hipEventRecord(c->ev_join, c->half_stream), "half join");
-  if (st == MC3_OK) st = hip_ok(c, hipStreamWaitEvent(main, c->ev_join, 0), "half join");
-  MC3_TRY(st);
-  MC3_TRY(flush_moves(c, step0 + (uint32_t)(n - 1)));
-  c->have_proposal = false;
-  c->have_scores = false;
-  return MC3_OK;
 }
 
 int64_t gcd64(int64_t a, int64_t b) { return b ? gcd64(b, a % b) : a; }
@@ -1213,9 +1122,6 @@ mc3_status create_impl(const mc3_batch_config* cfg, void* workspace, size_t byte
   hipError_t e = up(P.chain_inst_off, P.chain_inst.data(), P.chain_inst.size() * 4);
   for (int k = 0; k < kClasses && e == hipSuccess; ++k)
     e = up(P.units_global_off[k], P.units_global[k].data(), P.units_global[k].size() * sizeof(mc3::Unit));
-  for (int q = 0; q < P.halves; ++q)
-    for (int k = 0; k < kClasses && e == hipSuccess; ++k)
-      e = up(P.half[q].units_off[k], P.half[q].units[k].data(), P.half[q].units[k].size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.units_local_off, P.units_local.data(), P.units_local.size() * sizeof(mc3::Unit));
   if (e == hipSuccess) e = up(P.pblocks_off, P.pblocks.data(), P.pblocks.size() * sizeof(mc3::PBlock));
   if (e == hipSuccess) e = up(P.rec_units_off, P.rec_units.data(), P.rec_units.size() * sizeof(mc3::RecUnit));
@@ -1429,12 +1335,6 @@ mc3_status mc3_destroy(mc3_ctx* ctx) {
   for (hipEvent_t e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
-  if (ctx->half_stream) {
-    (void)hipStreamSynchronize(ctx->half_stream);
-    (void)hipStreamDestroy(ctx->half_stream);
-  }
-  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
   return MC3_OK;
 }

@@ -199,10 +199,12 @@ def test_batch_rejects_bad_header_fields(lib):
 @pytest.mark.parametrize("shape,scorer,arity,expect", [
     ((64, 4, 2, 1, 16), "delta", 0, native.MC3_OK),
     # beyond the small-flip kernel: stars go to the kernel for flip sets of any size
-    ((64, 4, 2, 1, 17), "delta", 0, native.MC3_OK), ((4097, 4, 2, 1, 2), "delta", 0, native.MC3_E_UNSUPPORTED),
-    ((3000, 4, 2, 1, 2), "delta", 0, native.MC3_OK),
+    ((64, 4, 2, 1, 17), "delta", 0, native.MC3_OK), ((4097, 4, 2, 1, 2), "delta", 0, native.MC3_OK),
+    ((3000, 4, 2, 1, 2), "delta", 0, native.MC3_OK), ((8192, 4, 2, 1, 2), "delta", 0, native.MC3_OK),
     ((64, 513, 2, 1, 2), "delta", 0, native.MC3_OK), ((1024, 128, 4, 1, 128), "delta", 0, native.MC3_OK),
-    ((4096, 512, 2, 1, 16), "delta", 0, native.MC3_E_UNSUPPORTED),   # LDS beyond 64 KiB in both kernels
+    ((2048, 256, 4, 1, 128), "delta", 0, native.MC3_OK),              # the star kernel's state: 106 KiB
+    ((8192, 64, 2, 1, 2), "delta", 0, native.MC3_E_UNSUPPORTED),      # 200 KiB: beyond 160 KiB
+    ((4096, 512, 2, 1, 16), "delta", 0, native.MC3_E_UNSUPPORTED),   # LDS beyond either kernel's limit
     ((64, 14, 2, 1, 17), "delta", 2, native.MC3_E_UNSUPPORTED),      # a tree with large flip sets
     ((64, 4, 2, 1, 17), "auto", 0, native.MC3_OK), ((64, 4, 2, 1, 16), "gemm", 0, native.MC3_OK)])
 def test_field_update_scorer_limits(lib, shape, scorer, arity, expect):

@@ -162,67 +162,3 @@ def test_batching_workload_full_size_sampled():
     picks = sorted({int(np.argmin(Ns)), int(np.argmax(Ns))} | set(range(0, 2000, 200)))
     worst = _sampled_energy_check(ctx, descs, prec, 2, picks, 2, w.seed, 0, inputs.batch_couplings)
     print(f"max rel energy error over sampled batch columns: {worst:.3e}")
-
-
-def _halves_run(prec, descs, steps, timed, kind="gauss", schedules=None):
-    cfg = native.make_batch_config(descs, precision=prec, trace_steps=steps, seed=SEED, chain_base=BASE)
-    ctx = native.Context(cfg)
-    for i, d in enumerate(descs):
-        J, scale = _couplings(kind, i, d[0])
-        ctx.init_couplings(J, scale, instance=i)
-    ctx.init_chains()
-    if timed:
-        ctx.timing_enable(True, every=1)
-    split = 37
-    for t0, n in ((0, split), (split, steps - split)):
-        if schedules is not None:
-            ctx.step_n_schedules(t0, n, schedules)
-        else:
-            ctx.step_n(t0, n, 0.5, 2.0, steps)
-    rec = ctx.read_records(0, steps)
-    e, bits, summ = ctx.measure()
-    blob = ctx.checkpoint_save()
-    ctx.close()
-    return rec, e, bits, summ, blob
-
-
-HALF_DESCS = DESCS + [(96, 8, 2, 1, 4), (160, 12, 3, 1, 6), (257, 33, 2, 1, 9)] * 3
-
-
-@pytest.mark.parametrize("prec", ["fp64", "split_bf16"])
-def test_halves_on_two_streams_equal_one_stream(prec):
-    """Without the means trace or the periodic recompute, a batch's run of steps gives
-    each half of its instances a stream of its own; with the scoring launches timed it
-    runs on one stream.  Records, energies, states, counters and the checkpoint are
-    bit-identical."""
-    steps = 80
-    announce(f"batch halves vs one stream {prec}")
-    a = _halves_run(prec, HALF_DESCS, steps, timed=False)
-    b = _halves_run(prec, HALF_DESCS, steps, timed=True)
-    assert np.array_equal(a[0], b[0])
-    assert np.array_equal(a[1], b[1])
-    assert np.array_equal(a[2], b[2])
-    for k in ("steps_done", "moves", "near_ties", "min_margin"):
-        assert a[3][k] == b[3][k], k
-    assert a[4] == b[4]
-    assert a[3]["moves"] > 0
-
-
-def test_halves_with_schedules_and_pm1_oracle():
-    """Per-instance schedules on the two streams equal the one-stream run bit for bit,
-    and +-1 instances follow the oracle's trajectories exactly."""
-    steps = 60
-    announce("batch halves, schedules, pm1 oracle")
-    descs = HALF_DESCS[:8]
-    sched = [(0.3 + 0.1 * i, 1.5 + 0.05 * i, steps) for i in range(len(descs))]
-    a = _halves_run("split_bf16", descs, steps, timed=False, kind="pm1", schedules=sched)
-    b = _halves_run("split_bf16", descs, steps, timed=True, kind="pm1", schedules=sched)
-    assert np.array_equal(a[0], b[0])
-    assert np.array_equal(a[2], b[2])
-    for i, (d, g0) in enumerate(zip(descs, _first_chains(descs))):
-        N, M, chains, kmin, kmax = d
-        J, scale = _couplings("pm1", i, N)
-        b0, b1, tot = sched[i]
-        betas = inputs.beta_schedule(b0, b1, tot, 0, steps)
-        compare_trajectory(a[0][:, int(g0):int(g0) + chains], J, scale, N, M, chains, kmin, kmax, SEED, betas,
-                           "mcmcmc", 0.0, exact=True, chain_base=BASE + int(g0))

@@ -168,3 +168,51 @@ def test_star_headline_flip_sizes_gauss_guided():
     assert (rec["flags"] & 2).any()
     compare_trajectory(rec, J, scale, N, M, chains, 1, 128, 3, np.ones(steps), "mcmcmc", 1e-9,
                        eps_e=eps_energy("fp64", N), max_forced=2, ecur_rtol=1e-9)
+
+
+def test_star_batch_beyond_64k_lds_pm1_bit_exact():
+    """A heterogeneous batch on the star field-update kernel whose per-chain state needs
+    more than 64 KiB of LDS (N = 2048, M = 256, flip sets up to 128 sites: 106 KiB): +-1
+    trajectories equal the FP64 matrix-core batch bit for bit, and the small instances'
+    the oracle's."""
+    descs = [(2048, 256, 1, 1, 128), (64, 8, 2, 1, 4), (200, 33, 2, 1, 12), (96, 5, 3, 4, 6)]
+    steps = 30
+    announce("delta star batch, 106 KiB of LDS")
+    Js = [inputs.couplings_pm1(d[0], 1700 + i) for i, d in enumerate(descs)]
+    recs = {}
+    for scorer in ("delta", "gemm"):
+        cfg = native.make_batch_config(descs, precision="fp64", trace_steps=steps, seed=8, chain_base=3,
+                                       scorer=scorer)
+        ctx = native.Context(cfg)
+        for i, (J, scale) in enumerate(Js):
+            ctx.init_couplings(J, scale, instance=i)
+        ctx.init_chains()
+        ctx.step_n(0, steps, 0.7, 0.7, 1)
+        recs[scorer] = (ctx.read_records(0, steps), ctx.measure()[1])
+        ctx.close()
+    for f in ("r", "vstar", "e_cur", "margin", "flags"):
+        assert np.array_equal(recs["delta"][0][f], recs["gemm"][0][f]), f
+    assert np.array_equal(recs["delta"][1], recs["gemm"][1])
+    g0 = descs[0][2]
+    for d, (J, scale) in zip(descs[1:], Js[1:]):
+        N, M, chains, kmin, kmax = d
+        compare_trajectory(recs["delta"][0][:, g0:g0 + chains], J, scale, N, M, chains, kmin, kmax, 8,
+                           np.full(steps, 0.7), "mcmcmc", 0.0, exact=True, chain_base=3 + g0)
+        g0 += chains
+
+
+def test_star_n8192_gauss_guided():
+    """N = 8192 on the star field-update kernel (133 KiB of LDS per chain): 6 steps of
+    2 chains match the oracle, guided at flagged near ties, energies within 1e-9."""
+    N, M, chains, steps = 8192, 4, 2, 6
+    announce("delta star N=8192")
+    J, scale = inputs.couplings_gauss(N, 0x5EED0006)
+    cfg = native.make_config(N, M, chains, 1, 3, precision="fp64", trace_steps=steps, seed=12, scorer="delta")
+    ctx = native.Context(cfg)
+    ctx.init_couplings(J, scale)
+    ctx.init_chains()
+    ctx.step_n(0, steps, 0.3, 0.3, 1)
+    rec = ctx.read_records(0, steps)
+    assert (rec["flags"] & 2).any()
+    compare_trajectory(rec, J, scale, N, M, chains, 1, 3, 12, np.full(steps, 0.3), "mcmcmc", 1e-9,
+                       eps_e=eps_energy("fp64", N), max_forced=2, ecur_rtol=1e-9)
