@@ -123,6 +123,23 @@ def _time_path(w, precision, steps, warmup, J, scale, every=1, energy_update="ex
             "moves": summ["moves"], "near_ties": summ["near_ties"]}
 
 
+def _steady_state(w, J, scale, after, steps):
+    """Steps per second of the headline path once the chains have settled: `steps`
+    steps timed after `after` untimed ones (no events inside the timed steps)."""
+    import torch
+    ctx = _context(w, "split_bf16", "mcmcmc", w.M, w.kmin, w.kmax, J, scale)
+    ctx.step_n(0, after, w.beta0, w.beta0, 1)
+    ms = _timed_steps(ctx, after, steps, w.beta0, w.beta0, 1)
+    summ = ctx.measure()[2]
+    ctx.close()
+    torch.cuda.synchronize()
+    return {"after_steps": after, "steps": steps, "ms_per_step": ms / steps,
+            "candidates_per_s": w.chains * w.M * steps / (ms / 1e3),
+            "moves_per_chain_step": summ["moves"] / (summ["steps_done"] * w.chains),
+            "note": "the same path and workload as the headline, timed once the chains have settled (fewer "
+                    "moves, so fewer coupling rows for the exact energy update); not the headline value"}
+
+
 def _kernel_pass(w, precision, launches, J, scale, warmup=8):
     """The scoring kernel's average duration over `launches` consecutive steps of the
     same workload, every launch bracketed by HIP events on its stream (a pass of its
@@ -708,6 +725,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="sk_n1024_m128_split")
     ap.add_argument("--fp64-steps", type=int, default=40)
+    ap.add_argument("--steady-steps", type=int, default=200,
+                    help="headline steps timed after 1500 untimed ones (0 skips it)")
     ap.add_argument("--kernel-launches", type=int, default=200,
                     help="scoring launches timed one by one for the roofline figure (a pass of their own)")
     ap.add_argument("--thermalize-steps", type=int, default=20000)
@@ -775,6 +794,10 @@ def main():
              f"with the split kernel's traffic mix {ceiling['mix_tflops']['split_kernel']:.0f}")
     fp64 = _time_path(w, "fp64", args.fp64_steps, min(args.warmup, 2), J, scale)
     _log(f"headline fp64: {fp64['total_ms'] / args.fp64_steps:.4f} ms/step")
+    steady = None
+    if args.steady_steps > 0:
+        steady = _steady_state(w, J, scale, 1500, args.steady_steps)
+        _log(f"headline at steady state: {steady['ms_per_step']:.4f} ms/step")
 
     cand = w.chains * w.M
     ms_step = split["total_ms"] / args.steps
@@ -826,6 +849,7 @@ def main():
                       "achieved_tflops": achieved64, "peak_tflops": PEAK_FP64_TFLOPS,
                       "frac": achieved64 / PEAK_FP64_TFLOPS},
         "split_vs_fp64": fp64_ms_step / ms_step,
+        "steady_state": steady,
         "energy_update": {
             "headline": "exact: the carried energy advances by the FP64 difference of each move, from the |D*| "
                         "coupling rows of the sites the move flips",
