@@ -158,6 +158,10 @@ typedef enum {
  *           of sites where the new state differs from the old one:
  *           dU = -2 sum_{i in D*} s_i sum_{j not in D*} J_ij s_j (old spins); exact
  *           integers for +-1 couplings.  Costs |D*| N coupling reads per move.
+ *           Inside a run of steps each move's difference is added by the next
+ *           step's selection; every call that selects (mc3_select, mc3_select_betas,
+ *           the mc3_step_n family) returns with the carried energies and the records
+ *           complete.
  *   SCORED: U = the chosen candidate's pair sum as scored (split BF16 on the split
  *           path), no extra reads. */
 typedef enum {
