@@ -758,7 +758,7 @@ def main():
                          "then --steps split steps; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(independent chains would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -57,7 +57,7 @@ typedef enum {
     MC3_E_ARG = -1,         /* invalid argument or configuration */
     MC3_E_DEVICE = -3,      /* a HIP call or kernel failed */
     MC3_E_STATE = -4,       /* call out of order, or context poisoned */
-    MC3_E_UNSUPPORTED = -5, /* valid request this build does not implement */
+    MC3_E_UNSUPPORTED = -5, /* valid request the library does not implement */
     MC3_E_NUMERIC = -6,     /* non-finite or inconsistent couplings */
     MC3_E_WORKSPACE = -7    /* workspace missing, too small or misaligned */
 } mc3_status;
