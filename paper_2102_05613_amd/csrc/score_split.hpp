@@ -69,8 +69,14 @@ __global__ void k_pack_split(uint4* __restrict__ Apack, const double* __restrict
 // place.
 __device__ __forceinline__ bf16x8 spins_to_bf16(uint32_t word, int q0) {
   union { uint32_t u[4]; bf16x8 v; } r;
+  // the two constants are held in registers (the empty asm statements hide their
+  // values from the compiler), so that each register takes a shift and one and-or
+  // (that form takes no literal operands) instead of a shift, an and and an or
+  uint32_t m = 0x80008000u, one = 0x3F803F80u;
+  asm("" : "+s"(m));
+  asm("" : "+v"(one));
 #pragma unroll
-  for (int p = 0; p < 4; ++p) r.u[p] = ((word << (15 - q0 - p)) & 0x80008000u) | 0x3F803F80u;
+  for (int p = 0; p < 4; ++p) r.u[p] = ((word << (15 - q0 - p)) & m) | one;
   return r.v;
 }
 
