@@ -818,19 +818,17 @@ struct ClockArg {
   int64_t total = 0;
 };
 
+mc3_status launch_moves(mc3_ctx* c, int g0, int n);
+
 // Selection of global chains [g0, g0 + n) at `step`; with next_base, also the base
 // words of step+1 (whose flip sets and roots must already be proposed).  Ring slots are
 // those of `step` itself; with a clock the kernel takes step - base.
-mc3_status launch_moves(mc3_ctx* c, uint32_t step, int g0, int n, const ClockArg& ck);
 
 mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base, int g0, int n,
                          const ClockArg& ck = ClockArg{}, const double* sched = nullptr) {
   const Plan& pl = c->pl;
-  int Nmax = 0;
-  for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
   const size_t lds = (size_t)(pl.Mmax + 1) * 16;
   const bool exact = c->cfg.energy_update == MC3_ENERGY_EXACT;
-  (void)Nmax;
   hipLaunchKernelGGL(mc3::k_select, dim3(n), dim3(256), lds, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
                      pl.total_chains, c->at<double>(pl.e_cur), c->at<double>(pl.u_cur), c->roots(step),
                      c->roots(step + 1u),
@@ -843,20 +841,18 @@ mc3_status launch_select(mc3_ctx* c, uint32_t step, double beta, bool next_base,
                      move_row_parts(pl.total_chains));
   MC3_TRY(check_launch(c, "select kernel"));
   if (!exact) return MC3_OK;
-  return launch_moves(c, step, g0, n, ck);
+  return launch_moves(c, g0, n);
 }
 
-// The exact energy update of the chains [g0, g0 + n) that moved at `step`: their
-// difference from the rows of the flipped sites, kMoveCols x RS blocks per chain (a
+// The exact energy update of the chains [g0, g0 + n) that moved at the last
+// selection: their difference from the rows of the flipped sites, kMoveCols x RS blocks per chain (a
 // column slice of J64 each, the rows split RS ways; RS depends on the plan alone, so a
 // chain's sum has the same order in every launch).  The next selection adds it into
 // the carried energy and the step's record, or flush_moves does.
-mc3_status launch_moves(mc3_ctx* c, uint32_t step, int g0, int n, const ClockArg& ck) {
+mc3_status launch_moves(mc3_ctx* c, int g0, int n) {
   const Plan& pl = c->pl;
   int Nmax = 0;
   for (const InstH& h : pl.inst) Nmax = std::max(Nmax, h.desc.N);
-  (void)step;
-  (void)ck;
   const int RS = move_row_parts(pl.total_chains);
   hipLaunchKernelGGL(mc3::k_move_delta, dim3(n * mc3::kMoveCols * RS), dim3(256),
                      (size_t)8 * pl.Wmax + (size_t)2 * Nmax, c->stream, c->ws, c->insts(), c->chain_inst(), g0,
@@ -1367,7 +1363,6 @@ mc3_status mc3_init_chains(mc3_ctx* c, const int8_t* spins) {
   MC3_TRY(usable(c));
   if (!c->all_J()) return fail(c, MC3_E_STATE, "init_chains before init_couplings of every instance");
   const Plan& pl = c->pl;
-  const size_t C = (size_t)pl.total_chains;
   if (spins) {
     size_t off = 0;
     std::vector<uint32_t> bits;
