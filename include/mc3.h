@@ -87,7 +87,7 @@ typedef enum {
  *          longest path between two nodes (in edges) <= 32 and the per-chain state
  *          within 64 KiB of LDS; or (the star, flip sets of any size) the per-chain
  *          state within 160 KiB of LDS: 16 N + 24 (M+1) + 8 W + 4 M W + 8 kmax bytes
- *          for the batch's largest N, M, kmax and W = ceil(N/128) 4
+ *          for the batch's largest N, M, kmax and W = 4 ceil(N/128)
  *          (MC3_E_UNSUPPORTED otherwise); only mc3_step_n moves the chains
  *          (mc3_propose, mc3_score_candidates, mc3_select, mc3_read_candidates and
  *          mc3_step_n_per_instance return MC3_E_UNSUPPORTED).  `precision` is unused.
