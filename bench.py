@@ -756,6 +756,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection run: one plain 512 MiB device copy (calibrates FETCH_SIZE/WRITE_SIZE), "
                          "then --steps split steps; prints nothing else")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="counter-collection run of the batched workload: one plain 512 MiB device copy, "
+                         "then its 2000 instances with Gaussian couplings generated on the device (same law as "
+                         "the benchmark's host-loaded ones) and --steps steps; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -766,6 +770,24 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.profile_batch:
+        from paper_2102_05613_amd import native
+        src = torch.ones(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        descs = inputs.batch_descs(args.batch_instances)
+        bw = inputs.workload("sk_batch_rep_n1024_m128")
+        ctx = native.Context(native.make_batch_config(descs, precision="split_bf16", seed=bw.seed))
+        for i in range(len(descs)):
+            ctx.generate_couplings(native.MC3_J_GAUSS, (inputs.BATCH_SEED << 20) + i, instance=i)
+        ctx.init_chains()
+        ctx.step_n(0, args.steps, inputs.BATCH_BETA, inputs.BATCH_BETA, 1)
+        ctx.sync()
+        ctx.close()
+        print(json.dumps({"profile_run": True, "workload": "sk_batch_2000_instances", "steps": args.steps}))
+        return
     w = inputs.workload(args.workload)
     J, scale = w.couplings_matrix()
     if args.profile:
